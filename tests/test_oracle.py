@@ -1,0 +1,318 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+* exact rational brute force (tests/bruteforce.py: 49 face-pair stationary
+  points in fractions) for the pair distance and the intersection flag, on
+  random, integer-grid (many exact degeneracies), near-coplanar (exact
+  fallback), separated, degenerate and far-from-origin triangles;
+* exact rational signs of orient3d / orient2d;
+* hand-derived closed forms (tests/golden/closed_forms.json);
+* invariants: symmetry, sign flips and power-of-two scaling (bit-exact),
+  triangle shuffles and split-min (bit-exact), rotations (1e-12);
+* the exact pruned mode equals the all-pairs mode bit for bit;
+* construction properties of the synthetic configurations.
+
+Error model of an FP64 pair distance (Sec. 3.2.2 minimisation evaluated in
+binary64 from differences of input coordinates): |d_fp64 - d| <= 1e-12 d +
+16 u S, u = 2^-53, S = the largest coordinate difference within the pair.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import oracle
+from paper_1808_09571_amd import synth
+
+U = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+
+
+def _extent(A, B):
+    P = np.concatenate([np.asarray(A).reshape(3, 3), np.asarray(B).reshape(3, 3)])
+    return float(np.max(P.max(0) - P.min(0)))
+
+
+def _check_pair(A, B, olib):
+    e2 = bf.tri_tri_d2(A, B)
+    hit = oracle.tri_tri_intersect(A, B, lib=olib)
+    assert hit == (e2 == 0), (A.tolist(), B.tolist())
+    d = math.sqrt(oracle.pair_d2(A, B, lib=olib))
+    de = math.sqrt(e2)
+    tol = 1e-12 * de + 16 * U * _extent(A, B)
+    assert abs(d - de) <= tol, (A.tolist(), B.tolist(), d, de)
+    if hit:
+        assert d == 0.0
+    return hit
+
+
+def _onplane(g, n, scale=1.0):
+    xy = g.uniform(-scale, scale, (n, 2))
+    return np.c_[xy, 0.1 * xy[:, 0] + 0.3 * xy[:, 1]]
+
+
+DISTS = ["uniform", "intgrid", "nearplane", "separated", "degenerate", "far", "tiny"]
+
+
+def _sample(dist, g):
+    if dist == "uniform":
+        return g.uniform(0, 1, (3, 3)), g.uniform(0, 1, (3, 3))
+    if dist == "intgrid":
+        return g.integers(0, 3, (3, 3)).astype(float), g.integers(0, 3, (3, 3)).astype(float)
+    if dist == "nearplane":
+        return _onplane(g, 3), _onplane(g, 3)
+    if dist == "separated":
+        A = g.uniform(0, 1, (3, 3))
+        B = g.uniform(0, 1, (3, 3)) + g.normal(size=3) * g.uniform(0.5, 3)
+        return A, B
+    if dist == "degenerate":
+        A = g.uniform(0, 1, (3, 3))
+        B = g.uniform(0, 1, (3, 3))
+        k = g.integers(0, 3)
+        if k == 0:      # repeated vertex
+            B[2] = B[0]
+        elif k == 1:    # collinear vertices
+            B[2] = B[0] + g.uniform(-1, 2) * (B[1] - B[0])
+        else:           # a point
+            B[1] = B[0]
+            B[2] = B[0]
+        return (A, B) if g.integers(0, 2) else (B, A)
+    if dist == "far":
+        c = g.uniform(500, 1000, 3)
+        return c + g.uniform(0, 1, (3, 3)), c + g.uniform(0, 1, (3, 3)) + [0, 0, 0.5]
+    if dist == "tiny":
+        return g.uniform(0, 1e-3, (3, 3)), g.uniform(0, 1e-3, (3, 3))
+    raise KeyError(dist)
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_pair_vs_rational_bruteforce(dist, olib):
+    g = np.random.default_rng(1000 + DISTS.index(dist))
+    hits = 0
+    n = 120
+    for _ in range(n):
+        A, B = _sample(dist, g)
+        hits += _check_pair(A, B, olib)
+    if dist in ("uniform", "intgrid", "nearplane"):
+        assert 0 < hits < n  # both outcomes exercised
+
+
+def test_exact_fallback_exercised(olib):
+    g = np.random.default_rng(7)
+    c0 = oracle.exact_calls(lib=olib)
+    for _ in range(50):
+        _check_pair(_onplane(g, 3), _onplane(g, 3), olib)
+    assert oracle.exact_calls(lib=olib) > c0
+
+
+@pytest.mark.parametrize("kind", ["random", "nearplane", "integer"])
+def test_orient3d_exact_sign(kind, olib):
+    g = np.random.default_rng({"random": 1, "nearplane": 2, "integer": 3}[kind])
+    zeros = 0
+    for _ in range(1500):
+        if kind == "random":
+            P = g.normal(size=(4, 3)) * 10.0 ** g.uniform(-3, 3)
+        elif kind == "nearplane":
+            P = _onplane(g, 4, scale=10.0 ** g.uniform(-2, 3))
+        else:
+            P = g.integers(-2, 3, (4, 3)).astype(float)
+        s = oracle.orient3d(*P, lib=olib)
+        assert s == bf.orient3d_sign(*P) == oracle.orient3d_exact(*P, lib=olib)
+        zeros += s == 0
+    if kind == "integer":
+        assert zeros > 0
+
+
+def test_orient2d_exact_sign(olib):
+    g = np.random.default_rng(5)
+    for _ in range(1500):
+        t = g.uniform(-1, 1, 3)
+        a = g.uniform(-1, 1, 2)
+        d = g.uniform(-1, 1, 2)
+        P = [a + s * d for s in t]   # collinear in reals, rounded in binary64
+        if g.integers(0, 3) == 0:
+            P = g.integers(-2, 3, (3, 2)).astype(float)
+        assert oracle.orient2d(*P, lib=olib) == bf.orient2d_sign(*P)
+
+
+def _golden_mesh(spec):
+    if "cube" in spec:
+        return synth.cube(spec["cube"], spec.get("size", 1.0))
+    return np.asarray(spec["xyz"], dtype=float), np.asarray(spec["tri"], dtype=np.int32)
+
+
+def _golden_cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_closed_forms(case, olib):
+    A, B = _golden_mesh(case["A"]), _golden_mesh(case["B"])
+    want = case["distance"] if "distance" in case else eval(case["distance_expr"], {"sqrt": math.sqrt})
+    for mode in ("all", "pruned"):
+        d, h, _ = oracle.mesh(A, B, mode=mode, lib=olib)
+        assert h == case["intersects"]
+        assert abs(d - want) <= 1e-14 * max(1.0, want)
+        _, h2, _ = oracle.mesh(A, B, mode=mode, want="intersects", lib=olib)
+        assert h2 == case["intersects"]
+    # pair-level: the same answer from the rational brute force when single triangles
+    if len(A[1]) == 1 and len(B[1]) == 1:
+        e2 = bf.tri_tri_d2(A[0][A[1][0]], B[0][B[1][0]])
+        assert abs(math.sqrt(e2) - want) <= 1e-15 * max(1.0, want)
+
+
+def test_segment_and_point_primitives(olib):
+    h = 0.3125
+    # perpendicular skew segments crossing above each other: distance h
+    assert oracle.seg_seg_d2([0, 0, 0], [1, 0, 0], [0.5, -1, h], [0.5, 1, h], lib=olib) == h * h
+    # parallel overlapping segments at offset h
+    assert oracle.seg_seg_d2([0, 0, 0], [2, 0, 0], [1, h, 0], [3, h, 0], lib=olib) == h * h
+    # collinear disjoint segments: gap between the facing end points
+    assert oracle.seg_seg_d2([0, 0, 0], [1, 0, 0], [1.5, 0, 0], [3, 0, 0], lib=olib) == 0.25
+    # the minimum sits on the side t = 1 only: q1 = (1,1,0) projects inside [p0,p1]
+    assert oracle.seg_seg_d2([0, 0, 0], [2, 0, 0], [1, 5, 1], [1, 1, 0], lib=olib) == 1.0
+    assert oracle.seg_seg_d2([1, 5, 1], [1, 1, 0], [0, 0, 0], [2, 0, 0], lib=olib) == 1.0
+    # degenerate segment (a point) to a segment
+    assert oracle.seg_seg_d2([0, 1, 0], [0, 1, 0], [-1, 0, 0], [1, 0, 0], lib=olib) == 1.0
+    # point straight above the interior of a triangle
+    assert oracle.vertex_face_d2([0.25, 0.25, h], [0, 0, 0], [1, 0, 0], [0, 1, 0], lib=olib) == h * h
+    # foot outside the triangle: left to the edge terms
+    assert oracle.vertex_face_d2([2, 2, h], [0, 0, 0], [1, 0, 0], [0, 1, 0], lib=olib) == math.inf
+    # degenerate face
+    assert oracle.vertex_face_d2([0, 0, 1], [0, 0, 0], [1, 0, 0], [2, 0, 0], lib=olib) == math.inf
+
+
+def _mesh(A, B, olib, **kw):
+    return oracle.mesh(A, B, lib=olib, **kw)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_icospheres_invariants(seed, olib):
+    A, B = synth.config_icospheres(seed)
+    d, h, n = _mesh(A, B, olib)
+    assert n == 1280 * 1280
+    # pruned mode: identical bits
+    dp, hp, npr = _mesh(A, B, olib, mode="pruned")
+    assert (dp, hp) == (d, h) and npr <= n
+    # intersects-only agrees with the by-product flag
+    assert _mesh(A, B, olib, want="intersects")[1] == h
+    assert _mesh(A, B, olib, mode="pruned", want="intersects")[1] == h
+    # distance 0 iff intersects (the gaps here are far above FP64 resolution)
+    assert (d == 0.0) == h
+    # geometry bounds: vertices on the unit spheres, faces at least r_in from the centre
+    c = np.linalg.norm(B[0].mean(0) - A[0].mean(0))
+    tri = A[0][A[1]]
+    nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    r_in = np.min(np.abs(np.einsum("ij,ij->i", nrm, tri[:, 0])) / np.linalg.norm(nrm, axis=1))
+    assert d >= c - 2.0 - 1e-12
+    if c > 2.0 + 1e-9:
+        assert d <= c - 2.0 * r_in + 1e-12
+        assert not h
+    if c < 2.0 * r_in:
+        assert h
+    # symmetry
+    ds, hs, _ = _mesh(B, A, olib)
+    assert hs == h and abs(ds - d) <= 1e-12 * max(d, 1e-300)
+    # sign flip of an axis, power-of-two scaling: bit-exact
+    flip = np.array([1.0, -1.0, 1.0])
+    assert _mesh((A[0] * flip, A[1]), (B[0] * flip, B[1]), olib)[:2] == (d, h)
+    assert _mesh((A[0] * 8.0, A[1]), (B[0] * 8.0, B[1]), olib)[:2] == (d * 8.0, h)
+    assert _mesh((A[0] * 0.125, A[1]), (B[0] * 0.125, B[1]), olib)[:2] == (d * 0.125, h)
+    # axis permutation and translation: within rounding
+    perm = [2, 0, 1]
+    dq, hq, _ = _mesh((A[0][:, perm], A[1]), (B[0][:, perm], B[1]), olib)
+    assert hq == h and abs(dq - d) <= 1e-12 * max(d, 1e-300)
+    t = np.array([3.0, -5.0, 7.0])
+    dq, hq, _ = _mesh((A[0] + t, A[1]), (B[0] + t, B[1]), olib)
+    assert hq == h and abs(dq - d) <= 1e-12 * max(d, 1e-300) + 64 * U * 10
+    # triangle order shuffle: bit-exact; vertex rotation inside triangles: rounding
+    g = np.random.default_rng(seed)
+    assert _mesh((A[0], A[1][g.permutation(len(A[1]))]), B, olib)[:2] == (d, h)
+    dq, hq, _ = _mesh((A[0], A[1][:, [1, 2, 0]]), B, olib)
+    assert hq == h and abs(dq - d) <= 1e-12 * max(d, 1e-300)
+    # split-min: bit-exact
+    k = len(A[1]) // 3
+    d1 = _mesh((A[0], A[1][:k]), B, olib)[0]
+    d2 = _mesh((A[0], A[1][k:]), B, olib)[0]
+    assert min(d1, d2) == d
+
+
+def test_empty_meshes(olib):
+    A = synth.cube()
+    E = (np.zeros((0, 3)), np.zeros((0, 3), dtype=np.int32))
+    for mode in ("all", "pruned"):
+        d, h, n = _mesh(A, E, olib, mode=mode)
+        assert d == math.inf and not h and n == 0
+        d, h, n = _mesh(E, A, olib, mode=mode)
+        assert d == math.inf and not h
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_soups_pruned_equals_all_pairs(seed, olib):
+    A = synth.random_triangle_soup(700, seed, scale=3.0)
+    B = synth.random_triangle_soup(600, seed + 100, scale=3.0, center=(2.5, 0, 0))
+    for want in ("distance", "intersects"):
+        r0 = _mesh(A, B, olib, want=want)
+        r1 = _mesh(A, B, olib, mode="pruned", want=want)
+        assert r0[:2] == r1[:2]
+    # x-sorted soups (chunks become slabs): pruned mode must visit fewer pairs
+    def xsort(m):
+        return m[0], m[1][np.argsort(m[0][m[1]].mean(axis=1)[:, 0], kind="stable")]
+    A = xsort(A)
+    B2 = xsort(synth.random_triangle_soup(600, seed + 200, scale=3.0, center=(7.0, 0, 0)))
+    r0 = _mesh(A, B2, olib)
+    r1 = _mesh(A, B2, olib, mode="pruned")
+    assert r0[:2] == r1[:2] and r1[2] < r0[2]
+
+
+def test_tin_pair_construction(olib):
+    A, B = synth.config_tin_pair(n=24, extent=48.0, amplitude=5.0, gap=0.01)
+    d, h, _ = _mesh(A, B, olib)
+    assert not h and 0.0 < d <= 0.01 + 1e-12
+    assert _mesh(A, B, olib, mode="pruned")[:2] == (d, h)
+    # lowering B below the clearance makes the surfaces cross
+    B2 = (B[0] - np.array([0, 0, 0.02]), B[1])
+    d2, h2, _ = _mesh(A, B2, olib)
+    assert h2 and d2 == 0.0
+
+
+def test_tube_blob_rows(olib):
+    A, B = synth.config_tube_blob_batch(rows=6, seed=11, tube_tri=(200, 400),
+                                        blob_tri=(1000, 2000), aim_range=1.2)
+    pa, pb = synth.pack(A), synth.pack(B)
+    d_all, h_all = oracle.batch(pa, pb, lib=olib)
+    d_pr, h_pr = oracle.batch(pa, pb, mode="pruned", lib=olib)
+    assert np.array_equal(d_all, d_pr) and np.array_equal(h_all, h_pr)
+    assert np.all((d_all == 0) == h_all)
+
+
+def test_pruning_adversarial(olib):
+    """Chunks of 256 consecutive triangles: the first chunk's box encloses B
+    (bound 0) but its triangles are 10 away; the second chunk's box is 6 away
+    while its nearest triangle is 7 away.  A pruning rule that drops the second
+    chunk after seeing 10 would return the wrong minimum."""
+    B = (np.array([[-0.1, -0.1, 0.0], [0.1, -0.1, 0.0], [0.0, 0.1, 0.0]]),
+         np.array([[0, 1, 2]], dtype=np.int32))
+    g = np.random.default_rng(3)
+    tris = []
+    for _ in range(256):                       # shell of radius ~10 around B
+        c = g.normal(size=3)
+        c = 10.5 * c / np.linalg.norm(c)
+        tris.append(c + g.uniform(-0.05, 0.05, (3, 3)))
+    for k in range(256):                       # spread cluster, box starts at x = 6
+        if k == 0:
+            tris.append(np.array([[7.0, -0.1, 0.0], [7.0, 0.1, 0.0], [7.0, 0.0, 0.1]]))
+        else:
+            y = 5.0 + 0.01 * k
+            tris.append(np.array([[6.0, y, 0.0], [8.0, y, 0.0], [6.0, y, 5.0]]) *
+                        np.array([1.0, 1.0 if k % 2 else -1.0, 1.0]))
+    xyz = np.concatenate(tris)
+    A = (xyz, np.arange(xyz.shape[0], dtype=np.int32).reshape(-1, 3))
+    d, h, n = _mesh(A, B, olib)
+    # one thread: the chunk pairs are visited strictly in bound order
+    dp, hp, npr = _mesh(A, B, olib, mode="pruned", threads=1)
+    assert (dp, hp) == (d, h) and not h
+    assert abs(d - 6.9) < 0.11   # the k == 0 triangle of the cluster
