@@ -1,0 +1,155 @@
+/*
+ * sd3 -- exact 3D distance and 3D intersects between triangulated surfaces
+ * (TINs, polyhedral surfaces) on AMD Instinct MI355X (gfx950).
+ *
+ * The two operators are those of "Full Speed Ahead: 3D Spatial Database
+ * Acceleration with GPUs" (arXiv 1808.09571):
+ *   - 3D Distance (Sec. 3.2.2): per-face distances between the two geometries
+ *     followed by the minimum, which is returned to the caller; each per-face
+ *     distance minimises the squared distance Q of Eq. 3 over closed parameter
+ *     ranges.
+ *   - 3D Intersection (Sec. 3.2.3): per-face segment/plane crossing followed by
+ *     the barycentric inside test of Eq. 4, with closed constraints (touching
+ *     counts as intersecting).
+ * Both are generalised from the paper's segment/triangle primitive to
+ * triangle/triangle pairs (edge/edge, vertex/face and edge/face-crossing
+ * tests) so that two meshes can be compared.  A geometry is the union of its
+ * closed triangles (surface semantics: a mesh nested inside a closed mesh
+ * does not intersect it).
+ *
+ * Results: distance is the Euclidean distance in FP64 (0 when the geometries
+ * intersect, +inf when either is empty); intersects is exact (decided with
+ * exact orientation signs).  The bulk of the work runs in FP32 with forward
+ * error bounds; every pair that the bounds cannot settle is recomputed in
+ * FP64, so the returned distance is the FP64 minimum.
+ *
+ * Batches: row g of the first batch is compared with row g of the second (one
+ * geometry pair per table row, Sec. 3.1 "whole column" processing).
+ *
+ * Thread safety: a context may be used by one host thread at a time.  Calls are
+ * synchronous: they return after the results are in `out`.
+ */
+#ifndef SD3_H
+#define SD3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sd3_status {
+    SD3_OK = 0,
+    SD3_E_INVALID_ARG = 1, /* null pointer, count < 0, mismatched batch sizes,
+                              offsets not starting at 0 or decreasing, unknown
+                              option value, geometry memory kinds differ */
+    SD3_E_INDEX_RANGE = 2, /* a triangle index outside its row's vertices */
+    SD3_E_NONFINITE = 3,   /* a NaN or infinite coordinate */
+    SD3_E_RANGE = 4,       /* a nonzero |coordinate| outside [2^-256, 2^256]
+                              (needed for exact orientation signs) */
+    SD3_E_NOMEM = 5,       /* device allocation failed */
+    SD3_E_DEVICE = 6,      /* HIP runtime error; see sd3_last_error() */
+    SD3_E_NO_DEVICE = 7,   /* no usable gfx950 device */
+    SD3_E_CAPACITY = 8     /* an internal work list overflowed its bound */
+} sd3_status;
+
+/* Where xyz / tri live.  Offsets are always host memory. */
+#define SD3_MEM_HOST 0
+#define SD3_MEM_DEVICE 1
+
+/*
+ * A batch of `count` triangle meshes in CSR form (one mesh per table row).
+ *   xyz   : [v_off[count] * 3] doubles, x y z of every vertex, rows back to back
+ *   tri   : [t_off[count] * 3] int32, vertex indices of every triangle, local to
+ *           its row (0 <= index < v_off[g+1] - v_off[g])
+ *   v_off : [count + 1] int64 host array, v_off[0] = 0, non-decreasing
+ *   t_off : [count + 1] int64 host array, t_off[0] = 0, non-decreasing
+ *   mem   : SD3_MEM_HOST or SD3_MEM_DEVICE for xyz and tri
+ * The caller owns every array; the library keeps no pointer after a call.
+ */
+typedef struct sd3_geoms {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off;
+    const int64_t *t_off;
+    int64_t count;
+    int32_t mem;
+} sd3_geoms;
+
+/* Arithmetic of the bulk triangle-pair pass. */
+#define SD3_PREC_FP32_RESCUE 0 /* FP32 with error bounds + FP64 rescue (default) */
+#define SD3_PREC_FP64 1        /* plain FP64 for every tested pair */
+
+/* Order in which candidate tile pairs are visited (results never depend on it). */
+#define SD3_ORDER_BOUND 0 /* increasing bounding-box lower bound (default) */
+#define SD3_ORDER_NONE 1  /* generation order */
+
+typedef struct sd3_opts {
+    int32_t precision; /* SD3_PREC_* */
+    int32_t order;     /* SD3_ORDER_* */
+    int32_t reserved[6];
+} sd3_opts;
+
+/* Work counters of the last call (all tile and triangle counts summed over rows). */
+typedef struct sd3_stats {
+    int64_t tile_pairs_total;     /* sum of tilesA * tilesB */
+    int64_t tile_pairs_candidate; /* kept by the bounding-box filter */
+    int64_t tile_pairs_evaluated; /* candidates still live when dequeued */
+    int64_t tri_pairs_boxed;      /* triangle pairs whose boxes were compared */
+    int64_t tri_pairs_fp32;       /* triangle pairs through the FP32 test */
+    int64_t tri_pairs_fp64;       /* triangle pairs through the FP64 test */
+    int64_t rescued;              /* FP32 pairs sent to the FP64 pass */
+    int64_t exact;                /* pairs settled by exact arithmetic */
+    double ms_total;              /* wall time of the call, host clock */
+    int64_t reserved[7];
+} sd3_stats;
+
+typedef struct sd3_ctx sd3_ctx;
+
+/* Default options: SD3_PREC_FP32_RESCUE, SD3_ORDER_BOUND. */
+void sd3_default_opts(sd3_opts *opts);
+
+/* Create a context on HIP device `device` (must be gfx950).  *out receives the
+ * handle or NULL on error.  Errors: SD3_E_INVALID_ARG (out is NULL),
+ * SD3_E_NO_DEVICE, SD3_E_DEVICE. */
+sd3_status sd3_create(sd3_ctx **out, int device);
+
+/* Release the context and its device memory.  NULL is accepted. */
+sd3_status sd3_destroy(sd3_ctx *ctx);
+
+/*
+ * 3D distance, row by row (Sec. 3.2.2: per-face distances, then the minimum
+ * returned to the user).
+ *   dist : [count] doubles, distance of row g of a to row g of b
+ *   hit  : [count] bytes or NULL; 1 where the rows intersect (exact)
+ * dist/hit are device pointers when a->mem == SD3_MEM_DEVICE, host pointers
+ * otherwise.  opts and stats may be NULL.  stream is a hipStream_t (NULL: the
+ * default stream); the call synchronises it before returning.
+ * On any error the outputs are left untouched.
+ */
+sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
+                        uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream);
+
+/*
+ * 3D intersects, row by row (Sec. 3.2.3: per-face crossing tests of Eq. 4,
+ * combined with OR).  hit : [count] bytes, 1 where the rows share a point.
+ * Memory kinds, stream and error behaviour as for sd3_distance.
+ */
+sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
+                          const sd3_opts *opts, sd3_stats *stats, void *stream);
+
+/* Host-side validation of a batch whose xyz/tri are host memory (the checks
+ * the two operators run before any launch); needs no device. */
+sd3_status sd3_validate(const sd3_geoms *g);
+
+/* Static description of a status code. */
+const char *sd3_status_string(sd3_status s);
+
+/* Message of the last error raised on ctx ("" if none). */
+const char *sd3_last_error(const sd3_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SD3_H */

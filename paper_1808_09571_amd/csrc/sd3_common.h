@@ -1,0 +1,111 @@
+// Shared device/host definitions of the sd3 GPU path (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sd3 {
+
+// Triangles per tile: one tile is one wave's worth of triangles, so a tile
+// reduction is a single wave reduction and a tile pair is K*K = 4096 tests.
+constexpr int K = 64;
+constexpr int WG = 256;  // threads per workgroup in the tile-pair kernels
+
+constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double SQRT3 = 1.7320508075688772;
+
+// Per-tile metadata.  Vertex coordinates are stored twice: exact FP64 copies
+// (t64) and FP32 offsets from the tile origin (t32).
+struct TileMeta {
+    double o[3];    // origin; an FP32-representable point near the box centre
+    double lo[3];   // exact bounding box of the tile's vertices
+    double hi[3];
+    double rep[3];  // one vertex of the tile (exact), for cheap upper bounds
+    float eps;      // Euclidean bound of |t32 vertex - (vertex - o)|
+    float rad;      // max |t32 coordinate| over the tile
+    int32_t row;    // batch row of the tile
+    int32_t n;      // real triangles (slots >= n repeat slot n - 1)
+};
+
+// Rescue list entry: a triangle pair whose FP32 bounds did not settle it.
+struct Rescue {
+    int32_t ta, tb;   // global tile ids (A side, B side)
+    uint32_t slots;   // slot in ta | slot in tb << 16
+    float lb;         // certified lower bound of the pair distance
+};
+
+// Exact list entry: a pair whose FP64 filtered predicates were undecided.
+struct ExactItem {
+    int32_t ta, tb;
+    uint32_t slots;
+    int32_t pad;
+    double d2;        // FP64 squared distance if the pair turns out disjoint
+};
+
+// Row state (one per geometry pair).  Non-negative doubles compare like their
+// bit patterns, so unsigned 64-bit atomicMin is a floating-point min.
+struct RowState {
+    unsigned long long ub;   // upper bound of the row distance (double bits)
+    unsigned long long d2;   // min FP64 squared distance found (double bits)
+    uint32_t hit;            // 1 once an intersecting pair is certified
+    uint32_t pad;
+    double margin_scale;     // 2^-36 * (row extent); margin m(ub) = scale + 2^-36 ub
+};
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long double_to_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+__device__ __forceinline__ void atomic_min_pos(unsigned long long *p, double v) {
+    atomicMin(p, double_to_bits(v));
+}
+
+// Order-preserving map of any double to an unsigned 64-bit key.
+__device__ __forceinline__ unsigned long long ordered_bits(double d) {
+    unsigned long long b = double_to_bits(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_bits(unsigned long long k) {
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return bits_to_double(b);
+}
+
+// Wave-wide (64 lanes) reductions.
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ unsigned long long lanes_below() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Pruning margin m(ub): far above twice the FP64 rounding error of any pair
+// distance in the row (errors scale with the row extent), so a pair skipped
+// because its lower bound exceeds ub + m can never hold the FP64 minimum.
+__device__ __forceinline__ double row_margin(const RowState &r, double ub) {
+    return r.margin_scale + 1.4551915228366852e-11 * ub;  // 2^-36
+}
+
+}  // namespace sd3

@@ -1,0 +1,86 @@
+// Host-side launch wrappers of the sd3 kernels (defined in sd3_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sd3_common.h"
+
+namespace sd3 {
+
+// Per-side prepared data (all device pointers).
+struct SideBufs {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off;     // [G+1]
+    const int64_t *t_off;     // [G+1]
+    const int64_t *tile_off;  // [G+1]
+    int64_t G, nv, nt, NT;
+    unsigned long long *rowbox;  // [G*6] ordered bits: lo xyz (min), hi xyz (max)
+    uint64_t *keys[2];
+    int32_t *vals[2];
+    uint32_t *hist;              // radix histograms
+    float *t32;                  // [NT*9*K]
+    double *t64;                 // [NT*9*K]
+    TileMeta *meta;              // [NT]
+};
+
+// Counters (device, unsigned long long[16]).
+enum Counter : int {
+    C_TP_CAND = 0,
+    C_TP_EVAL = 1,
+    C_TRI_BOXED = 2,
+    C_TRI32 = 3,
+    C_TRI64 = 4,
+    C_RESCUED = 5,
+    C_EXACT = 6,
+    C_QUEUE_OVF = 7,
+    C_RESCUE_OVF = 8,
+    C_EXACT_OVF = 9,
+    C_NCOUNTERS = 16,
+};
+
+// Queue / work lists (device).
+struct Lists {
+    int2 *queue;
+    float *qlb;
+    unsigned int *qcount;   // [1]
+    unsigned int *qhead;    // [1]
+    unsigned int qcap;
+    Rescue *rescue;
+    unsigned int *rcount;
+    unsigned int *rhead;
+    unsigned int rcap;
+    ExactItem *exact;
+    unsigned int *xcount;
+    unsigned int xcap;
+    unsigned long long *counters;  // [C_NCOUNTERS]
+};
+
+// Validation flags.
+enum : uint32_t { V_NONFINITE = 1, V_RANGE = 2, V_INDEX = 4 };
+
+void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                     const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
+                     hipStream_t s);
+void launch_prep(SideBufs &side, int key_bits, hipStream_t s);
+void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
+                      const unsigned long long *boxB, hipStream_t s);
+// Q_SEED: upper bounds from vertex pairs; Q_FILTER_DIST: keep box lower bound
+// <= ub + m; Q_FILTER_HIT: keep overlapping boxes.
+enum : int { Q_SEED = 0, Q_FILTER_DIST = 1, Q_FILTER_HIT = 2 };
+void launch_queue(const SideBufs &A, const SideBufs &B, const int64_t *wi_off, int64_t n_wi,
+                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s);
+void launch_sort_queue(Lists &L, uint64_t *tmp_keys, int32_t *tmp_vals, uint64_t *keys2,
+                       int32_t *vals2, uint32_t *hist, int2 *queue2, float *qlb2,
+                       unsigned int n_max, hipStream_t s);
+void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
+                  int mode, int grid, hipStream_t s);
+void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                   int grid, hipStream_t s);
+void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                  int grid, hipStream_t s);
+void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, hipStream_t s);
+void launch_reset_lists(Lists &L, hipStream_t s);
+void launch_reset_queue(Lists &L, hipStream_t s);
+
+}  // namespace sd3

@@ -1,0 +1,938 @@
+// sd3 kernels for gfx950: validation, spatial sort and tiling, tile-pair
+// bounds and work queue, the triangle-pair passes (FP32 with error bounds,
+// FP64), the FP64 rescue pass, exact arithmetic, and the final reduction.
+#include <type_traits>
+
+#include "sd3_kernels.h"
+#include "sd3_pair64.h"
+#include "sd3_pair32.h"
+#include "sd3_exact.h"
+
+namespace sd3 {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+// Row g with off[g] <= i < off[g+1] (off non-decreasing, off[0] <= i < off[G]).
+__device__ __forceinline__ int64_t find_row(const int64_t *off, int64_t G, int64_t i) {
+    int64_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned long long load_acq(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_acq32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+static inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// a1: validation of device-resident inputs
+// ---------------------------------------------------------------------------
+__global__ void k_validate_xyz(const double *xyz, int64_t n, uint32_t *flags) {
+    uint32_t f = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double x = fabs(xyz[i]);
+        if (!(x <= 1.7976931348623157e308)) f |= V_NONFINITE;
+        else if (x != 0.0 && (x < 0x1p-256 || x > 0x1p256)) f |= V_RANGE;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_validate_tri(const int32_t *tri, int64_t nt, const int64_t *v_off,
+                               const int64_t *t_off, int64_t G, uint32_t *flags) {
+    uint32_t f = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t g = find_row(t_off, G, t);
+        int64_t nvr = v_off[g + 1] - v_off[g];
+        for (int k = 0; k < 3; k++) {
+            int32_t v = tri[3 * t + k];
+            if (v < 0 || v >= nvr) f |= V_INDEX;
+        }
+    }
+    if (f) atomicOr(flags, f);
+}
+
+void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                     const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
+                     hipStream_t s) {
+    if (nv > 0) {
+        unsigned g = grid_for(nv * 3, 256);
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_validate_xyz, dim3(g), dim3(256), 0, s, xyz, nv * 3, flags);
+    }
+    if (nt > 0) {
+        unsigned g = grid_for(nt, 256);
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_validate_tri, dim3(g), dim3(256), 0, s, tri, nt, v_off, t_off, G, flags);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2: row boxes, Morton keys, radix sort, tiles
+// ---------------------------------------------------------------------------
+__global__ void k_rowbox_init(unsigned long long *box, int64_t G) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < G * 6) box[i] = (i % 6) < 3 ? ~0ull : 0ull;
+}
+
+// Row bounding boxes of all vertices (ordered-bit atomics; a wave whose lanes
+// all belong to one row reduces first).
+__global__ void k_rowbox(const double *xyz, int64_t nv, const int64_t *v_off, int64_t G,
+                         unsigned long long *box) {
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nv;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        bool valid = i < nv;
+        int64_t ic = valid ? i : nv - 1;
+        int64_t g = find_row(v_off, G, ic);
+        unsigned long long lo[3], hi[3];
+        for (int k = 0; k < 3; k++) {
+            unsigned long long b = ordered_bits(xyz[3 * ic + k]);
+            lo[k] = valid ? b : ~0ull;
+            hi[k] = valid ? b : 0ull;
+        }
+        int64_t g0 = __shfl(g, 0);
+        bool uniform = __all(g == g0 || !valid);
+        if (uniform) {
+            for (int k = 0; k < 3; k++) {
+                lo[k] = wave_min(lo[k]);
+                hi[k] = wave_max(hi[k]);
+            }
+            if (lane_id() == 0) {
+                for (int k = 0; k < 3; k++) {
+                    atomicMin(&box[g0 * 6 + k], lo[k]);
+                    atomicMax(&box[g0 * 6 + 3 + k], hi[k]);
+                }
+            }
+        } else if (valid) {
+            for (int k = 0; k < 3; k++) {
+                atomicMin(&box[g * 6 + k], lo[k]);
+                atomicMax(&box[g * 6 + 3 + k], hi[k]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// key = row << 30 | 30-bit Morton code of the triangle centroid in the row box
+__global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, const int64_t *v_off,
+                         const int64_t *t_off, int64_t G, const unsigned long long *box,
+                         uint64_t *keys, int32_t *vals) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t g = find_row(t_off, G, t);
+        const double *X = xyz + 3 * v_off[g];
+        uint32_t q[3];
+        double cen[3] = {0.0, 0.0, 0.0};
+        for (int v = 0; v < 3; v++) {
+            const double *p = X + 3 * (int64_t)tri[3 * t + v];
+            cen[0] += p[0];
+            cen[1] += p[1];
+            cen[2] += p[2];
+        }
+        for (int k = 0; k < 3; k++) {
+            double lo = from_ordered_bits(box[g * 6 + k]), hi = from_ordered_bits(box[g * 6 + 3 + k]);
+            double c = cen[k] * (1.0 / 3.0);
+            double f = hi > lo ? (c - lo) / (hi - lo) * 1024.0 : 0.0;
+            int qi = (int)f;
+            q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
+        }
+        uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
+        keys[t] = ((uint64_t)g << 30) | code;
+        vals[t] = (int32_t)t;
+    }
+}
+
+// Stable LSD radix sort, 8-bit digits.  Blocks of 256 threads own 4096
+// consecutive items; per pass: digit histogram per block, one exclusive scan
+// over (digit, block), and a stable scatter that ranks equal digits inside a
+// wave with ballots.
+constexpr int RS_ITEMS = 4096;
+
+__global__ void k_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_ITEMS;
+    for (int r = 0; r < RS_ITEMS / 256; r++) {
+        int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of `total` entries by one workgroup of 1024 threads
+__global__ void k_scan(uint32_t *a, int64_t total) {
+    __shared__ uint32_t part[1024];
+    int64_t per = (total + 1023) / 1024;
+    int64_t b0 = threadIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
+    uint32_t s = 0;
+    for (int64_t i = b0; i < b1; i++) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = b0; i < b1; i++) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout,
+                          int64_t n, int shift, const uint32_t *hist, int nblocks) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[4][256];
+    int tid = threadIdx.x, w = tid >> 6;
+    base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+    int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
+    for (int r = 0; r < RS_ITEMS / 256; r++) {
+        for (int k = 0; k < 4; k++) wcnt[k][tid] = 0;
+        __syncthreads();
+        int64_t i = b0 + r * 256 + tid;
+        bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0;
+        int32_t val = valid ? vin[i] : 0;
+        uint32_t d = (uint32_t)((key >> shift) & 255);
+        unsigned long long peers = __ballot(valid);
+        for (int bit = 0; bit < 8; bit++) {
+            unsigned long long m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int k = 0; k < w; k++) pos += wcnt[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        __syncthreads();
+    }
+}
+
+// Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
+static int radix_sort(uint64_t **keys, int32_t **vals, uint32_t *hist, int64_t n, int bits,
+                      hipStream_t s) {
+    int cur = 0;
+    if (n <= 1) return cur;
+    int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)nb * 256);
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+// One wave per tile: gather the tile's triangles in sorted order, write the
+// FP64 and FP32 SoA copies and the tile metadata.
+__global__ void k_tiles(const double *xyz, const int32_t *tri, const int64_t *v_off,
+                        const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t NT,
+                        const int32_t *sorted, float *t32, double *t64, TileMeta *meta) {
+    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= NT) return;
+    int j = lane_id();
+    int64_t g = find_row(tile_off, G, t);
+    int64_t i = t - tile_off[g];
+    int64_t ntr = t_off[g + 1] - t_off[g];
+    int n = (int)min((int64_t)K, ntr - i * K);
+    int64_t pos = t_off[g] + i * K + (j < n ? j : n - 1);
+    int64_t tid = sorted[pos];
+    const double *X = xyz + 3 * v_off[g];
+    double v[9];
+    for (int k = 0; k < 3; k++) {
+        const double *p = X + 3 * (int64_t)tri[3 * tid + k];
+        v[3 * k] = p[0];
+        v[3 * k + 1] = p[1];
+        v[3 * k + 2] = p[2];
+    }
+    for (int c = 0; c < 9; c++) t64[(t * 9 + c) * K + j] = v[c];
+    double lo[3], hi[3], o[3];
+    for (int k = 0; k < 3; k++) {
+        lo[k] = wave_min(fmin(v[k], fmin(v[3 + k], v[6 + k])));
+        hi[k] = wave_max(fmax(v[k], fmax(v[3 + k], v[6 + k])));
+        o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
+    }
+    double err = 0.0, rad = 0.0;
+    for (int vtx = 0; vtx < 3; vtx++) {
+        double e2 = 0.0;
+        for (int k = 0; k < 3; k++) {
+            double dlt = v[3 * vtx + k] - o[k];
+            float f = (float)dlt;
+            t32[(t * 9 + 3 * vtx + k) * K + j] = f;
+            double e = fabs((double)f - dlt) + U64 * fabs(dlt);
+            e2 += e * e;
+            rad = fmax(rad, fabs((double)f));
+        }
+        err = fmax(err, sqrt(e2));
+    }
+    err = wave_max(err);
+    rad = wave_max(rad);
+    if (j == 0) {
+        TileMeta m;
+        for (int k = 0; k < 3; k++) {
+            m.o[k] = o[k];
+            m.lo[k] = lo[k];
+            m.hi[k] = hi[k];
+            m.rep[k] = v[k];
+        }
+        m.eps = (float)(err * (1.0 + 0x1p-20) + 0x1p-1000);
+        m.rad = (float)rad;
+        m.row = (int32_t)g;
+        m.n = n;
+        meta[t] = m;
+    }
+}
+
+void launch_prep(SideBufs &S, int key_bits, hipStream_t s) {
+    if (S.G == 0) return;
+    hipLaunchKernelGGL(k_rowbox_init, dim3(grid_for(S.G * 6, 256)), dim3(256), 0, s, S.rowbox, S.G);
+    if (S.nv > 0) {
+        unsigned g = grid_for(S.nv, 256);
+        if (g > 8192) g = 8192;
+        hipLaunchKernelGGL(k_rowbox, dim3(g), dim3(256), 0, s, S.xyz, S.nv, S.v_off, S.G, S.rowbox);
+    }
+    if (S.nt == 0) return;
+    {
+        unsigned g = grid_for(S.nt, 256);
+        if (g > 16384) g = 16384;
+        hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, s, S.xyz, S.tri, S.nt, S.v_off, S.t_off,
+                           S.G, S.rowbox, S.keys[0], S.vals[0]);
+    }
+    int cur = radix_sort(S.keys, S.vals, S.hist, S.nt, key_bits, s);
+    hipLaunchKernelGGL(k_tiles, dim3(grid_for(S.NT, 4)), dim3(256), 0, s, S.xyz, S.tri, S.v_off,
+                       S.t_off, S.tile_off, S.G, S.NT, S.vals[cur], S.t32, S.t64, S.meta);
+}
+
+// ---------------------------------------------------------------------------
+// row state
+// ---------------------------------------------------------------------------
+__global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
+                            const unsigned long long *boxB) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    RowState r;
+    r.ub = double_to_bits(__builtin_inf());
+    r.d2 = double_to_bits(__builtin_inf());
+    r.hit = 0;
+    r.pad = 0;
+    double ext2 = 0.0;
+    bool ok = boxA[g * 6] != ~0ull && boxB[g * 6] != ~0ull;
+    if (ok) {
+        for (int k = 0; k < 3; k++) {
+            double lo = fmin(from_ordered_bits(boxA[g * 6 + k]), from_ordered_bits(boxB[g * 6 + k]));
+            double hi = fmax(from_ordered_bits(boxA[g * 6 + 3 + k]), from_ordered_bits(boxB[g * 6 + 3 + k]));
+            ext2 += (hi - lo) * (hi - lo);
+        }
+    }
+    r.margin_scale = 0x1p-36 * sqrt(ext2) * 1.01;
+    rows[g] = r;
+}
+
+void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
+                      const unsigned long long *boxB, hipStream_t s) {
+    if (G > 0)
+        hipLaunchKernelGGL(k_rows_init, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, boxA, boxB);
+}
+
+// ---------------------------------------------------------------------------
+// a3: tile-pair bounds and the work queue
+// ---------------------------------------------------------------------------
+// A work item is (row, block of 64 A tiles, chunk of 256 B tiles); the A
+// tiles' boxes sit in LDS and each thread walks them against its B tile.
+struct WorkItem {
+    int64_t g, a0, na, b;
+    bool bvalid;
+};
+
+__device__ __forceinline__ WorkItem decode_item(const int64_t *wi_off, int64_t G, int64_t wi,
+                                                const int64_t *tA, const int64_t *tB) {
+    WorkItem w;
+    w.g = find_row(wi_off, G, wi);
+    int64_t local = wi - wi_off[w.g];
+    int64_t nA = tA[w.g + 1] - tA[w.g], nB = tB[w.g + 1] - tB[w.g];
+    int64_t nbc = (nB + 255) / 256;
+    int64_t ab = local / nbc, bc = local % nbc;
+    w.a0 = tA[w.g] + ab * 64;
+    w.na = min((int64_t)64, nA - ab * 64);
+    int64_t bl = bc * 256 + threadIdx.x;
+    w.bvalid = bl < nB;
+    w.b = tB[w.g] + (w.bvalid ? bl : 0);
+    return w;
+}
+
+__device__ __forceinline__ double box_gap2(const double *alo, const double *ahi, const double *blo,
+                                           const double *bhi) {
+    double s = 0.0;
+    for (int k = 0; k < 3; k++) {
+        double gp = fmax(0.0, fmax(blo[k] - ahi[k], alo[k] - bhi[k]));
+        s += gp * gp;
+    }
+    return s;
+}
+
+// Upper bound seed: the distance between two real vertices bounds the row
+// distance from above.
+__global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileMeta *mB,
+                                                 const int64_t *tA, const int64_t *tB,
+                                                 const int64_t *wi_off, int64_t G, int64_t wi0,
+                                                 RowState *rows) {
+    __shared__ double rep[64][3];
+    WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
+    if (threadIdx.x < w.na)
+        for (int k = 0; k < 3; k++) rep[threadIdx.x][k] = mA[w.a0 + threadIdx.x].rep[k];
+    __syncthreads();
+    double best = __builtin_inf();
+    if (w.bvalid) {
+        double bp[3];
+        for (int k = 0; k < 3; k++) bp[k] = mB[w.b].rep[k];
+        for (int a = 0; a < w.na; a++) {
+            double dx = rep[a][0] - bp[0], dy = rep[a][1] - bp[1], dz = rep[a][2] - bp[2];
+            best = fmin(best, dx * dx + dy * dy + dz * dz);
+        }
+    }
+    best = wave_min(best);
+    if (lane_id() == 0 && best < __builtin_inf())
+        atomic_min_pos(&rows[w.g].ub, sqrt(best) * (1.0 + 8.0 * U64));
+}
+
+// Keep the tile pairs that may hold the minimum (distance: box lower bound
+// <= ub + m) or a contact (intersects: closed boxes overlap).
+__global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMeta *mB,
+                                                const int64_t *tA, const int64_t *tB,
+                                                const int64_t *wi_off, int64_t G, int64_t wi0,
+                                                const RowState *rows, int mode, int2 *queue,
+                                                float *qlb, unsigned int *qcount,
+                                                unsigned int qcap) {
+    __shared__ double box[64][6];
+    WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
+    if (threadIdx.x < w.na)
+        for (int k = 0; k < 3; k++) {
+            box[threadIdx.x][k] = mA[w.a0 + threadIdx.x].lo[k];
+            box[threadIdx.x][3 + k] = mA[w.a0 + threadIdx.x].hi[k];
+        }
+    __syncthreads();
+    double blo[3], bhi[3];
+    for (int k = 0; k < 3; k++) {
+        blo[k] = mB[w.b].lo[k];
+        bhi[k] = mB[w.b].hi[k];
+    }
+    const RowState &R = rows[w.g];
+    double ub = bits_to_double(R.ub);
+    double lim = ub + row_margin(R, ub);
+    bool hit = R.hit != 0;
+    for (int a = 0; a < w.na; a++) {
+        bool keep = false;
+        float lbf = 0.0f;
+        if (w.bvalid && !hit) {
+            double g2 = box_gap2(box[a], box[a] + 3, blo, bhi);
+            if (mode == 0) {
+                double lb = sqrt(g2) * (1.0 - 8.0 * U64);
+                keep = lb <= lim;
+                lbf = (float)(lb * (1.0 - 0x1p-20));
+            } else {
+                keep = g2 == 0.0 && box[a][0] <= bhi[0] && blo[0] <= box[a][3] &&
+                       box[a][1] <= bhi[1] && blo[1] <= box[a][4] && box[a][2] <= bhi[2] &&
+                       blo[2] <= box[a][5];
+            }
+        }
+        unsigned long long m = __ballot(keep);
+        if (m == 0) continue;
+        unsigned int basei = 0;
+        if (lane_id() == 0) basei = atomicAdd(qcount, (unsigned int)__popcll(m));
+        basei = __shfl(basei, 0);
+        if (keep) {
+            unsigned int idx = basei + (unsigned int)__popcll(m & lanes_below());
+            if (idx < qcap) {
+                queue[idx] = make_int2((int)(w.a0 + a), (int)w.b);
+                qlb[idx] = lbf;
+            }
+        }
+    }
+}
+
+void launch_queue(const SideBufs &A, const SideBufs &B, const int64_t *wi_off, int64_t n_wi,
+                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s) {
+    if (n_wi <= 0) return;
+    if (what == Q_SEED)
+        hipLaunchKernelGGL(k_ub_seed, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
+                           A.tile_off, B.tile_off, wi_off, A.G, wi_begin, rows);
+    else
+        hipLaunchKernelGGL(k_filter, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
+                           A.tile_off, B.tile_off, wi_off, A.G, wi_begin, rows,
+                           what == Q_FILTER_DIST ? 0 : 1, L.queue, L.qlb, L.qcount, L.qcap);
+}
+
+// ---------------------------------------------------------------------------
+// a4-a7: triangle-pair passes over the queue (persistent workgroups)
+// ---------------------------------------------------------------------------
+// Per-tile-pair constants of the FP32 pass (see sd3_pair32.h for the model):
+// the A tile is shifted into the B tile's frame; eps_c bounds how far the real
+// triangles are from their FP32 copies; eu / elb bound the evaluation error of
+// the upper / lower bounds; eo bounds the error of FP32 orientation values.
+struct TP32 {
+    float sh[3];
+    float eu, elb, eo, box_tol;
+    double eps_c;
+};
+
+__device__ __forceinline__ TP32 tp32_consts(const TileMeta &a, const TileMeta &b) {
+    TP32 c;
+    double dinf = 0.0;
+    for (int k = 0; k < 3; k++) {
+        double d = a.o[k] - b.o[k];
+        c.sh[k] = (float)d;
+        dinf = fmax(dinf, fabs(d));
+    }
+    double Ra = a.rad, Rb = b.rad;
+    double MA = (Ra + dinf) * (1.0 + 2.0 * U32) + 1e-30;
+    double epsA = a.eps + SQRT3 * (U32 * (Ra + 2.01 * dinf) + 2.0 * U64 * dinf);
+    double eps_c = (epsA + b.eps) * (1.0 + 1e-6);
+    double Mr = MA + Rb;
+    double Mw = Mr + 4.0 * fmax(Ra + 2.0 * U32 * MA, Rb);
+    c.eps_c = eps_c;
+    c.eu = (float)((8.0 * SQRT3 * U32 * Mw + eps_c) * (1.0 + 1e-5));
+    c.elb = (float)((16.0 * SQRT3 * U32 * Mr + eps_c) * (1.0 + 1e-5));
+    c.eo = (float)((24.0 * eps_c * Mw * Mw + 64.0 * U32 * Mw * Mw * Mw) * (1.0 + 1e-5));
+    c.box_tol = (float)((eps_c + 4.0 * U32 * Mr) * (1.0 + 1e-5));
+    return c;
+}
+
+struct TPShared {
+    int q, live, ta, tb, g, na, nb;
+    double ub, m;
+    float T2f;        // FP32 triangle-box cull threshold (squared)
+    double T2d;       // FP64 triangle-box cull threshold (squared)
+    TP32 c;
+    unsigned int cnt;
+    float redf[4];
+    double redd[4];
+};
+
+// Thread 0 dequeues the next tile pair and computes its constants.
+__device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned qcount,
+                                           const TileMeta *mA, const TileMeta *mB,
+                                           RowState *rows, int precision, int mode) {
+    unsigned q = atomicAdd(L.qhead, 1u);
+    S.q = (int)q;
+    S.live = 0;
+    S.cnt = 0;
+    if (q >= qcount) return;
+    int2 e = L.queue[q];
+    const TileMeta &a = mA[e.x];
+    const TileMeta &b = mB[e.y];
+    RowState *R = rows + a.row;
+    double ub = bits_to_double(load_acq(&R->ub));
+    uint32_t hit = load_acq32(&R->hit);
+    double m = row_margin(*R, ub);
+    S.ta = e.x;
+    S.tb = e.y;
+    S.g = a.row;
+    S.na = a.n;
+    S.nb = b.n;
+    S.ub = ub;
+    S.m = m;
+    if (hit) return;
+    if (mode == 0 && (double)L.qlb[q] > ub + m) return;
+    S.live = 1;
+    if (precision == 0) {
+        S.c = tp32_consts(a, b);
+        double T = (ub + m + S.c.eps_c) / (1.0 - 4.0 * U32);
+        double T2 = T * T * (1.0 + 16.0 * U32);
+        S.T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
+    } else {
+        double T = (ub + m) * (1.0 + 8.0 * U64);
+        S.T2d = T * T;
+    }
+}
+
+// Stage one tile into LDS (64 threads): FP32 copies shifted by sh, or FP64.
+__device__ __forceinline__ void stage32(float *dst, const float *src_tile, const float *sh, int j) {
+#pragma unroll
+    for (int c = 0; c < 9; c++) dst[c * K + j] = src_tile[c * K + j] + (sh ? sh[c % 3] : 0.0f);
+    tri_prep32(TriRef<float>{dst + j, K});
+}
+
+__device__ __forceinline__ void stage64(double *dst, const double *src_tile, int j) {
+#pragma unroll
+    for (int c = 0; c < 9; c++) dst[c * K + j] = src_tile[c * K + j];
+    tri_prep64(TriRef<double>{dst + j, K});
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        double x0 = dst[(F_V + k) * K + j], x1 = dst[(F_V + 3 + k) * K + j],
+               x2 = dst[(F_V + 6 + k) * K + j];
+        dst[(F_LO + k) * K + j] = fmin(x0, fmin(x1, x2));
+        dst[(F_HI + k) * K + j] = fmax(x0, fmax(x1, x2));
+    }
+}
+
+// Ballot-compacted append of (a | b << 8) to the LDS pair list.
+__device__ __forceinline__ void list_push(bool keep, int a, int b, uint16_t *list,
+                                          unsigned int *cnt) {
+    unsigned long long m = __ballot(keep);
+    if (m == 0) return;
+    unsigned int base = 0;
+    if (lane_id() == 0) base = atomicAdd(cnt, (unsigned int)__popcll(m));
+    base = __shfl(base, 0);
+    if (keep) list[base + __popcll(m & lanes_below())] = (uint16_t)(a | (b << 8));
+}
+
+// Append to a global list with one atomic per wave (divergence-safe).
+template <typename T>
+__device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, unsigned int *count,
+                                            unsigned int cap) {
+    unsigned long long act = __ballot(1);
+    unsigned long long m = __ballot(keep);
+    if (m == 0) return;
+    int leader = __ffsll((long long)act) - 1;
+    unsigned int base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (unsigned int)__popcll(m));
+    base = __shfl(base, leader);
+    if (keep) {
+        unsigned int idx = base + (unsigned int)__popcll(m & lanes_below());
+        if (idx < cap) arr[idx] = item;
+    }
+}
+
+template <int PREC, int MODE>
+__global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *t64A,
+                                               const TileMeta *mA, const float *t32B,
+                                               const double *t64B, const TileMeta *mB,
+                                               RowState *rows, Lists L) {
+    constexpr int NF = PREC == 0 ? F_NTRI32 : F_NTRI32;
+    using Tt = typename std::conditional<PREC == 0, float, double>::type;
+    __shared__ Tt sA[NF * K];
+    __shared__ Tt sB[NF * K];
+    __shared__ uint16_t list[K * K];
+    __shared__ TPShared S;
+    const int tid = threadIdx.x, w = tid >> 6;
+    const unsigned qcount = min(*L.qcount, L.qcap);
+    unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0;
+    for (;;) {
+        if (tid == 0) tp_dequeue(S, L, qcount, mA, mB, rows, PREC, MODE);
+        __syncthreads();
+        if ((unsigned)S.q >= qcount) break;
+        if (S.live) {
+            if (tid < 64) {
+                if (PREC == 0) stage32((float *)sA, t32A + (int64_t)S.ta * 9 * K, S.c.sh, tid);
+                else stage64((double *)sA, t64A + (int64_t)S.ta * 9 * K, tid);
+            } else if (tid < 128) {
+                if (PREC == 0) stage32((float *)sB, t32B + (int64_t)S.tb * 9 * K, nullptr, tid - 64);
+                else stage64((double *)sB, t64B + (int64_t)S.tb * 9 * K, tid - 64);
+            }
+            __syncthreads();
+            // phase 1: triangle boxes, compacted into the LDS list
+            {
+                int a = tid & 63, bq = tid >> 6;
+                Tt alo[3], ahi[3];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    alo[k] = sA[(F_LO + k) * K + a];
+                    ahi[k] = sA[(F_HI + k) * K + a];
+                }
+                for (int jb = 0; jb < 16; jb++) {
+                    int b = bq * 16 + jb;
+                    bool keep = a < S.na && b < S.nb;
+                    if (MODE == 0) {
+                        Tt g2 = 0;
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            Tt gp = fmax(fmax(sB[(F_LO + k) * K + b] - ahi[k], alo[k] - sB[(F_HI + k) * K + b]), (Tt)0);
+                            g2 += gp * gp;
+                        }
+                        if (PREC == 0) keep = keep && (float)g2 <= S.T2f;
+                        else keep = keep && (double)g2 <= S.T2d;
+                    } else {
+                        Tt tol = PREC == 0 ? (Tt)S.c.box_tol : (Tt)0;
+#pragma unroll
+                        for (int k = 0; k < 3; k++)
+                            keep = keep && sB[(F_LO + k) * K + b] - ahi[k] <= tol &&
+                                   alo[k] - sB[(F_HI + k) * K + b] <= tol;
+                    }
+                    list_push(keep, a, b, list, &S.cnt);
+                }
+            }
+            __syncthreads();
+            const unsigned cnt = S.cnt;
+            n_eval += tid == 0;
+            n_boxed += tid == 0 ? (unsigned long long)S.na * S.nb : 0;
+            n_tested += tid == 0 ? cnt : 0;
+            // phase 2: full tests of the surviving pairs
+            Tt tmin = (Tt)__builtin_inf();
+            for (unsigned k = tid; k < cnt; k += 256) {
+                int a = list[k] & 255, b = list[k] >> 8;
+                if (PREC == 0) {
+                    TriRef<float> TA{(float *)sA + a, K}, TB{(float *)sB + b, K};
+                    if (MODE == 0) {
+                        Pair32 r = pair32(TA, TB, S.c.elb);
+                        tmin = fmin(tmin, (Tt)r.d2);
+                        bool resc = (double)r.lb <= S.ub + S.m;
+                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), r.lb};
+                        global_push(resc, it, L.rescue, L.rcount, L.rcap);
+                        n_resc += resc;
+                    } else {
+                        int c = isect32(TA, TB, S.c.eo);
+                        if (c == 1) atomicOr(&rows[S.g].hit, 1u);
+                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0.0f};
+                        global_push(c == 2, it, L.rescue, L.rcount, L.rcap);
+                        n_resc += c == 2;
+                    }
+                } else {
+                    TriRef<double> TA{(double *)sA + a, K}, TB{(double *)sB + b, K};
+                    int st;
+                    double d2 = 0.0;
+                    if (MODE == 0) {
+                        Pair64 r = pair64(TA, TB);
+                        st = r.status;
+                        d2 = r.d2;
+                        tmin = fmin(tmin, (Tt)r.d2);
+                    } else {
+                        double va[9], vb[9];
+#pragma unroll
+                        for (int i = 0; i < 9; i++) {
+                            va[i] = TA[F_V + i];
+                            vb[i] = TB[F_V + i];
+                        }
+                        int f = tri_tri_filtered64(va, vb);
+                        st = f == 1 ? 1 : (f == 0 ? 0 : 2);
+                    }
+                    if (st == 1) atomicOr(&rows[S.g].hit, 1u);
+                    ExactItem it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0, d2};
+                    global_push(st == 2, it, L.exact, L.xcount, L.xcap);
+                    n_exact += st == 2;
+                }
+            }
+            if (MODE == 0) {
+                tmin = wave_min(tmin);
+                if (lane_id() == 0) {
+                    if (PREC == 0) S.redf[w] = (float)tmin;
+                    else S.redd[w] = (double)tmin;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    RowState *R = rows + S.g;
+                    if (PREC == 0) {
+                        float dm = fminf(fminf(S.redf[0], S.redf[1]), fminf(S.redf[2], S.redf[3]));
+                        if (dm < __builtin_inff()) {
+                            double U = sqrt((double)dm) * (1.0 + 4.0 * U32) + (double)S.c.eu;
+                            atomic_min_pos(&R->ub, U * (1.0 + 4.0 * U64));
+                        }
+                    } else {
+                        double dm = fmin(fmin(S.redd[0], S.redd[1]), fmin(S.redd[2], S.redd[3]));
+                        if (dm < __builtin_inf()) {
+                            atomic_min_pos(&R->d2, dm);
+                            atomic_min_pos(&R->ub, sqrt(dm));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        atomicAdd(&L.counters[C_TP_EVAL], n_eval);
+        atomicAdd(&L.counters[C_TRI_BOXED], n_boxed);
+        atomicAdd(&L.counters[PREC == 0 ? C_TRI32 : C_TRI64], n_tested);
+    }
+    n_resc = wave_sum(n_resc);
+    n_exact = wave_sum(n_exact);
+    if (lane_id() == 0) {
+        if (n_resc) atomicAdd(&L.counters[C_RESCUED], n_resc);
+        if (n_exact) atomicAdd(&L.counters[C_EXACT], n_exact);
+    }
+}
+
+void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
+                  int mode, int grid, hipStream_t s) {
+#define SD3_LAUNCH_PAIRS(P, M)                                                                   \
+    hipLaunchKernelGGL((k_pairs<P, M>), dim3(grid), dim3(WG), 0, s, A.t32, A.t64, A.meta, B.t32, \
+                       B.t64, B.meta, rows, L)
+    if (precision == 0 && mode == 0) SD3_LAUNCH_PAIRS(0, 0);
+    else if (precision == 0) SD3_LAUNCH_PAIRS(0, 1);
+    else if (mode == 0) SD3_LAUNCH_PAIRS(1, 0);
+    else SD3_LAUNCH_PAIRS(1, 1);
+#undef SD3_LAUNCH_PAIRS
+}
+
+// ---------------------------------------------------------------------------
+// a5: FP64 rescue of the pairs the FP32 bounds did not settle
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_tri64(const double *t64, int tile, int slot, double *out) {
+#pragma unroll
+    for (int c = 0; c < 9; c++) out[c] = t64[((int64_t)tile * 9 + c) * K + slot];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMeta *mA,
+                                                const double *t64B, RowState *rows, Lists L) {
+    const unsigned n = min(*L.rcount, L.rcap);
+    unsigned long long n64 = 0, nex = 0;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        Rescue e = L.rescue[i];
+        int g = mA[e.ta].row;
+        RowState *R = rows + g;
+        if (load_acq32(&R->hit)) continue;
+        int a = e.slots & 0xffff, b = e.slots >> 16;
+        if (MODE == 0) {
+            double ub = bits_to_double(load_acq(&R->ub));
+            if ((double)e.lb > ub + row_margin(*R, ub)) continue;
+            double ta[F_NTRI64], tb[F_NTRI64];
+            load_tri64(t64A, e.ta, a, ta);
+            load_tri64(t64B, e.tb, b, tb);
+            tri_prep64(TriRef<double>{ta, 1});
+            tri_prep64(TriRef<double>{tb, 1});
+            Pair64 r = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1});
+            n64++;
+            if (r.status == 1) {
+                atomicOr(&R->hit, 1u);
+                atomic_min_pos(&R->d2, 0.0);
+            } else {
+                atomic_min_pos(&R->d2, r.d2);
+                if (r.status == 2) {
+                    ExactItem it{e.ta, e.tb, e.slots, 0, r.d2};
+                    unsigned j = atomicAdd(L.xcount, 1u);
+                    if (j < L.xcap) L.exact[j] = it;
+                    nex++;
+                }
+            }
+        } else {
+            double va[9], vb[9];
+            load_tri64(t64A, e.ta, a, va);
+            load_tri64(t64B, e.tb, b, vb);
+            int f = tri_tri_filtered64(va, vb);
+            n64++;
+            if (f == 1) atomicOr(&R->hit, 1u);
+            else if (f == 2) {
+                ExactItem it{e.ta, e.tb, e.slots, 0, 0.0};
+                unsigned j = atomicAdd(L.xcount, 1u);
+                if (j < L.xcap) L.exact[j] = it;
+                nex++;
+            }
+        }
+    }
+    n64 = wave_sum(n64);
+    nex = wave_sum(nex);
+    if (lane_id() == 0) {
+        if (n64) atomicAdd(&L.counters[C_TRI64], n64);
+        if (nex) atomicAdd(&L.counters[C_EXACT], nex);
+    }
+}
+
+void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                   int grid, hipStream_t s) {
+    if (mode == 0)
+        hipLaunchKernelGGL(k_rescue<0>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L);
+    else
+        hipLaunchKernelGGL(k_rescue<1>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L);
+}
+
+// ---------------------------------------------------------------------------
+// exact arithmetic for the pairs the FP64 filter left undecided
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_exact(const double *t64A, const TileMeta *mA,
+                                              const double *t64B, RowState *rows, Lists L,
+                                              int mode) {
+    const unsigned n = min(*L.xcount, L.xcap);
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        ExactItem e = L.exact[i];
+        RowState *R = rows + mA[e.ta].row;
+        if (load_acq32(&R->hit)) continue;
+        double va[9], vb[9];
+        load_tri64(t64A, e.ta, e.slots & 0xffff, va);
+        load_tri64(t64B, e.tb, e.slots >> 16, vb);
+        if (ex::tri_tri_exact(va, vb)) {
+            atomicOr(&R->hit, 1u);
+            atomic_min_pos(&R->d2, 0.0);
+        } else if (mode == 0) {
+            atomic_min_pos(&R->d2, e.d2);
+        }
+    }
+}
+
+void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                  int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, A.t64, A.meta, B.t64, rows, L, mode);
+}
+
+// ---------------------------------------------------------------------------
+// final reduction
+// ---------------------------------------------------------------------------
+__global__ void k_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    bool h = rows[g].hit != 0;
+    if (dist) dist[g] = h ? 0.0 : sqrt(bits_to_double(rows[g].d2));
+    if (hit) hit[g] = h ? 1 : 0;
+}
+
+void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, hipStream_t s) {
+    if (G > 0)
+        hipLaunchKernelGGL(k_finalize, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, dist, hit);
+}
+
+__global__ void k_reset_lists(Lists L) {
+    int i = threadIdx.x;
+    if (i == 0) {
+        *L.qcount = 0;
+        *L.qhead = 0;
+        *L.rcount = 0;
+        *L.rhead = 0;
+        *L.xcount = 0;
+    }
+    if (i < C_NCOUNTERS) L.counters[i] = 0;
+}
+
+void launch_reset_lists(Lists &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_lists, dim3(1), dim3(64), 0, s, L);
+}
+
+__global__ void k_reset_queue(Lists L) {
+    if (threadIdx.x == 0) {
+        *L.qcount = 0;
+        *L.qhead = 0;
+    }
+}
+
+void launch_reset_queue(Lists &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, L);
+}
+
+void launch_sort_queue(Lists &, uint64_t *, int32_t *, uint64_t *, int32_t *, uint32_t *, int2 *,
+                       float *, unsigned int, hipStream_t) {}
+
+}  // namespace sd3

@@ -1,0 +1,217 @@
+"""Python binding of the sd3 C-ABI (include/sd3.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libsd3.so`` built in this directory.  PyTorch provides device
+memory and the current HIP stream.  There is no CPU fallback: if the library
+is not built, or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsd3.so")
+
+MEM_HOST, MEM_DEVICE = 0, 1
+PREC = {"fp32": 0, "fp64": 1}
+ORDER = {"bound": 0, "none": 1}
+
+STATUS = {
+    0: "SD3_OK", 1: "SD3_E_INVALID_ARG", 2: "SD3_E_INDEX_RANGE", 3: "SD3_E_NONFINITE",
+    4: "SD3_E_RANGE", 5: "SD3_E_NOMEM", 6: "SD3_E_DEVICE", 7: "SD3_E_NO_DEVICE",
+    8: "SD3_E_CAPACITY",
+}
+
+EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
+           "sd3_validate", "sd3_status_string", "sd3_last_error"]
+
+
+class Geoms(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("tri", ctypes.c_void_p), ("v_off", ctypes.c_void_p),
+                ("t_off", ctypes.c_void_p), ("count", ctypes.c_int64), ("mem", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("tile_pairs_total", ctypes.c_int64), ("tile_pairs_candidate", ctypes.c_int64),
+                ("tile_pairs_evaluated", ctypes.c_int64), ("tri_pairs_boxed", ctypes.c_int64),
+                ("tri_pairs_fp32", ctypes.c_int64), ("tri_pairs_fp64", ctypes.c_int64),
+                ("rescued", ctypes.c_int64), ("exact", ctypes.c_int64),
+                ("ms_total", ctypes.c_double), ("reserved", ctypes.c_int64 * 7)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class SD3Error(RuntimeError):
+    def __init__(self, status, message=""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsd3.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"sd3 HIP library not built: {path} (run python -m "
+                           "paper_1808_09571_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.sd3_default_opts.argtypes = [P(Opts)]
+    lib.sd3_default_opts.restype = None
+    lib.sd3_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int]
+    lib.sd3_create.restype = ctypes.c_int
+    lib.sd3_destroy.argtypes = [ctypes.c_void_p]
+    lib.sd3_destroy.restype = ctypes.c_int
+    lib.sd3_distance.argtypes = [ctypes.c_void_p, P(Geoms), P(Geoms), ctypes.c_void_p,
+                                 ctypes.c_void_p, P(Opts), P(Stats), ctypes.c_void_p]
+    lib.sd3_distance.restype = ctypes.c_int
+    lib.sd3_intersects.argtypes = [ctypes.c_void_p, P(Geoms), P(Geoms), ctypes.c_void_p,
+                                   P(Opts), P(Stats), ctypes.c_void_p]
+    lib.sd3_intersects.restype = ctypes.c_int
+    lib.sd3_validate.argtypes = [P(Geoms)]
+    lib.sd3_validate.restype = ctypes.c_int
+    lib.sd3_status_string.argtypes = [ctypes.c_int]
+    lib.sd3_status_string.restype = ctypes.c_char_p
+    lib.sd3_last_error.argtypes = [ctypes.c_void_p]
+    lib.sd3_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Batch:
+    """CSR batch of meshes: ``xyz`` float64 [nv*3] and ``tri`` int32 [nt*3] (host
+    numpy arrays or device torch tensors), offsets int64 numpy arrays [G+1]."""
+    xyz: object
+    tri: object
+    v_off: np.ndarray
+    t_off: np.ndarray
+
+    @property
+    def count(self) -> int:
+        return int(self.v_off.shape[0] - 1)
+
+    @property
+    def on_device(self) -> bool:
+        return not isinstance(self.xyz, np.ndarray)
+
+    @classmethod
+    def from_packed(cls, p, device=None):
+        """From a synth.Packed (host arrays); ``device`` copies xyz/tri to a torch
+        device."""
+        v_off = np.ascontiguousarray(p.v_off, dtype=np.int64)
+        t_off = np.ascontiguousarray(p.t_off, dtype=np.int64)
+        if device is None:
+            return cls(np.ascontiguousarray(p.xyz, dtype=np.float64),
+                       np.ascontiguousarray(p.tri, dtype=np.int32), v_off, t_off)
+        import torch
+        return cls(torch.from_numpy(np.ascontiguousarray(p.xyz, dtype=np.float64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(p.tri, dtype=np.int32)).to(device),
+                   v_off, t_off)
+
+    def geoms(self) -> Geoms:
+        if self.on_device:
+            import torch
+            assert self.xyz.dtype == torch.float64 and self.tri.dtype == torch.int32
+            assert self.xyz.is_contiguous() and self.tri.is_contiguous()
+            xp, tp, mem = self.xyz.data_ptr(), self.tri.data_ptr(), MEM_DEVICE
+        else:
+            assert self.xyz.dtype == np.float64 and self.tri.dtype == np.int32
+            xp, tp, mem = self.xyz.ctypes.data, self.tri.ctypes.data, MEM_HOST
+        return Geoms(xp, tp, self.v_off.ctypes.data, self.t_off.ctypes.data, self.count, mem)
+
+
+class Context:
+    """An sd3 context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        st = self.lib.sd3_create(ctypes.byref(h), int(device))
+        if st != 0:
+            raise SD3Error(st, self.lib.sd3_status_string(st).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sd3_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        raise SD3Error(st, self.lib.sd3_last_error(self.handle).decode())
+
+    @staticmethod
+    def _opts(precision, order):
+        o = Opts()
+        o.precision = PREC[precision]
+        o.order = ORDER[order]
+        return o
+
+    def _stream(self, a: Batch):
+        if not a.on_device:
+            return None
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(a.xyz.device).cuda_stream)
+
+    def _outputs(self, a: Batch, want_dist: bool):
+        G = a.count
+        if a.on_device:
+            import torch
+            d = torch.empty(G, dtype=torch.float64, device=a.xyz.device) if want_dist else None
+            h = torch.empty(G, dtype=torch.uint8, device=a.xyz.device)
+            return d, h, (d.data_ptr() if want_dist else None), h.data_ptr()
+        d = np.empty(G, dtype=np.float64) if want_dist else None
+        h = np.empty(G, dtype=np.uint8)
+        return d, h, (d.ctypes.data if want_dist else None), h.ctypes.data
+
+    def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False):
+        """Row-wise 3D distance (and the exact intersects flag as a by-product)."""
+        ga, gb = a.geoms(), b.geoms()
+        d, h, dp, hp = self._outputs(a, True)
+        s = Stats()
+        o = self._opts(precision, order)
+        st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
+                                   ctypes.byref(o), ctypes.byref(s), self._stream(a))
+        if st != 0:
+            self._raise(st)
+        return (d, h, s.as_dict()) if stats else (d, h)
+
+    def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False):
+        """Row-wise exact 3D intersects."""
+        ga, gb = a.geoms(), b.geoms()
+        _, h, _, hp = self._outputs(a, False)
+        s = Stats()
+        o = self._opts(precision, order)
+        st = self.lib.sd3_intersects(self.handle, ctypes.byref(ga), ctypes.byref(gb), hp,
+                                     ctypes.byref(o), ctypes.byref(s), self._stream(a))
+        if st != 0:
+            self._raise(st)
+        return (h, s.as_dict()) if stats else h
+
+
+def validate(batch: Batch) -> int:
+    """Host-side validation status of a host batch (0 = valid)."""
+    g = batch.geoms()
+    return int(load().sd3_validate(ctypes.byref(g)))

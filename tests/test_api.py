@@ -1,0 +1,127 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+function include/sd3.h declares, maps status codes, and rejects malformed
+host batches before any device work (Sec. 3.1: inputs are TINs / polyhedral
+surfaces given as vertex and triangle arrays, one geometry per table row)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1808_09571_amd import sd3, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sd3.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sd3_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return sd3.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(sd3.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", sd3.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sd3_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+
+
+def test_status_strings(lib):
+    for code in range(9):
+        s = lib.sd3_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.sd3_status_string(99).decode() == "unknown status"
+
+
+def test_default_opts(lib):
+    o = sd3.Opts()
+    o.precision, o.order = 7, 7
+    lib.sd3_default_opts(ctypes.byref(o))
+    assert o.precision == 0 and o.order == 0
+
+
+def _batch(meshes):
+    return sd3.Batch.from_packed(synth.pack(meshes))
+
+
+def test_validate_accepts_good_batches():
+    assert sd3.validate(_batch([synth.cube(), synth.icosphere(1)])) == 0
+    empty = (np.zeros((0, 3)), np.zeros((0, 3), dtype=np.int32))
+    assert sd3.validate(_batch([empty, synth.cube()])) == 0
+    assert sd3.validate(_batch([])) == 0
+
+
+def test_validate_rejects_bad_batches():
+    x, t = synth.cube()
+    b = _batch([(x, t)])
+    b.xyz[5] = np.nan
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_NONFINITE"
+    b = _batch([(x, t)])
+    b.xyz[2] = np.inf
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_NONFINITE"
+    b = _batch([(x, t)])
+    b.xyz[0] = 1e-300
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_RANGE"
+    b = _batch([(x, t)])
+    b.xyz[0] = 2.0 ** 300
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_RANGE"
+    b = _batch([(x, t)])
+    b.tri[4] = 8
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INDEX_RANGE"
+    b = _batch([(x, t)])
+    b.tri[0] = -1
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INDEX_RANGE"
+    # indices are local to their row
+    b = _batch([(x, t), (x, t)])
+    b.tri[3 * 12] = 8
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INDEX_RANGE"
+    b = _batch([(x, t), (x, t)])
+    b.t_off = np.array([0, 12, 6], dtype=np.int64)
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INVALID_ARG"
+    b = _batch([(x, t)])
+    b.v_off = np.array([1, 8], dtype=np.int64)
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INVALID_ARG"
+
+
+def test_validate_null_pointers(lib):
+    assert sd3.STATUS[lib.sd3_validate(None)] == "SD3_E_INVALID_ARG"
+    g = sd3.Geoms(None, None, None, None, 1, 0)
+    assert sd3.STATUS[lib.sd3_validate(ctypes.byref(g))] == "SD3_E_INVALID_ARG"
+    off = np.array([0, 3], dtype=np.int64)
+    toff = np.array([0, 1], dtype=np.int64)
+    g = sd3.Geoms(None, None, off.ctypes.data, toff.ctypes.data, 1, 0)
+    assert sd3.STATUS[lib.sd3_validate(ctypes.byref(g))] == "SD3_E_INVALID_ARG"
+    g = sd3.Geoms(None, None, off.ctypes.data, toff.ctypes.data, -1, 0)
+    assert sd3.STATUS[lib.sd3_validate(ctypes.byref(g))] == "SD3_E_INVALID_ARG"
+
+
+def test_null_context_and_outputs(lib):
+    b = _batch([synth.cube()])
+    ga, gb = b.geoms(), b.geoms()
+    out = np.zeros(1)
+    st = lib.sd3_distance(None, ctypes.byref(ga), ctypes.byref(gb), out.ctypes.data, None, None,
+                          None, None)
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+    assert lib.sd3_destroy(None) == 0
+    assert lib.sd3_last_error(None).decode() == ""
+    assert sd3.STATUS[lib.sd3_create(None, 0)] == "SD3_E_INVALID_ARG"
+
+
+def test_create_without_gfx950_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p(123)
+    st = lib.sd3_create(ctypes.byref(h), 0)
+    assert sd3.STATUS[st] == "SD3_E_NO_DEVICE" and h.value is None
