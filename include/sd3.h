@@ -87,7 +87,9 @@ typedef struct sd3_geoms {
 typedef struct sd3_opts {
     int32_t precision; /* SD3_PREC_* */
     int32_t order;     /* SD3_ORDER_* */
-    int32_t reserved[6];
+    int32_t timing;    /* nonzero: record HIP events around each phase on the
+                          call's stream and report their durations in stats */
+    int32_t reserved[5];
 } sd3_opts;
 
 /* Work counters of the last call (all tile and triangle counts summed over rows). */
@@ -101,7 +103,11 @@ typedef struct sd3_stats {
     int64_t rescued;              /* FP32 pairs sent to the FP64 pass */
     int64_t exact;                /* pairs settled by exact arithmetic */
     double ms_total;              /* wall time of the call, host clock */
-    int64_t reserved[7];
+    /* with opts.timing: device time of each phase (HIP events on the stream):
+       [0] validation + upload, [1] sort + tiles, [2] bounds + queue,
+       [3] triangle-pair pass, [4] FP64 rescue, [5] exact arithmetic,
+       [6] final reduction and download */
+    double ms_phase[7];
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;

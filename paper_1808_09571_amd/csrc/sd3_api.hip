@@ -20,13 +20,14 @@ struct DevBuf {
 };
 
 struct SideState {
-    DevBuf xyz, tri, v_off, t_off, tile_off, rowbox, keys0, keys1, vals0, vals1, hist, t32, t64, meta;
+    DevBuf xyz, tri, v_off, t_off, tile_off, rowbox, t32, t64, meta;
 };
 
 struct Plan {
     int64_t G = 0;
     std::vector<int64_t> tileA, tileB;  // [G+1] tile offsets
     std::vector<int64_t> wi;            // [G+1] work-item offsets
+    std::vector<int64_t> blkA, chkB;    // [G+1] A-block (64 tiles) / B-chunk (256 tiles) offsets
     int64_t potential = 0;              // sum of tilesA * tilesB
 };
 
@@ -38,6 +39,11 @@ struct sd3_ctx {
     std::string err;
     SideState side[2];
     DevBuf rows, wi_off, queue, qlb, rescue, exact, counters, scalars, flags, out_d, out_h;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb;
+    void *pin = nullptr;  // pinned host staging: offsets up, counters down
+    size_t pin_cap = 0;
+    int pairs_grid[2][2] = {{0, 0}, {0, 0}};
+    hipEvent_t ev[8] = {};
 };
 
 namespace {
@@ -76,6 +82,22 @@ void *ensure(DevBuf &b, size_t bytes) {
     b.cap = want;
     return b.p;
 }
+
+// Pinned host staging of `bytes` (+ a 512-byte readback area at the end).
+char *ensure_pinned(sd3_ctx *ctx, size_t bytes) {
+    bytes += 512;
+    if (ctx->pin_cap < bytes) {
+        if (ctx->pin) check(hipHostFree(ctx->pin), "hipHostFree");
+        ctx->pin = nullptr;
+        ctx->pin_cap = 0;
+        size_t want = bytes + bytes / 4 + 4096;
+        check(hipHostMalloc(&ctx->pin, want, hipHostMallocDefault), "hipHostMalloc");
+        ctx->pin_cap = want;
+    }
+    return (char *)ctx->pin;
+}
+
+char *readback_area(sd3_ctx *ctx) { return (char *)ctx->pin + ctx->pin_cap - 512; }
 
 void release(DevBuf &b) {
     if (b.p) (void)hipFree(b.p);
@@ -159,15 +181,16 @@ sd3_status check_host_data(const sd3_geoms *g, std::string &msg) {
 int64_t tiles_of(int64_t nt) { return (nt + K - 1) / K; }
 
 // Upload (host inputs) or reference (device inputs) one side and size its
-// buffers.  No kernel reads the data before it has been validated.
-void setup_side(sd3_ctx *ctx, int which, const sd3_geoms *g, const std::vector<int64_t> &tile_off,
-                  SideBufs &S, hipStream_t s) {
+// buffers.  Offsets were staged already.  No kernel reads the data before it
+// has been validated.
+void setup_side(sd3_ctx *ctx, int which, const sd3_geoms *g, int64_t NT, const int64_t *d_offs,
+                SideBufs &S, hipStream_t s) {
     SideState &st = ctx->side[which];
     int64_t G = g->count, nv = g->v_off[G], nt = g->t_off[G];
     S.G = G;
     S.nv = nv;
     S.nt = nt;
-    S.NT = tile_off[G];
+    S.NT = NT;
     if (g->mem == SD3_MEM_HOST) {
         double *x = (double *)ensure(st.xyz, sizeof(double) * 3 * nv);
         int32_t *t = (int32_t *)ensure(st.tri, sizeof(int32_t) * 3 * nt);
@@ -179,21 +202,10 @@ void setup_side(sd3_ctx *ctx, int which, const sd3_geoms *g, const std::vector<i
         S.xyz = g->xyz;
         S.tri = g->tri;
     }
-    int64_t *vo = (int64_t *)ensure(st.v_off, sizeof(int64_t) * (G + 1));
-    int64_t *to = (int64_t *)ensure(st.t_off, sizeof(int64_t) * (G + 1));
-    int64_t *tf = (int64_t *)ensure(st.tile_off, sizeof(int64_t) * (G + 1));
-    check(hipMemcpyAsync(vo, g->v_off, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s), "H2D v_off");
-    check(hipMemcpyAsync(to, g->t_off, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s), "H2D t_off");
-    check(hipMemcpyAsync(tf, tile_off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s), "H2D tiles");
-    S.v_off = vo;
-    S.t_off = to;
-    S.tile_off = tf;
+    S.v_off = d_offs;
+    S.t_off = d_offs + (G + 1);
+    S.tile_off = d_offs + 2 * (G + 1);
     S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * (G > 0 ? G : 1));
-    S.keys[0] = (uint64_t *)ensure(st.keys0, sizeof(uint64_t) * nt);
-    S.keys[1] = (uint64_t *)ensure(st.keys1, sizeof(uint64_t) * nt);
-    S.vals[0] = (int32_t *)ensure(st.vals0, sizeof(int32_t) * nt);
-    S.vals[1] = (int32_t *)ensure(st.vals1, sizeof(int32_t) * nt);
-    S.hist = (uint32_t *)ensure(st.hist, sizeof(uint32_t) * 256 * ((nt + 4095) / 4096 + 1));
     S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * K * S.NT);
     S.t64 = (double *)ensure(st.t64, sizeof(double) * 9 * K * S.NT);
     S.meta = (TileMeta *)ensure(st.meta, sizeof(TileMeta) * S.NT);
@@ -207,18 +219,40 @@ int key_bits(int64_t G) {
 }
 
 // Validate device-resident data on the device (one synchronisation).
-sd3_status validate_device(sd3_ctx *ctx, const sd3_geoms *g, const SideBufs &S, hipStream_t s) {
+sd3_status validate_device(sd3_ctx *ctx, const sd3_geoms *a, const SideBufs &A,
+                           const sd3_geoms *b, const SideBufs &B, hipStream_t s) {
     uint32_t *flags = (uint32_t *)ensure(ctx->flags, 256);
-    check(hipMemsetAsync(flags, 0, sizeof(uint32_t), s), "memset flags");
-    launch_validate(g->xyz, S.nv, g->tri, S.nt, S.v_off, S.t_off, S.G, flags, s);
-    uint32_t h = 0;
-    check(hipMemcpyAsync(&h, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "D2H flags");
+    check(hipMemsetAsync(flags, 0, 2 * sizeof(uint32_t), s), "memset flags");
+    launch_validate(a->xyz, A.nv, a->tri, A.nt, A.v_off, A.t_off, A.G, flags, s);
+    launch_validate(b->xyz, B.nv, b->tri, B.nt, B.v_off, B.t_off, B.G, flags + 1, s);
+    uint32_t *h = (uint32_t *)readback_area(ctx);
+    check(hipMemcpyAsync(h, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "D2H flags");
     check(hipStreamSynchronize(s), "sync");
-    if (h & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
-    if (h & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
-    if (h & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside its row");
+    uint32_t f = h[0] | h[1];
+    if (f & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
+    if (f & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
+    if (f & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside its row");
     return SD3_OK;
 }
+
+// Phase events (opts.timing): ev[0] at the start, ev[k+1] at the end of phase k.
+struct PhaseClock {
+    sd3_ctx *ctx;
+    hipStream_t s;
+    bool on;
+    void mark(int k) {
+        if (!on) return;
+        if (!ctx->ev[k]) check(hipEventCreate(&ctx->ev[k]), "hipEventCreate");
+        check(hipEventRecord(ctx->ev[k], s), "hipEventRecord");
+    }
+    void read(double *ms) {
+        for (int k = 0; k < 7; k++) {
+            float f = 0.0f;
+            if (on) check(hipEventElapsedTime(&f, ctx->ev[k], ctx->ev[k + 1]), "hipEventElapsedTime");
+            ms[k] = f;
+        }
+    }
+};
 
 sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist, uint8_t *hit,
                const sd3_opts *opts_in, sd3_stats *stats, void *stream, int mode) {
@@ -255,28 +289,68 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         P.tileA.assign(G + 1, 0);
         P.tileB.assign(G + 1, 0);
         P.wi.assign(G + 1, 0);
+        P.blkA.assign(G + 1, 0);
+        P.chkB.assign(G + 1, 0);
         for (int64_t g = 0; g < G; g++) {
             int64_t na = tiles_of(a->t_off[g + 1] - a->t_off[g]);
             int64_t nb = tiles_of(b->t_off[g + 1] - b->t_off[g]);
             P.tileA[g + 1] = P.tileA[g] + na;
             P.tileB[g + 1] = P.tileB[g] + nb;
-            P.wi[g + 1] = P.wi[g] + ((na + 63) / 64) * ((nb + 255) / 256);
+            P.blkA[g + 1] = P.blkA[g] + (na + 63) / 64;
+            P.chkB[g + 1] = P.chkB[g] + (nb + 255) / 256;
+            // a row with an empty side has no work items
+            P.wi[g + 1] = P.wi[g] + (na > 0 && nb > 0 ? ((na + 63) / 64) * ((nb + 255) / 256) : 0);
             P.potential += na * nb;
         }
+        PhaseClock clk{ctx, s, opts.timing != 0};
+        clk.mark(0);
+        // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
+        // B v_off | B t_off | B tiles | work items | A blocks | B chunks]
+        const int64_t G1 = G + 1;
+        int64_t *hs = (int64_t *)ensure_pinned(ctx, sizeof(int64_t) * 9 * G1);
+        memcpy(hs, a->v_off, sizeof(int64_t) * G1);
+        memcpy(hs + G1, a->t_off, sizeof(int64_t) * G1);
+        memcpy(hs + 2 * G1, P.tileA.data(), sizeof(int64_t) * G1);
+        memcpy(hs + 3 * G1, b->v_off, sizeof(int64_t) * G1);
+        memcpy(hs + 4 * G1, b->t_off, sizeof(int64_t) * G1);
+        memcpy(hs + 5 * G1, P.tileB.data(), sizeof(int64_t) * G1);
+        memcpy(hs + 6 * G1, P.wi.data(), sizeof(int64_t) * G1);
+        memcpy(hs + 7 * G1, P.blkA.data(), sizeof(int64_t) * G1);
+        memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
+        int64_t *ds = (int64_t *)ensure(ctx->small, sizeof(int64_t) * 9 * G1);
+        check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
         SideBufs A{}, B{};
-        setup_side(ctx, 0, a, P.tileA, A, s);
-        setup_side(ctx, 1, b, P.tileB, B, s);
+        setup_side(ctx, 0, a, P.tileA[G], ds, A, s);
+        setup_side(ctx, 1, b, P.tileB[G], ds + 3 * G1, B, s);
         if (a->mem == SD3_MEM_DEVICE) {
-            st = validate_device(ctx, a, A, s);
-            if (st == SD3_OK) st = validate_device(ctx, b, B, s);
+            st = validate_device(ctx, a, A, b, B, s);
             if (st != SD3_OK) return st;
         }
-        launch_prep(A, key_bits(G), s);
-        launch_prep(B, key_bits(G), s);
+        clk.mark(1);
+        PrepBufs PB{};
+        {
+            int64_t n = A.nt + B.nt;
+            int64_t nb = (n + 4095) / 4096 + 1;
+            PB.keys[0] = (uint64_t *)ensure(ctx->keys0, sizeof(uint64_t) * n);
+            PB.keys[1] = (uint64_t *)ensure(ctx->keys1, sizeof(uint64_t) * n);
+            PB.vals[0] = (int32_t *)ensure(ctx->vals0, sizeof(int32_t) * n);
+            PB.vals[1] = (int32_t *)ensure(ctx->vals1, sizeof(int32_t) * n);
+            PB.hist = (uint32_t *)ensure(ctx->hist, sizeof(uint32_t) * 256 * nb);
+            PB.part = (uint32_t *)ensure(ctx->part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
+        }
+        launch_prep(A, B, PB, key_bits(G), s);
+        QueueGeo Q{};
+        Q.wi_off = ds + 6 * G1;
+        Q.blkA = ds + 7 * G1;
+        Q.chkB = ds + 8 * G1;
+        Q.gA = (GroupBox *)ensure(ctx->grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
+        Q.gB = (GroupBox *)ensure(ctx->grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
+        Q.wi_lb = (float *)ensure(ctx->wi_lb, sizeof(float) * (P.wi[G] + 1));
+        launch_group_boxes(A, Q.blkA, P.blkA[G], 64, Q.gA, s);
+        launch_group_boxes(B, Q.chkB, P.chkB[G], 256, Q.gB, s);
         RowState *rows = (RowState *)ensure(ctx->rows, sizeof(RowState) * (G > 0 ? G : 1));
         launch_rows_init(rows, G, A.rowbox, B.rowbox, s);
-        int64_t *wi = (int64_t *)ensure(ctx->wi_off, sizeof(int64_t) * (G + 1));
-        check(hipMemcpyAsync(wi, P.wi.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s), "H2D wi");
+
         Lists L{};
         unsigned int qcap = (unsigned int)std::min<int64_t>(std::max<int64_t>(P.potential, 1), QUEUE_BUDGET);
         L.queue = (int2 *)ensure(ctx->queue, sizeof(int2) * qcap);
@@ -286,38 +360,62 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         L.rcap = RESCUE_CAP;
         L.exact = (ExactItem *)ensure(ctx->exact, sizeof(ExactItem) * EXACT_CAP);
         L.xcap = EXACT_CAP;
-        unsigned int *sc = (unsigned int *)ensure(ctx->scalars, 64);
+        // device scalars (64 B) followed by the counters, read back in one copy
+        unsigned int *sc = (unsigned int *)ensure(ctx->scalars, 64 + sizeof(unsigned long long) * C_NCOUNTERS);
         L.qcount = sc;
         L.qhead = sc + 1;
         L.rcount = sc + 2;
         L.rhead = sc + 3;
         L.xcount = sc + 4;
-        L.counters = (unsigned long long *)ensure(ctx->counters, sizeof(unsigned long long) * C_NCOUNTERS);
+        L.counters = (unsigned long long *)(sc + 16);
         launch_reset_lists(L, s);
+        clk.mark(2);
         const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
-        const int grid_pairs = ctx->cus * 8;
+        int &gp = ctx->pairs_grid[prec][mode];
+        if (gp == 0) gp = ctx->cus * pairs_blocks_per_cu(prec, mode);
+        const int grid_pairs = gp;
         // the queue holds at most qcap tile pairs: split the work items into
         // passes whose potential tile pairs fit
         int64_t n_wi = P.wi[G];
         int64_t per_pass = P.potential <= (int64_t)qcap ? std::max<int64_t>(n_wi, 1)
                                                         : std::max<int64_t>(1, qcap / (64 * 256));
-        if (mode == 0) launch_queue(A, B, wi, n_wi, 0, rows, L, Q_SEED, s);
+        launch_queue(A, B, Q, n_wi, 0, rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
         std::vector<unsigned long long> cand_total(1, 0);
         for (int64_t w0 = 0; w0 < n_wi; w0 += per_pass) {
             int64_t nw = std::min(per_pass, n_wi - w0);
             if (w0 > 0) launch_reset_queue(L, s);
-            launch_queue(A, B, wi, nw, w0, rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
+            launch_queue(A, B, Q, nw, w0, rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
+            if (w0 == 0) clk.mark(3);
             launch_pairs(A, B, rows, L, prec, mode, grid_pairs, s);
             if (n_wi > per_pass) {
-                unsigned int qc = 0;
-                check(hipMemcpyAsync(&qc, L.qcount, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "D2H qcount");
+                unsigned int *qh = (unsigned int *)readback_area(ctx);
+                check(hipMemcpyAsync(qh, L.qcount, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "D2H qcount");
                 check(hipStreamSynchronize(s), "sync");
+                unsigned int qc = *qh;
                 if (qc > qcap) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
                 cand_total[0] += qc;
             }
         }
+        if (n_wi == 0) clk.mark(3);
+        clk.mark(4);
         if (prec == 0) launch_rescue(A, B, rows, L, mode, ctx->cus * 4, s);
-        launch_exact(A, B, rows, L, mode, ctx->cus * 4, s);
+        clk.mark(5);
+        launch_exact(A, B, rows, L, mode, 64, s);
+        clk.mark(6);
+        // counters first: an overflow is reported before any output is written
+        char *rb = readback_area(ctx);
+        check(hipMemcpyAsync(rb, sc, 64 + sizeof(unsigned long long) * C_NCOUNTERS, hipMemcpyDeviceToHost, s),
+              "D2H counters");
+        const unsigned int *sc_h = (const unsigned int *)rb;
+        const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
+        check(hipStreamSynchronize(s), "sync");
+        check(hipGetLastError(), "kernel launch");
+        if (n_wi <= per_pass) {
+            if (sc_h[0] > qcap) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
+            cand_total[0] = sc_h[0];
+        }
+        if (sc_h[2] > L.rcap) return fail(ctx, SD3_E_CAPACITY, "rescue list overflow");
+        if (sc_h[4] > L.xcap) return fail(ctx, SD3_E_CAPACITY, "exact list overflow");
         // outputs
         double *dd = nullptr;
         uint8_t *hd = nullptr;
@@ -330,23 +428,12 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             hd = hit ? (uint8_t *)(ob + sizeof(double) * G) : nullptr;
         }
         launch_finalize(rows, G, dd, hd, s);
-        unsigned int sc_h[5];
-        unsigned long long cnt_h[C_NCOUNTERS];
-        check(hipMemcpyAsync(sc_h, sc, sizeof(sc_h), hipMemcpyDeviceToHost, s), "D2H scalars");
-        check(hipMemcpyAsync(cnt_h, L.counters, sizeof(cnt_h), hipMemcpyDeviceToHost, s), "D2H counters");
-        check(hipStreamSynchronize(s), "sync");
-        check(hipGetLastError(), "kernel launch");
-        if (n_wi <= per_pass) {
-            if (sc_h[0] > qcap) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
-            cand_total[0] = sc_h[0];
-        }
-        if (sc_h[2] > L.rcap) return fail(ctx, SD3_E_CAPACITY, "rescue list overflow");
-        if (sc_h[4] > L.xcap) return fail(ctx, SD3_E_CAPACITY, "exact list overflow");
         if (a->mem == SD3_MEM_HOST && G > 0) {
             if (dist) check(hipMemcpyAsync(dist, dd, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H dist");
             if (hit) check(hipMemcpyAsync(hit, hd, G, hipMemcpyDeviceToHost, s), "D2H hit");
-            check(hipStreamSynchronize(s), "sync");
         }
+        clk.mark(7);
+        check(hipStreamSynchronize(s), "sync");
         if (stats) {
             memset(stats, 0, sizeof(*stats));
             stats->tile_pairs_total = P.potential;
@@ -359,6 +446,7 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             stats->exact = (int64_t)cnt_h[C_EXACT];
             stats->ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            clk.read(stats->ms_phase);
         }
     } catch (const HipError &e) {
         (void)hipGetLastError();
@@ -407,13 +495,19 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
     if (!ctx) return SD3_OK;
     (void)hipSetDevice(ctx->device);
     for (auto &sd : ctx->side) {
-        DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.v_off, &sd.t_off, &sd.tile_off, &sd.rowbox, &sd.keys0,
-                        &sd.keys1, &sd.vals0, &sd.vals1, &sd.hist, &sd.t32, &sd.t64, &sd.meta};
+        DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.v_off, &sd.t_off, &sd.tile_off, &sd.rowbox,
+                        &sd.t32, &sd.t64, &sd.meta};
         for (DevBuf *b : bs) release(*b);
     }
     DevBuf *bs[] = {&ctx->rows, &ctx->wi_off, &ctx->queue, &ctx->qlb, &ctx->rescue, &ctx->exact,
-                    &ctx->counters, &ctx->scalars, &ctx->flags, &ctx->out_d, &ctx->out_h};
+                    &ctx->counters, &ctx->scalars, &ctx->flags, &ctx->out_d, &ctx->out_h,
+                    &ctx->keys0, &ctx->keys1, &ctx->vals0, &ctx->vals1, &ctx->hist, &ctx->part,
+                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb};
     for (DevBuf *b : bs) release(*b);
+    for (hipEvent_t &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    release(ctx->small);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
     delete ctx;
     return SD3_OK;
 }

@@ -16,12 +16,17 @@ struct SideBufs {
     const int64_t *tile_off;  // [G+1]
     int64_t G, nv, nt, NT;
     unsigned long long *rowbox;  // [G*6] ordered bits: lo xyz (min), hi xyz (max)
-    uint64_t *keys[2];
-    int32_t *vals[2];
-    uint32_t *hist;              // radix histograms
     float *t32;                  // [NT*9*K]
     double *t64;                 // [NT*9*K]
     TileMeta *meta;              // [NT]
+};
+
+// Sort buffers shared by both sides (device).
+struct PrepBufs {
+    uint64_t *keys[2];  // [ntA + ntB] ping-pong
+    int32_t *vals[2];
+    uint32_t *hist;     // [256 * blocks]
+    uint32_t *part;     // [chunks]
 };
 
 // Counters (device, unsigned long long[16]).
@@ -62,17 +67,37 @@ enum : uint32_t { V_NONFINITE = 1, V_RANGE = 2, V_INDEX = 4 };
 void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
                      const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
                      hipStream_t s);
-void launch_prep(SideBufs &side, int key_bits, hipStream_t s);
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s);
 void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
                       const unsigned long long *boxB, hipStream_t s);
-// Q_SEED: upper bounds from vertex pairs; Q_FILTER_DIST: keep box lower bound
-// <= ub + m; Q_FILTER_HIT: keep overlapping boxes.
-enum : int { Q_SEED = 0, Q_FILTER_DIST = 1, Q_FILTER_HIT = 2 };
-void launch_queue(const SideBufs &A, const SideBufs &B, const int64_t *wi_off, int64_t n_wi,
+// Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
+struct GroupBox {
+    double lo[3], hi[3], rep[3];
+};
+
+// Queue geometry (device): work-item offsets, group offsets and boxes, and the
+// per-work-item group lower bound.
+struct QueueGeo {
+    const int64_t *wi_off;  // [G+1]
+    const int64_t *blkA;    // [G+1] A-block offsets
+    const int64_t *chkB;    // [G+1] B-chunk offsets
+    GroupBox *gA, *gB;
+    float *wi_lb;           // [n_wi]
+};
+
+void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngroups, int gs,
+                        GroupBox *out, hipStream_t s);
+
+// Q_SEED: group bounds and upper bounds from vertex pairs (distance);
+// Q_GROUPS: group bounds only (intersects); Q_FILTER_DIST: keep tile pairs with
+// box lower bound <= ub + m; Q_FILTER_HIT: keep overlapping boxes.
+enum : int { Q_SEED = 0, Q_GROUPS = 1, Q_FILTER_DIST = 2, Q_FILTER_HIT = 3 };
+void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
                   int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s);
 void launch_sort_queue(Lists &L, uint64_t *tmp_keys, int32_t *tmp_vals, uint64_t *keys2,
                        int32_t *vals2, uint32_t *hist, int2 *queue2, float *qlb2,
                        unsigned int n_max, hipStream_t s);
+int pairs_blocks_per_cu(int precision, int mode);
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
                   int mode, int grid, hipStream_t s);
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,

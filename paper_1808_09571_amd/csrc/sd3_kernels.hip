@@ -90,42 +90,75 @@ __global__ void k_rowbox_init(unsigned long long *box, int64_t G) {
     if (i < G * 6) box[i] = (i % 6) < 3 ? ~0ull : 0ull;
 }
 
-// Row bounding boxes of all vertices (ordered-bit atomics; a wave whose lanes
-// all belong to one row reduces first).
-__global__ void k_rowbox(const double *xyz, int64_t nv, const int64_t *v_off, int64_t G,
-                         unsigned long long *box) {
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nv;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        int64_t i = base + threadIdx.x;
-        bool valid = i < nv;
-        int64_t ic = valid ? i : nv - 1;
-        int64_t g = find_row(v_off, G, ic);
-        unsigned long long lo[3], hi[3];
-        for (int k = 0; k < 3; k++) {
-            unsigned long long b = ordered_bits(xyz[3 * ic + k]);
-            lo[k] = valid ? b : ~0ull;
-            hi[k] = valid ? b : 0ull;
+// Row bounding boxes of all vertices.  Each block owns a contiguous range of
+// vertices and keeps running per-thread min/max while its chunks stay inside
+// one row; it reduces over the block and issues one atomic per component only
+// when the row changes (rows are contiguous), so large rows cost a few atomics
+// per block instead of one per wave.
+__device__ void rowbox_flush(int64_t g, unsigned long long *lo, unsigned long long *hi,
+                             unsigned long long (*red)[6], unsigned long long *box) {
+    for (int k = 0; k < 3; k++) {
+        unsigned long long a = wave_min(lo[k]), b = wave_max(hi[k]);
+        if (lane_id() == 0) {
+            red[threadIdx.x >> 6][k] = a;
+            red[threadIdx.x >> 6][3 + k] = b;
         }
-        int64_t g0 = __shfl(g, 0);
-        bool uniform = __all(g == g0 || !valid);
-        if (uniform) {
-            for (int k = 0; k < 3; k++) {
-                lo[k] = wave_min(lo[k]);
-                hi[k] = wave_max(hi[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int k = threadIdx.x;
+        unsigned long long v = red[0][k];
+        for (int w = 1; w < 4; w++) v = k < 3 ? min(v, red[w][k]) : max(v, red[w][k]);
+        if (k < 3) {
+            if (v < box[g * 6 + k]) atomicMin(&box[g * 6 + k], v);
+        } else {
+            if (v > box[g * 6 + k]) atomicMax(&box[g * 6 + k], v);
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; k++) {
+        lo[k] = ~0ull;
+        hi[k] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rowbox(const double *xyz, int64_t nv, const int64_t *v_off,
+                                                int64_t G, unsigned long long *box) {
+    __shared__ unsigned long long red[4][6];
+    int64_t per = ((nv + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    int64_t b0 = blockIdx.x * per, b1 = min(nv, b0 + per);
+    unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    int64_t cur = -1;
+    for (int64_t base = b0; base < b1; base += 256) {
+        int64_t last = min(base + 255, b1 - 1);
+        int64_t g0 = find_row(v_off, G, base), g1 = find_row(v_off, G, last);
+        int64_t i = base + threadIdx.x;
+        bool valid = i <= last;
+        if (g0 == g1) {
+            if (g0 != cur) {
+                if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
+                cur = g0;
             }
-            if (lane_id() == 0) {
+            if (valid)
                 for (int k = 0; k < 3; k++) {
-                    atomicMin(&box[g0 * 6 + k], lo[k]);
-                    atomicMax(&box[g0 * 6 + 3 + k], hi[k]);
+                    unsigned long long v = ordered_bits(xyz[3 * i + k]);
+                    lo[k] = min(lo[k], v);
+                    hi[k] = max(hi[k], v);
                 }
-            }
-        } else if (valid) {
-            for (int k = 0; k < 3; k++) {
-                atomicMin(&box[g * 6 + k], lo[k]);
-                atomicMax(&box[g * 6 + 3 + k], hi[k]);
+        } else {
+            if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
+            cur = -1;
+            if (valid) {
+                int64_t g = find_row(v_off, G, i);
+                for (int k = 0; k < 3; k++) {
+                    unsigned long long v = ordered_bits(xyz[3 * i + k]);
+                    atomicMin(&box[g * 6 + k], v);
+                    atomicMax(&box[g * 6 + 3 + k], v);
+                }
             }
         }
     }
+    if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -137,10 +170,11 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-// key = row << 30 | 30-bit Morton code of the triangle centroid in the row box
+// key = side << rowbits+30 | row << 30 | 30-bit Morton code of the triangle
+// centroid in the row box; value = triangle index within its side
 __global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, const int64_t *v_off,
                          const int64_t *t_off, int64_t G, const unsigned long long *box,
-                         uint64_t *keys, int32_t *vals) {
+                         uint64_t side_key, uint64_t *keys, int32_t *vals) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
          t += (int64_t)gridDim.x * blockDim.x) {
         int64_t g = find_row(t_off, G, t);
@@ -161,7 +195,7 @@ __global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, cons
             q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
         }
         uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-        keys[t] = ((uint64_t)g << 30) | code;
+        keys[t] = side_key | ((uint64_t)g << 30) | code;
         vals[t] = (int32_t)t;
     }
 }
@@ -185,35 +219,63 @@ __global__ void k_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *his
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of `total` entries by one workgroup of 1024 threads
-__global__ void k_scan(uint32_t *a, int64_t total) {
-    __shared__ uint32_t part[1024];
-    int64_t per = (total + 1023) / 1024;
-    int64_t b0 = threadIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
-    uint32_t s = 0;
-    for (int64_t i = b0; i < b1; i++) s += a[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+// Exclusive scan of the (digit, block) histogram in chunks of 4096 entries:
+// k_scan_local scans each chunk in LDS and records the chunk total, k_scan_top
+// scans the chunk totals; the scatter adds both parts.
+constexpr int SCAN_CHUNK = 4096;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane_id() >= o) v += t;
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (int64_t i = b0; i < b1; i++) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_local(uint32_t *a, int64_t total, uint32_t *part) {
+    __shared__ uint32_t wsum[16];
+    int64_t c0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int tid = threadIdx.x;
+    uint32_t v[4], s = 0;
+    for (int k = 0; k < 4; k++) {
+        int64_t i = c0 + 4 * tid + k;
+        v[k] = i < total ? a[i] : 0u;
+        s += v[k];
+    }
+    uint32_t inc = wave_incl_scan(s);
+    if (lane_id() == 63) wsum[tid >> 6] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < (tid >> 6); w++) wbase += wsum[w];
+    uint32_t run = wbase + inc - s;
+    for (int k = 0; k < 4; k++) {
+        int64_t i = c0 + 4 * tid + k;
+        if (i < total) a[i] = run;
+        run += v[k];
+    }
+    if (tid == 1023) part[blockIdx.x] = wbase + inc;
+}
+
+__global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
+    uint32_t carry = 0;
+    for (int64_t b = 0; b < n; b += 64) {
+        int64_t i = b + lane_id();
+        uint32_t v = i < n ? part[i] : 0u;
+        uint32_t inc = wave_incl_scan(v);
+        if (i < n) part[i] = carry + inc - v;
+        carry += __shfl(inc, 63);
     }
 }
 
 __global__ void k_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout,
-                          int64_t n, int shift, const uint32_t *hist, int nblocks) {
+                          int64_t n, int shift, const uint32_t *hist, const uint32_t *part,
+                          int nblocks) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     int tid = threadIdx.x, w = tid >> 6;
-    base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+    int64_t e = (int64_t)tid * nblocks + blockIdx.x;
+    base[tid] = hist[e] + part[e / SCAN_CHUNK];
     int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
     for (int r = 0; r < RS_ITEMS / 256; r++) {
         for (int k = 0; k < 4; k++) wcnt[k][tid] = 0;
@@ -244,16 +306,19 @@ __global__ void k_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kou
 }
 
 // Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
-static int radix_sort(uint64_t **keys, int32_t **vals, uint32_t *hist, int64_t n, int bits,
-                      hipStream_t s) {
+static int radix_sort(uint64_t **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
+                      int bits, hipStream_t s) {
     int cur = 0;
     if (n <= 1) return cur;
     int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+    int64_t total = (int64_t)nb * 256;
+    int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_hist, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)nb * 256);
+        hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, nb);
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb);
         cur ^= 1;
     }
     return cur;
@@ -319,24 +384,38 @@ __global__ void k_tiles(const double *xyz, const int32_t *tri, const int64_t *v_
     }
 }
 
-void launch_prep(SideBufs &S, int key_bits, hipStream_t s) {
-    if (S.G == 0) return;
+static void rowbox(SideBufs &S, hipStream_t s) {
     hipLaunchKernelGGL(k_rowbox_init, dim3(grid_for(S.G * 6, 256)), dim3(256), 0, s, S.rowbox, S.G);
     if (S.nv > 0) {
-        unsigned g = grid_for(S.nv, 256);
-        if (g > 8192) g = 8192;
+        unsigned g = grid_for(S.nv, 2048);
+        if (g > 512) g = 512;
         hipLaunchKernelGGL(k_rowbox, dim3(g), dim3(256), 0, s, S.xyz, S.nv, S.v_off, S.G, S.rowbox);
     }
+}
+
+static void morton(SideBufs &S, uint64_t side_key, uint64_t *keys, int32_t *vals, hipStream_t s) {
     if (S.nt == 0) return;
-    {
-        unsigned g = grid_for(S.nt, 256);
-        if (g > 16384) g = 16384;
-        hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, s, S.xyz, S.tri, S.nt, S.v_off, S.t_off,
-                           S.G, S.rowbox, S.keys[0], S.vals[0]);
-    }
-    int cur = radix_sort(S.keys, S.vals, S.hist, S.nt, key_bits, s);
-    hipLaunchKernelGGL(k_tiles, dim3(grid_for(S.NT, 4)), dim3(256), 0, s, S.xyz, S.tri, S.v_off,
-                       S.t_off, S.tile_off, S.G, S.NT, S.vals[cur], S.t32, S.t64, S.meta);
+    unsigned g = grid_for(S.nt, 256);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, s, S.xyz, S.tri, S.nt, S.v_off, S.t_off, S.G,
+                       S.rowbox, side_key, keys, vals);
+}
+
+// Both sides are sorted together (the side is the top key bit), so one
+// sequence of sort launches covers 2x the items.
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s) {
+    if (A.G == 0) return;
+    rowbox(A, s);
+    rowbox(B, s);
+    morton(A, 0ull, P.keys[0], P.vals[0], s);
+    morton(B, 1ull << key_bits, P.keys[0] + A.nt, P.vals[0] + A.nt, s);
+    int cur = radix_sort(P.keys, P.vals, P.hist, P.part, A.nt + B.nt, key_bits + 1, s);
+    if (A.NT > 0)
+        hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT, 4)), dim3(256), 0, s, A.xyz, A.tri, A.v_off,
+                           A.t_off, A.tile_off, A.G, A.NT, P.vals[cur], A.t32, A.t64, A.meta);
+    if (B.NT > 0)
+        hipLaunchKernelGGL(k_tiles, dim3(grid_for(B.NT, 4)), dim3(256), 0, s, B.xyz, B.tri, B.v_off,
+                           B.t_off, B.tile_off, B.G, B.NT, P.vals[cur] + A.nt, B.t32, B.t64, B.meta);
 }
 
 // ---------------------------------------------------------------------------
@@ -406,14 +485,91 @@ __device__ __forceinline__ double box_gap2(const double *alo, const double *ahi,
     return s;
 }
 
+// Boxes of tile groups: 64 consecutive tiles of a row on the A side (one work
+// item's A block), 256 on the B side (one work item's B chunk).
+__global__ __launch_bounds__(256) void k_group_boxes(const TileMeta *meta, const int64_t *tile_off,
+                                                     const int64_t *grp_off, int64_t G, int gs,
+                                                     GroupBox *out) {
+    __shared__ double red[4][6];
+    int64_t gid = blockIdx.x;
+    int64_t g = find_row(grp_off, G, gid);
+    int64_t t0 = tile_off[g] + (gid - grp_off[g]) * gs;
+    int64_t t1 = min(t0 + gs, tile_off[g + 1]);
+    int64_t t = t0 + threadIdx.x;
+    bool valid = threadIdx.x < gs && t < t1;
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; k++) {
+        lo[k] = valid ? meta[t].lo[k] : __builtin_inf();
+        hi[k] = valid ? meta[t].hi[k] : -__builtin_inf();
+        lo[k] = wave_min(lo[k]);
+        hi[k] = wave_max(hi[k]);
+    }
+    if (lane_id() == 0)
+        for (int k = 0; k < 3; k++) {
+            red[threadIdx.x >> 6][k] = lo[k];
+            red[threadIdx.x >> 6][3 + k] = hi[k];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GroupBox b;
+        for (int k = 0; k < 3; k++) {
+            b.lo[k] = fmin(fmin(red[0][k], red[1][k]), fmin(red[2][k], red[3][k]));
+            b.hi[k] = fmax(fmax(red[0][3 + k], red[1][3 + k]), fmax(red[2][3 + k], red[3][3 + k]));
+            b.rep[k] = meta[t0].rep[k];
+        }
+        out[gid] = b;
+    }
+}
+
+void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngroups, int gs,
+                        GroupBox *out, hipStream_t s) {
+    if (ngroups > 0)
+        hipLaunchKernelGGL(k_group_boxes, dim3((unsigned)ngroups), dim3(256), 0, s, S.meta,
+                           S.tile_off, grp_off, S.G, gs, out);
+}
+
+// Per work item: box lower bound of its (A block, B chunk) pair, kept for the
+// tile-level kernels, and the distance between two real vertices (an upper
+// bound of the row distance).
+__global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t *blkA,
+                          const int64_t *chkB, const int64_t *tA, const int64_t *tB,
+                          const int64_t *wi_off, int64_t G, int64_t n_wi, RowState *rows,
+                          float *wi_lb, int update_ub) {
+    int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (wi >= n_wi) return;
+    int64_t g = find_row(wi_off, G, wi);
+    int64_t local = wi - wi_off[g];
+    int64_t nB = tB[g + 1] - tB[g];
+    int64_t nbc = (nB + 255) / 256;
+    const GroupBox &a = gA[blkA[g] + local / nbc];
+    const GroupBox &b = gB[chkB[g] + local % nbc];
+    double g2 = box_gap2(a.lo, a.hi, b.lo, b.hi);
+    wi_lb[wi] = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
+    if (update_ub) {
+        double dx = a.rep[0] - b.rep[0], dy = a.rep[1] - b.rep[1], dz = a.rep[2] - b.rep[2];
+        double u = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 8.0 * U64);
+        if (u < bits_to_double(load_acq(&rows[g].ub))) atomic_min_pos(&rows[g].ub, u);
+    }
+}
+
+// true when the whole work item can be skipped (uniform per workgroup)
+__device__ __forceinline__ bool wi_pruned(const float *wi_lb, int64_t wi, const RowState &R,
+                                          int mode) {
+    double lb = (double)wi_lb[wi];
+    if (mode == 1) return lb > 0.0;
+    double ub = bits_to_double(load_acq(&R.ub));
+    return lb > ub + row_margin(R, ub);
+}
+
 // Upper bound seed: the distance between two real vertices bounds the row
 // distance from above.
 __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileMeta *mB,
                                                  const int64_t *tA, const int64_t *tB,
                                                  const int64_t *wi_off, int64_t G, int64_t wi0,
-                                                 RowState *rows) {
+                                                 RowState *rows, const float *wi_lb) {
     __shared__ double rep[64][3];
     WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
+    if (wi_pruned(wi_lb, wi0 + blockIdx.x, rows[w.g], 0)) return;
     if (threadIdx.x < w.na)
         for (int k = 0; k < 3; k++) rep[threadIdx.x][k] = mA[w.a0 + threadIdx.x].rep[k];
     __syncthreads();
@@ -426,9 +582,17 @@ __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileM
             best = fmin(best, dx * dx + dy * dy + dz * dz);
         }
     }
+    __shared__ double wred[4];
     best = wave_min(best);
-    if (lane_id() == 0 && best < __builtin_inf())
-        atomic_min_pos(&rows[w.g].ub, sqrt(best) * (1.0 + 8.0 * U64));
+    if (lane_id() == 0) wred[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        best = fmin(fmin(wred[0], wred[1]), fmin(wred[2], wred[3]));
+        if (best < __builtin_inf()) {
+            double u = sqrt(best) * (1.0 + 8.0 * U64);
+            if (u < bits_to_double(load_acq(&rows[w.g].ub))) atomic_min_pos(&rows[w.g].ub, u);
+        }
+    }
 }
 
 // Keep the tile pairs that may hold the minimum (distance: box lower bound
@@ -438,9 +602,10 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
                                                 const int64_t *wi_off, int64_t G, int64_t wi0,
                                                 const RowState *rows, int mode, int2 *queue,
                                                 float *qlb, unsigned int *qcount,
-                                                unsigned int qcap) {
+                                                unsigned int qcap, const float *wi_lb) {
     __shared__ double box[64][6];
     WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
+    if (wi_pruned(wi_lb, wi0 + blockIdx.x, rows[w.g], mode)) return;
     if (threadIdx.x < w.na)
         for (int k = 0; k < 3; k++) {
             box[threadIdx.x][k] = mA[w.a0 + threadIdx.x].lo[k];
@@ -455,6 +620,9 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
     const RowState &R = rows[w.g];
     double ub = bits_to_double(R.ub);
     double lim = ub + row_margin(R, ub);
+    // keep iff sqrt(g2) (1 - 8u) <= lim; compared squared with slack, the square
+    // root is taken only for kept pairs
+    double lim2 = lim * lim * (1.0 + 32.0 * U64);
     bool hit = R.hit != 0;
     for (int a = 0; a < w.na; a++) {
         bool keep = false;
@@ -462,9 +630,8 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
         if (w.bvalid && !hit) {
             double g2 = box_gap2(box[a], box[a] + 3, blo, bhi);
             if (mode == 0) {
-                double lb = sqrt(g2) * (1.0 - 8.0 * U64);
-                keep = lb <= lim;
-                lbf = (float)(lb * (1.0 - 0x1p-20));
+                keep = g2 <= lim2;
+                if (keep) lbf = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
             } else {
                 keep = g2 == 0.0 && box[a][0] <= bhi[0] && blo[0] <= box[a][3] &&
                        box[a][1] <= bhi[1] && blo[1] <= box[a][4] && box[a][2] <= bhi[2] &&
@@ -486,16 +653,21 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
     }
 }
 
-void launch_queue(const SideBufs &A, const SideBufs &B, const int64_t *wi_off, int64_t n_wi,
+void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
                   int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s) {
     if (n_wi <= 0) return;
-    if (what == Q_SEED)
-        hipLaunchKernelGGL(k_ub_seed, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
-                           A.tile_off, B.tile_off, wi_off, A.G, wi_begin, rows);
-    else
-        hipLaunchKernelGGL(k_filter, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
-                           A.tile_off, B.tile_off, wi_off, A.G, wi_begin, rows,
-                           what == Q_FILTER_DIST ? 0 : 1, L.queue, L.qlb, L.qcount, L.qcap);
+    if (what == Q_SEED || what == Q_GROUPS) {
+        hipLaunchKernelGGL(k_wi_seed, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.gA, Q.gB, Q.blkA,
+                           Q.chkB, A.tile_off, B.tile_off, Q.wi_off, A.G, n_wi, rows, Q.wi_lb,
+                           what == Q_SEED ? 1 : 0);
+        if (what == Q_SEED)
+            hipLaunchKernelGGL(k_ub_seed, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
+                               A.tile_off, B.tile_off, Q.wi_off, A.G, wi_begin, rows, Q.wi_lb);
+        return;
+    }
+    hipLaunchKernelGGL(k_filter, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                       B.tile_off, Q.wi_off, A.G, wi_begin, rows, what == Q_FILTER_DIST ? 0 : 1,
+                       L.queue, L.qlb, L.qcount, L.qcap, Q.wi_lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,7 +679,7 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const int64_t *wi_off, i
 // the upper / lower bounds; eo bounds the error of FP32 orientation values.
 struct TP32 {
     float sh[3];
-    float eu, elb, eo, box_tol;
+    float eu, elb, eps_f, box_tol;
     double eps_c;
 };
 
@@ -528,7 +700,7 @@ __device__ __forceinline__ TP32 tp32_consts(const TileMeta &a, const TileMeta &b
     c.eps_c = eps_c;
     c.eu = (float)((8.0 * SQRT3 * U32 * Mw + eps_c) * (1.0 + 1e-5));
     c.elb = (float)((16.0 * SQRT3 * U32 * Mr + eps_c) * (1.0 + 1e-5));
-    c.eo = (float)((24.0 * eps_c * Mw * Mw + 64.0 * U32 * Mw * Mw * Mw) * (1.0 + 1e-5));
+    c.eps_f = (float)(eps_c * (1.0 + 1e-5));
     c.box_tol = (float)((eps_c + 4.0 * U32 * Mr) * (1.0 + 1e-5));
     return c;
 }
@@ -547,8 +719,8 @@ struct TPShared {
 // Thread 0 dequeues the next tile pair and computes its constants.
 __device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned qcount,
                                            const TileMeta *mA, const TileMeta *mB,
-                                           RowState *rows, int precision, int mode) {
-    unsigned q = atomicAdd(L.qhead, 1u);
+                                           RowState *rows, int precision, int mode, bool first) {
+    unsigned q = first ? (unsigned)blockIdx.x : gridDim.x + atomicAdd(L.qhead, 1u);
     S.q = (int)q;
     S.live = 0;
     S.cnt = 0;
@@ -643,8 +815,11 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned qcount = min(*L.qcount, L.qcap);
     unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0;
-    for (;;) {
-        if (tid == 0) tp_dequeue(S, L, qcount, mA, mB, rows, PREC, MODE);
+    // first entry: blockIdx.x (no atomic); later entries from the shared head,
+    // which starts at gridDim.x
+    if ((unsigned)blockIdx.x >= qcount) return;
+    for (bool first = true;; first = false) {
+        if (tid == 0) tp_dequeue(S, L, qcount, mA, mB, rows, PREC, MODE, first);
         __syncthreads();
         if ((unsigned)S.q >= qcount) break;
         if (S.live) {
@@ -706,7 +881,11 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                         global_push(resc, it, L.rescue, L.rcount, L.rcap);
                         n_resc += resc;
                     } else {
-                        int c = isect32(TA, TB, S.c.eo);
+                        int c = isect32(TA, TB, S.c.eps_f);
+                        // not settled by planes and crossings: a certified
+                        // separating plane along the closest direction still
+                        // proves the pair disjoint
+                        if (c == 2 && pair32(TA, TB, S.c.elb).lb > 0.0f) c = 0;
                         if (c == 1) atomicOr(&rows[S.g].hit, 1u);
                         Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0.0f};
                         global_push(c == 2, it, L.rescue, L.rcount, L.rcap);
@@ -714,23 +893,13 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                     }
                 } else {
                     TriRef<double> TA{(double *)sA + a, K}, TB{(double *)sB + b, K};
-                    int st;
-                    double d2 = 0.0;
-                    if (MODE == 0) {
-                        Pair64 r = pair64(TA, TB);
-                        st = r.status;
-                        d2 = r.d2;
-                        tmin = fmin(tmin, (Tt)r.d2);
-                    } else {
-                        double va[9], vb[9];
-#pragma unroll
-                        for (int i = 0; i < 9; i++) {
-                            va[i] = TA[F_V + i];
-                            vb[i] = TB[F_V + i];
-                        }
-                        int f = tri_tri_filtered64(va, vb);
-                        st = f == 1 ? 1 : (f == 0 ? 0 : 2);
-                    }
+                    // distance and intersects both use the full FP64 pair
+                    // test: its separating-plane certificate settles the
+                    // disjoint pairs whose orientation signs are exact zeros
+                    Pair64 r = pair64(TA, TB);
+                    int st = r.status;
+                    double d2 = r.d2;
+                    if (MODE == 0) tmin = fmin(tmin, (Tt)r.d2);
                     if (st == 1) atomicOr(&rows[S.g].hit, 1u);
                     ExactItem it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0, d2};
                     global_push(st == 2, it, L.exact, L.xcount, L.xcap);
@@ -775,6 +944,17 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
         if (n_resc) atomicAdd(&L.counters[C_RESCUED], n_resc);
         if (n_exact) atomicAdd(&L.counters[C_EXACT], n_exact);
     }
+}
+
+int pairs_blocks_per_cu(int precision, int mode) {
+    int n = 0;
+    hipError_t e;
+    if (precision == 0 && mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<0, 0>, WG, 0);
+    else if (precision == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<0, 1>, WG, 0);
+    else if (mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<1, 0>, WG, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<1, 1>, WG, 0);
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
 }
 
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
@@ -831,10 +1011,12 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
                 }
             }
         } else {
-            double va[9], vb[9];
-            load_tri64(t64A, e.ta, a, va);
-            load_tri64(t64B, e.tb, b, vb);
-            int f = tri_tri_filtered64(va, vb);
+            double ta[F_NTRI64], tb[F_NTRI64];
+            load_tri64(t64A, e.ta, a, ta);
+            load_tri64(t64B, e.tb, b, tb);
+            tri_prep64(TriRef<double>{ta, 1});
+            tri_prep64(TriRef<double>{tb, 1});
+            int f = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1}).status;
             n64++;
             if (f == 1) atomicOr(&R->hit, 1u);
             else if (f == 2) {

@@ -146,8 +146,21 @@ __device__ __forceinline__ float orient3d_f32(float ax, float ay, float az, floa
 // 0 = certainly disjoint (one triangle strictly on one side of the other's
 // plane by more than eo), 1 = certainly meeting (an edge strictly crosses the
 // other triangle's plane and the line strictly passes inside all three edges,
-// Eq. 4 with margins), 2 = not settled (rescued to FP64 / exact).
-__device__ __forceinline__ int isect32(TriRef<float> A, TriRef<float> B, float eo) {
+// Eq. 4 with margins), 2 = not settled.
+// eo bounds the error of every orientation value of the pair: all points lie
+// in the pair's bounding box of extent Ms, so each of the 6 elementary triple
+// products is at most Ms^3 and passes through at most 8 FP32 roundings
+// (48 u Ms^3 < 64 u Ms^3), and moving the 4 points by at most eps each moves
+// the determinant by at most 18 eps Ms^2 + O(eps^2 Ms).
+__device__ __forceinline__ int isect32(TriRef<float> A, TriRef<float> B, float eps_c) {
+    float ms = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        ms = fmaxf(ms, fmaxf(A[F_HI + k], B[F_HI + k]) - fminf(A[F_LO + k], B[F_LO + k]));
+    ms *= 1.0f + 0x1p-20f;
+    const float eo = (24.0f * eps_c * ms * ms + 24.0f * eps_c * eps_c * ms +
+                      8.0f * eps_c * eps_c * eps_c + 64.0f * 0x1p-24f * ms * ms * ms) *
+                     (1.0f + 0x1p-16f);
     float o[2][3];
 #pragma unroll
     for (int side = 0; side < 2; side++) {

@@ -37,7 +37,7 @@ class Geoms(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -45,10 +45,14 @@ class Stats(ctypes.Structure):
                 ("tile_pairs_evaluated", ctypes.c_int64), ("tri_pairs_boxed", ctypes.c_int64),
                 ("tri_pairs_fp32", ctypes.c_int64), ("tri_pairs_fp64", ctypes.c_int64),
                 ("rescued", ctypes.c_int64), ("exact", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("reserved", ctypes.c_int64 * 7)]
+                ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7)]
+
+    PHASES = ("upload", "prep", "queue", "pairs", "rescue", "exact", "finalize")
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}
+        d["ms_phase"] = dict(zip(self.PHASES, list(self.ms_phase)))
+        return d
 
 
 class SD3Error(RuntimeError):
@@ -163,10 +167,11 @@ class Context:
         raise SD3Error(st, self.lib.sd3_last_error(self.handle).decode())
 
     @staticmethod
-    def _opts(precision, order):
+    def _opts(precision, order, timing=False):
         o = Opts()
         o.precision = PREC[precision]
         o.order = ORDER[order]
+        o.timing = 1 if timing else 0
         return o
 
     def _stream(self, a: Batch):
@@ -186,24 +191,26 @@ class Context:
         h = np.empty(G, dtype=np.uint8)
         return d, h, (d.ctypes.data if want_dist else None), h.ctypes.data
 
-    def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False):
+    def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
+                 timing=False):
         """Row-wise 3D distance (and the exact intersects flag as a by-product)."""
         ga, gb = a.geoms(), b.geoms()
         d, h, dp, hp = self._outputs(a, True)
         s = Stats()
-        o = self._opts(precision, order)
+        o = self._opts(precision, order, timing)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
             self._raise(st)
         return (d, h, s.as_dict()) if stats else (d, h)
 
-    def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False):
+    def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
+                   timing=False):
         """Row-wise exact 3D intersects."""
         ga, gb = a.geoms(), b.geoms()
         _, h, _, hp = self._outputs(a, False)
         s = Stats()
-        o = self._opts(precision, order)
+        o = self._opts(precision, order, timing)
         st = self.lib.sd3_intersects(self.handle, ctypes.byref(ga), ctypes.byref(gb), hp,
                                      ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
