@@ -80,16 +80,34 @@ typedef struct sd3_geoms {
 #define SD3_PREC_FP32_RESCUE 0 /* FP32 with error bounds + FP64 rescue (default) */
 #define SD3_PREC_FP64 1        /* plain FP64 for every tested pair */
 
-/* Order in which candidate tile pairs are visited (results never depend on it). */
-#define SD3_ORDER_BOUND 0 /* increasing bounding-box lower bound (default) */
-#define SD3_ORDER_NONE 1  /* generation order */
+/*
+ * Seed round of sd3_distance (results never depend on it): before the main
+ * pass, each row's best-ranked candidate tile pair is evaluated, so that its
+ * distance tightens the upper bound used to prune the others.
+ */
+#define SD3_ORDER_BOUND 0   /* rank by bounding-box lower bound (default) */
+#define SD3_ORDER_NONE 1    /* no seed round */
+#define SD3_ORDER_LEARNED 2 /* rank by the tile-pair ranker MLP (opts.ranker) */
+
+/* Tile-pair ranker MLP: 10 -> 64 -> 64 -> 64 -> 1, ReLU, FP32, parameters
+ * packed as W1[64][10] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] w4[64] b4. */
+#define SD3_MLP_NIN 10
+#define SD3_MLP_NHID 64
+#define SD3_MLP_NPARAM 9089
+/* One training-log record: 10 features, target, row (int32 bits). */
+#define SD3_LOG_STRIDE 12
 
 typedef struct sd3_opts {
-    int32_t precision; /* SD3_PREC_* */
-    int32_t order;     /* SD3_ORDER_* */
-    int32_t timing;    /* nonzero: record HIP events around each phase on the
-                          call's stream and report their durations in stats */
-    int32_t reserved[5];
+    int32_t precision;   /* SD3_PREC_* */
+    int32_t order;       /* SD3_ORDER_* */
+    int32_t timing;      /* nonzero: record HIP events around each phase on the
+                            call's stream and report their durations in stats */
+    int32_t reserved0;
+    const float *ranker; /* device, SD3_MLP_NPARAM floats (SD3_ORDER_LEARNED) */
+    float *log;          /* device or NULL: one record per tile pair dequeued by
+                            sd3_distance, SD3_LOG_STRIDE floats each */
+    int64_t log_cap;     /* records `log` can hold; extra records are dropped */
+    int64_t reserved[4];
 } sd3_opts;
 
 /* Work counters of the last call (all tile and triangle counts summed over rows). */
@@ -108,6 +126,8 @@ typedef struct sd3_stats {
        [3] triangle-pair pass, [4] FP64 rescue, [5] exact arithmetic,
        [6] final reduction and download */
     double ms_phase[7];
+    int64_t logged;                /* training-log records produced (may exceed log_cap) */
+    int64_t reserved[3];
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;
@@ -143,6 +163,27 @@ sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, do
  */
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
                           const sd3_opts *opts, sd3_stats *stats, void *stream);
+
+/*
+ * Training of the tile-pair ranker (SD3_ORDER_LEARNED) by the library's own
+ * kernels.  All arrays are device memory; calls are asynchronous on `stream`
+ * (a hipStream_t, NULL: default stream).
+ *   x    : [n][SD3_MLP_NIN] features (as logged by sd3_distance)
+ *   t, y : [n] targets / outputs
+ *   params, grad, m, v : [SD3_MLP_NPARAM] (packed layout above)
+ * sd3_mlp_forward:   y = MLP(x).
+ * sd3_mlp_loss_grad: *loss = mean((MLP(x) - t)^2) (one device float) and its
+ *                    gradient with respect to params (grad is overwritten).
+ * sd3_adam_step:     one Adam update (bias-corrected, step >= 1) of `count`
+ *                    parameters p with gradient g and moments m, v.
+ * Errors: SD3_E_INVALID_ARG for NULL pointers, n < 0, step < 1; SD3_E_NOMEM.
+ */
+sd3_status sd3_mlp_forward(sd3_ctx *ctx, const float *params, const float *x, int64_t n, float *y,
+                           void *stream);
+sd3_status sd3_mlp_loss_grad(sd3_ctx *ctx, const float *params, const float *x, const float *t,
+                             int64_t n, float *loss, float *grad, void *stream);
+sd3_status sd3_adam_step(sd3_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t count,
+                         int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Host-side validation of a batch whose xyz/tri are host memory (the checks
  * the two operators run before any launch); needs no device. */

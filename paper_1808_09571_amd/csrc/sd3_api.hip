@@ -1,5 +1,6 @@
 // sd3 C-ABI: argument checks, device buffers and the pipeline of one call.
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -9,6 +10,7 @@
 
 #include "../../include/sd3.h"
 #include "sd3_kernels.h"
+#include "sd3_mlp.h"
 
 using namespace sd3;
 
@@ -39,7 +41,8 @@ struct sd3_ctx {
     std::string err;
     SideState side[2];
     DevBuf rows, wi_off, queue, qlb, rescue, exact, counters, scalars, flags, out_d, out_h;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb;
+    DevBuf mlp;  // ranker training scratch
     void *pin = nullptr;  // pinned host staging: offsets up, counters down
     size_t pin_cap = 0;
     int pairs_grid[2][2] = {{0, 0}, {0, 0}};
@@ -272,8 +275,13 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
     if (opts_in) opts = *opts_in;
     if (opts.precision != SD3_PREC_FP32_RESCUE && opts.precision != SD3_PREC_FP64)
         return fail(ctx, SD3_E_INVALID_ARG, "unknown precision");
-    if (opts.order != SD3_ORDER_BOUND && opts.order != SD3_ORDER_NONE)
+    if (opts.order != SD3_ORDER_BOUND && opts.order != SD3_ORDER_NONE &&
+        opts.order != SD3_ORDER_LEARNED)
         return fail(ctx, SD3_E_INVALID_ARG, "unknown order");
+    if (opts.order == SD3_ORDER_LEARNED && !opts.ranker)
+        return fail(ctx, SD3_E_INVALID_ARG, "SD3_ORDER_LEARNED needs opts.ranker");
+    if (opts.log && (opts.log_cap < 0 || a->mem != SD3_MEM_DEVICE))
+        return fail(ctx, SD3_E_INVALID_ARG, "log needs a device buffer and log_cap >= 0");
     if (a->mem == SD3_MEM_HOST) {
         st = check_host_data(a, msg);
         if (st == SD3_OK) st = check_host_data(b, msg);
@@ -368,6 +376,10 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         L.rhead = sc + 3;
         L.xcount = sc + 4;
         L.counters = (unsigned long long *)(sc + 16);
+        L.seed_pass = 0;
+        L.log = mode == 0 ? opts.log : nullptr;
+        L.log_cap = (unsigned long long)opts.log_cap;
+        L.log_count = L.counters + C_LOGGED;
         launch_reset_lists(L, s);
         clk.mark(2);
         const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
@@ -381,10 +393,28 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
                                                         : std::max<int64_t>(1, qcap / (64 * 256));
         launch_queue(A, B, Q, n_wi, 0, rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
         std::vector<unsigned long long> cand_total(1, 0);
+        if (mode == 0) launch_row_scale(rows, G, s);
+        // seed round: single queue pass, distance only
+        const bool seed = mode == 0 && opts.order != SD3_ORDER_NONE && n_wi <= per_pass;
         for (int64_t w0 = 0; w0 < n_wi; w0 += per_pass) {
             int64_t nw = std::min(per_pass, n_wi - w0);
             if (w0 > 0) launch_reset_queue(L, s);
             launch_queue(A, B, Q, nw, w0, rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
+            if (seed) {
+                int2 *sq = (int2 *)ensure(ctx->seedq, sizeof(int2) * (G + 1));
+                float *sl = (float *)ensure(ctx->seedlb, sizeof(float) * (G + 1));
+                launch_rank(A, B, rows, L, opts.order == SD3_ORDER_LEARNED ? opts.ranker : nullptr,
+                            ctx->cus * 2, s);
+                Lists LS = L;
+                LS.queue = sq;
+                LS.qlb = sl;
+                LS.qcount = sc + 6;
+                LS.qhead = sc + 7;
+                LS.qcap = (unsigned int)(G > 0 ? G : 1);
+                LS.seed_pass = 1;
+                launch_seed_build(rows, G, L, sq, sl, LS.qcount, s);
+                launch_pairs(A, B, rows, LS, prec, mode, grid_pairs, s);
+            }
             if (w0 == 0) clk.mark(3);
             launch_pairs(A, B, rows, L, prec, mode, grid_pairs, s);
             if (n_wi > per_pass) {
@@ -434,6 +464,17 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         }
         clk.mark(7);
         check(hipStreamSynchronize(s), "sync");
+        if (getenv("SD3_DEBUG_ROWS") && G > 0) {
+            std::vector<RowState> rh(std::min<int64_t>(G, 4));
+            check(hipMemcpy(rh.data(), rows, sizeof(RowState) * rh.size(), hipMemcpyDeviceToHost), "D2H rows");
+            for (size_t g = 0; g < rh.size(); g++) {
+                double ub, d2;
+                memcpy(&ub, &rh[g].ub, 8);
+                memcpy(&d2, &rh[g].d2, 8);
+                fprintf(stderr, "sd3 row %zu: ub %.17g d2 %.17g hit %u seed_q %d margin %.3g scale %.17g\n", g,
+                        ub, d2, rh[g].hit, rh[g].seed_q, rh[g].margin_scale, rh[g].scale);
+            }
+        }
         if (stats) {
             memset(stats, 0, sizeof(*stats));
             stats->tile_pairs_total = P.potential;
@@ -444,6 +485,7 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             stats->tri_pairs_fp64 = (int64_t)cnt_h[C_TRI64];
             stats->rescued = (int64_t)cnt_h[C_RESCUED];
             stats->exact = (int64_t)cnt_h[C_EXACT];
+            stats->logged = (int64_t)cnt_h[C_LOGGED];
             stats->ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             clk.read(stats->ms_phase);
@@ -454,6 +496,41 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const std::bad_alloc &) {
         return fail(ctx, SD3_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, SD3_E_DEVICE, "unexpected error");
+    }
+    return SD3_OK;
+}
+
+}  // namespace
+
+namespace {
+
+MlpScratch mlp_scratch(sd3_ctx *ctx, int64_t n) {
+    int64_t m = n > 0 ? n : 1;
+    float *b = (float *)ensure(ctx->mlp, sizeof(float) * (6 * MLP_H + 2) * m);
+    MlpScratch s;
+    s.h1 = b;
+    s.h2 = b + MLP_H * m;
+    s.h3 = b + 2 * MLP_H * m;
+    s.d1 = b + 3 * MLP_H * m;
+    s.d2 = b + 4 * MLP_H * m;
+    s.d3 = b + 5 * MLP_H * m;
+    s.y = b + 6 * MLP_H * m;
+    s.dy = s.y + m;
+    return s;
+}
+
+template <typename F>
+sd3_status guarded(sd3_ctx *ctx, F f) {
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        f();
+        check(hipGetLastError(), "kernel launch");
+    } catch (const HipError &e) {
+        (void)hipGetLastError();
+        if (e.e == hipErrorOutOfMemory) return fail(ctx, SD3_E_NOMEM, "out of device memory");
+        return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (...) {
         return fail(ctx, SD3_E_DEVICE, "unexpected error");
     }
@@ -502,7 +579,7 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
     DevBuf *bs[] = {&ctx->rows, &ctx->wi_off, &ctx->queue, &ctx->qlb, &ctx->rescue, &ctx->exact,
                     &ctx->counters, &ctx->scalars, &ctx->flags, &ctx->out_d, &ctx->out_h,
                     &ctx->keys0, &ctx->keys1, &ctx->vals0, &ctx->vals1, &ctx->hist, &ctx->part,
-                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb};
+                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb, &ctx->seedq, &ctx->seedlb, &ctx->mlp};
     for (DevBuf *b : bs) release(*b);
     for (hipEvent_t &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -520,6 +597,35 @@ sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, do
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
                           const sd3_opts *opts, sd3_stats *stats, void *stream) {
     return run(ctx, a, b, nullptr, hit, opts, stats, stream, 1);
+}
+
+sd3_status sd3_mlp_forward(sd3_ctx *ctx, const float *params, const float *x, int64_t n, float *y,
+                           void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    if (!params || n < 0 || (n > 0 && (!x || !y))) return fail(ctx, SD3_E_INVALID_ARG, "bad MLP arguments");
+    return guarded(ctx, [&] {
+        MlpScratch s = mlp_scratch(ctx, n);
+        mlp_forward(params, x, n, s, y, (hipStream_t)stream);
+    });
+}
+
+sd3_status sd3_mlp_loss_grad(sd3_ctx *ctx, const float *params, const float *x, const float *t,
+                             int64_t n, float *loss, float *grad, void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    if (!params || !loss || !grad || n < 0 || (n > 0 && (!x || !t)))
+        return fail(ctx, SD3_E_INVALID_ARG, "bad MLP arguments");
+    return guarded(ctx, [&] {
+        MlpScratch s = mlp_scratch(ctx, n);
+        mlp_loss_grad(params, x, t, n, s, loss, grad, (hipStream_t)stream);
+    });
+}
+
+sd3_status sd3_adam_step(sd3_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t count,
+                         int32_t step, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    if (!p || !g || !m || !v || count < 0 || step < 1)
+        return fail(ctx, SD3_E_INVALID_ARG, "bad Adam arguments");
+    return guarded(ctx, [&] { adam_step(p, g, m, v, count, step, lr, beta1, beta2, eps, (hipStream_t)stream); });
 }
 
 sd3_status sd3_validate(const sd3_geoms *g) {

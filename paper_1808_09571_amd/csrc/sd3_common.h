@@ -45,12 +45,29 @@ struct ExactItem {
 // Row state (one per geometry pair).  Non-negative doubles compare like their
 // bit patterns, so unsigned 64-bit atomicMin is a floating-point min.
 struct RowState {
-    unsigned long long ub;   // upper bound of the row distance (double bits)
-    unsigned long long d2;   // min FP64 squared distance found (double bits)
-    uint32_t hit;            // 1 once an intersecting pair is certified
-    uint32_t pad;
-    double margin_scale;     // 2^-36 * (row extent); margin m(ub) = scale + 2^-36 ub
+    unsigned long long ub;    // upper bound of the row distance (double bits)
+    unsigned long long d2;    // min FP64 squared distance found (double bits)
+    uint32_t hit;             // 1 once an intersecting pair is certified
+    int32_t seed_q;           // queue index evaluated in the seed round, -1 if none
+    double margin_scale;      // 2^-36 * (row extent); margin m(ub) = scale + 2^-36 ub
+    unsigned long long best;  // seed choice: ordered score bits << 32 | queue index
+    double scale;             // feature length scale (upper bound after seeding)
 };
+
+// Tile-pair ranker: a 10 -> 64 -> 64 -> 64 -> 1 ReLU MLP in FP32, parameters packed
+// as W1[64][10] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] w4[64] b4.
+constexpr int MLP_IN = 10;
+constexpr int MLP_H = 64;
+constexpr int MLP_W1 = 0;
+constexpr int MLP_B1 = MLP_W1 + MLP_H * MLP_IN;
+constexpr int MLP_W2 = MLP_B1 + MLP_H;
+constexpr int MLP_B2 = MLP_W2 + MLP_H * MLP_H;
+constexpr int MLP_W3 = MLP_B2 + MLP_H;
+constexpr int MLP_B3 = MLP_W3 + MLP_H * MLP_H;
+constexpr int MLP_W4 = MLP_B3 + MLP_H;
+constexpr int MLP_B4 = MLP_W4 + MLP_H;
+constexpr int MLP_NPARAM = MLP_B4 + 1;  // 9089
+constexpr int LOG_STRIDE = 12;           // features[10], target, row
 
 __device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 __device__ __forceinline__ unsigned long long double_to_bits(double d) { return (unsigned long long)__double_as_longlong(d); }

@@ -41,6 +41,7 @@ enum Counter : int {
     C_QUEUE_OVF = 7,
     C_RESCUE_OVF = 8,
     C_EXACT_OVF = 9,
+    C_LOGGED = 10,
     C_NCOUNTERS = 16,
 };
 
@@ -59,6 +60,10 @@ struct Lists {
     unsigned int *xcount;
     unsigned int xcap;
     unsigned long long *counters;  // [C_NCOUNTERS]
+    int seed_pass;                 // 1 while the queue is the per-row seed list
+    float *log;                    // training log (device) or nullptr
+    unsigned long long log_cap;
+    unsigned long long *log_count;
 };
 
 // Validation flags.
@@ -104,6 +109,14 @@ void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &
                    int grid, hipStream_t s);
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                   int grid, hipStream_t s);
+// Seed round: k_rank scores every queued tile pair (box lower bound, or the
+// ranker MLP when `ranker` is given) and keeps the best per row; the seeds are
+// copied to `seedq` and evaluated before the main pass.
+void launch_row_scale(RowState *rows, int64_t G, hipStream_t s);
+void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
+                 const float *ranker, int grid, hipStream_t s);
+void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
+                       unsigned int *seedcount, hipStream_t s);
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, hipStream_t s);
 void launch_reset_lists(Lists &L, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);

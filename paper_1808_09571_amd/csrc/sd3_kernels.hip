@@ -429,7 +429,9 @@ __global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long 
     r.ub = double_to_bits(__builtin_inf());
     r.d2 = double_to_bits(__builtin_inf());
     r.hit = 0;
-    r.pad = 0;
+    r.seed_q = -1;
+    r.best = ~0ull;
+    r.scale = 0.0;
     double ext2 = 0.0;
     bool ok = boxA[g * 6] != ~0ull && boxB[g * 6] != ~0ull;
     if (ok) {
@@ -552,13 +554,23 @@ __global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t 
     }
 }
 
-// true when the whole work item can be skipped (uniform per workgroup)
+// True when the whole work item can be skipped.  The row bound is read by
+// thread 0 only and broadcast through LDS: other workgroups lower it
+// concurrently, and every thread of the block must take the same branch.
 __device__ __forceinline__ bool wi_pruned(const float *wi_lb, int64_t wi, const RowState &R,
                                           int mode) {
-    double lb = (double)wi_lb[wi];
-    if (mode == 1) return lb > 0.0;
-    double ub = bits_to_double(load_acq(&R.ub));
-    return lb > ub + row_margin(R, ub);
+    __shared__ int flag;
+    if (threadIdx.x == 0) {
+        double lb = (double)wi_lb[wi];
+        if (mode == 1) {
+            flag = lb > 0.0;
+        } else {
+            double ub = bits_to_double(load_acq(&R.ub));
+            flag = lb > ub + row_margin(R, ub);
+        }
+    }
+    __syncthreads();
+    return flag != 0;
 }
 
 // Upper bound seed: the distance between two real vertices bounds the row
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
         bhi[k] = mB[w.b].hi[k];
     }
     const RowState &R = rows[w.g];
-    double ub = bits_to_double(R.ub);
+    double ub = bits_to_double(R.ub);  // final after the seed kernels (previous launch)
     double lim = ub + row_margin(R, ub);
     // keep iff sqrt(g2) (1 - 8u) <= lim; compared squared with slack, the square
     // root is taken only for kept pairs
@@ -705,8 +717,48 @@ __device__ __forceinline__ TP32 tp32_consts(const TileMeta &a, const TileMeta &b
     return c;
 }
 
+// Ranker features of a tile pair, length-normalised by the row scale (the
+// vertex-pair upper bound after seeding) and compressed with log2(1 + x):
+// box lower bound, the two tiles' box extents, box-centre distance, and the
+// two real triangle counts.
+__device__ __forceinline__ void tp_features(const TileMeta &a, const TileMeta &b, double scale,
+                                            float lbf, float *f) {
+    double s = scale > 0.0 ? 1.0 / scale : 1.0;
+    double c2 = 0.0;
+    f[0] = log2f(1.0f + (float)(lbf * s));
+    for (int k = 0; k < 3; k++) {
+        f[1 + k] = log2f(1.0f + (float)((a.hi[k] - a.lo[k]) * s));
+        f[4 + k] = log2f(1.0f + (float)((b.hi[k] - b.lo[k]) * s));
+        double d = 0.5 * (a.lo[k] + a.hi[k]) - 0.5 * (b.lo[k] + b.hi[k]);
+        c2 += d * d;
+    }
+    f[7] = log2f(1.0f + (float)(sqrt(c2) * s));
+    f[8] = (float)a.n * (1.0f / K);
+    f[9] = (float)b.n * (1.0f / K);
+}
+
+// Training target: log2 of the tile pair's smallest candidate distance (or a
+// lower bound of it when no triangle pair was tested), in row-scale units.
+__device__ __forceinline__ float tp_target(double outcome, double scale) {
+    double s = scale > 0.0 ? 1.0 / scale : 1.0;
+    return log2f((float)(outcome * s) + 0x1p-10f);
+}
+
+__device__ __forceinline__ void log_tile_pair(const Lists &L, const TileMeta &a, const TileMeta &b,
+                                              double scale, float lbf, double outcome, int row) {
+    unsigned long long i = atomicAdd(L.log_count, 1ull);
+    if (i >= L.log_cap) return;
+    float f[MLP_IN];
+    tp_features(a, b, scale, lbf, f);
+    float *r = L.log + i * LOG_STRIDE;
+    for (int k = 0; k < MLP_IN; k++) r[k] = f[k];
+    r[MLP_IN] = tp_target(outcome, scale);
+    r[MLP_IN + 1] = __int_as_float(row);
+}
+
 struct TPShared {
-    int q, live, ta, tb, g, na, nb;
+    int q, live, ta, tb, g, na, nb, logged;
+    float lbf;
     double ub, m;
     float T2f;        // FP32 triangle-box cull threshold (squared)
     double T2d;       // FP64 triangle-box cull threshold (squared)
@@ -739,8 +791,18 @@ __device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned
     S.nb = b.n;
     S.ub = ub;
     S.m = m;
+    S.lbf = L.qlb[q];
+    S.logged = 0;
     if (hit) return;
-    if (mode == 0 && (double)L.qlb[q] > ub + m) return;
+    if (!L.seed_pass && (int)q == R->seed_q) return;  // already evaluated as the seed
+    if (mode == 0 && (double)S.lbf > ub + m) {
+        // pruned at dequeue: its box bound is the logged (lower-bound) outcome
+        if (L.log) {
+            log_tile_pair(L, a, b, R->scale, S.lbf, S.lbf, a.row);
+            S.logged = 1;
+        }
+        return;
+    }
     S.live = 1;
     if (precision == 0) {
         S.c = tp32_consts(a, b);
@@ -928,6 +990,17 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                             atomic_min_pos(&R->ub, sqrt(dm));
                         }
                     }
+                    if (L.log) {
+                        // smallest tested candidate distance, else the cull
+                        // threshold (every untested pair lies beyond it)
+                        double dm = PREC == 0 ? (double)fminf(fminf(S.redf[0], S.redf[1]),
+                                                              fminf(S.redf[2], S.redf[3]))
+                                              : fmin(fmin(S.redd[0], S.redd[1]),
+                                                     fmin(S.redd[2], S.redd[3]));
+                        double T2 = PREC == 0 ? (double)S.T2f : S.T2d;
+                        double out = sqrt(fmin(dm, T2));
+                        log_tile_pair(L, mA[S.ta], mB[S.tb], R->scale, S.lbf, out, S.g);
+                    }
                 }
             }
         }
@@ -1072,6 +1145,114 @@ void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
 }
 
 // ---------------------------------------------------------------------------
+// seed round: rank the queued tile pairs, evaluate each row's best first
+// ---------------------------------------------------------------------------
+__global__ void k_row_scale(RowState *rows, int64_t G) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double ub = bits_to_double(rows[g].ub);
+    double ext = rows[g].margin_scale * 0x1p36;
+    rows[g].scale = (ub > 0.0 && ub < __builtin_inf()) ? ub : (ext > 0.0 ? ext : 1.0);
+}
+
+void launch_row_scale(RowState *rows, int64_t G, hipStream_t s) {
+    if (G > 0) hipLaunchKernelGGL(k_row_scale, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G);
+}
+
+__device__ __forceinline__ uint32_t float_order_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+// One wave per queued tile pair (lane = hidden unit).  Without a ranker the
+// score is the box lower bound.  Weights sit in LDS transposed so that lanes
+// read consecutive words.
+__global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta *mB, RowState *rows,
+                                              Lists L, const float *W) {
+    __shared__ float w1t[MLP_IN * MLP_H], w2t[MLP_H * MLP_H], w3t[MLP_H * MLP_H];
+    __shared__ float bias[3 * MLP_H + MLP_H + 1];
+    __shared__ float hbuf[4][MLP_H];
+    const unsigned n = min(*L.qcount, L.qcap);
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    if (W) {
+        for (int i = threadIdx.x; i < MLP_H * MLP_IN; i += blockDim.x) {
+            int j = i / MLP_IN, k = i % MLP_IN;
+            w1t[k * MLP_H + j] = W[MLP_W1 + i];
+        }
+        for (int i = threadIdx.x; i < MLP_H * MLP_H; i += blockDim.x) {
+            int j = i / MLP_H, k = i % MLP_H;
+            w2t[k * MLP_H + j] = W[MLP_W2 + i];
+            w3t[k * MLP_H + j] = W[MLP_W3 + i];
+        }
+        for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
+            bias[i] = W[MLP_B1 + i];
+            bias[MLP_H + i] = W[MLP_B2 + i];
+            bias[2 * MLP_H + i] = W[MLP_B3 + i];
+            bias[3 * MLP_H + i] = W[MLP_W4 + i];
+        }
+        if (threadIdx.x == 0) bias[4 * MLP_H] = W[MLP_B4];
+        __syncthreads();
+    }
+    const unsigned nw = gridDim.x * 4;
+    for (unsigned q = blockIdx.x * 4 + wv; q < n; q += nw) {
+        int2 e = L.queue[q];
+        const TileMeta &a = mA[e.x];
+        RowState *R = rows + a.row;
+        float score;
+        if (W) {
+            float f[MLP_IN];
+            tp_features(a, mB[e.y], R->scale, L.qlb[q], f);
+            float h = bias[lane];
+            for (int k = 0; k < MLP_IN; k++) h += w1t[k * MLP_H + lane] * f[k];
+            hbuf[wv][lane] = fmaxf(h, 0.0f);
+            __builtin_amdgcn_wave_barrier();
+            h = bias[MLP_H + lane];
+            for (int k = 0; k < MLP_H; k++) h += w2t[k * MLP_H + lane] * hbuf[wv][k];
+            h = fmaxf(h, 0.0f);
+            __builtin_amdgcn_wave_barrier();
+            hbuf[wv][lane] = h;
+            __builtin_amdgcn_wave_barrier();
+            h = bias[2 * MLP_H + lane];
+            for (int k = 0; k < MLP_H; k++) h += w3t[k * MLP_H + lane] * hbuf[wv][k];
+            h = fmaxf(h, 0.0f);
+            score = wave_sum(h * bias[3 * MLP_H + lane]) + bias[4 * MLP_H];
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            score = L.qlb[q];
+        }
+        if (lane == 0) {
+            unsigned long long key = ((unsigned long long)float_order_bits(score) << 32) | q;
+            if (key < R->best) atomicMin(&R->best, key);
+        }
+    }
+}
+
+void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
+                 const float *ranker, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_rank, dim3(grid), dim3(256), 0, s, A.meta, B.meta, rows, L, ranker);
+}
+
+__global__ void k_seed_build(RowState *rows, int64_t G, Lists L, int2 *seedq, float *seedlb,
+                             unsigned int *seedcount) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    unsigned long long b = rows[g].best;
+    if (b == ~0ull) return;
+    unsigned q = (unsigned)(b & 0xffffffffu);
+    rows[g].seed_q = (int)q;
+    unsigned i = atomicAdd(seedcount, 1u);
+    seedq[i] = L.queue[q];
+    seedlb[i] = L.qlb[q];
+}
+
+void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
+                       unsigned int *seedcount, hipStream_t s) {
+    if (G > 0)
+        hipLaunchKernelGGL(k_seed_build, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, L, seedq,
+                           seedlb, seedcount);
+}
+
+// ---------------------------------------------------------------------------
 // final reduction
 // ---------------------------------------------------------------------------
 __global__ void k_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit) {
@@ -1089,13 +1270,7 @@ void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit
 
 __global__ void k_reset_lists(Lists L) {
     int i = threadIdx.x;
-    if (i == 0) {
-        *L.qcount = 0;
-        *L.qhead = 0;
-        *L.rcount = 0;
-        *L.rhead = 0;
-        *L.xcount = 0;
-    }
+    if (i < 16) L.qcount[i] = 0;  // the 16 device scalars (queue, rescue, exact, seed)
     if (i < C_NCOUNTERS) L.counters[i] = 0;
 }
 

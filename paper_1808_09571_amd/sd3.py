@@ -18,7 +18,10 @@ LIB_PATH = os.path.join(HERE, "libsd3.so")
 
 MEM_HOST, MEM_DEVICE = 0, 1
 PREC = {"fp32": 0, "fp64": 1}
-ORDER = {"bound": 0, "none": 1}
+ORDER = {"bound": 0, "none": 1, "learned": 2}
+MLP_NPARAM = 9089
+MLP_NIN = 10
+LOG_STRIDE = 12
 
 STATUS = {
     0: "SD3_OK", 1: "SD3_E_INVALID_ARG", 2: "SD3_E_INDEX_RANGE", 3: "SD3_E_NONFINITE",
@@ -27,7 +30,8 @@ STATUS = {
 }
 
 EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
-           "sd3_validate", "sd3_status_string", "sd3_last_error"]
+           "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step", "sd3_validate",
+           "sd3_status_string", "sd3_last_error"]
 
 
 class Geoms(ctypes.Structure):
@@ -37,7 +41,9 @@ class Geoms(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("ranker", ctypes.c_void_p), ("log", ctypes.c_void_p),
+                ("log_cap", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -45,12 +51,13 @@ class Stats(ctypes.Structure):
                 ("tile_pairs_evaluated", ctypes.c_int64), ("tri_pairs_boxed", ctypes.c_int64),
                 ("tri_pairs_fp32", ctypes.c_int64), ("tri_pairs_fp64", ctypes.c_int64),
                 ("rescued", ctypes.c_int64), ("exact", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7)]
+                ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7),
+                ("logged", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
     PHASES = ("upload", "prep", "queue", "pairs", "rescue", "exact", "finalize")
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ms_phase", "reserved")}
         d["ms_phase"] = dict(zip(self.PHASES, list(self.ms_phase)))
         return d
 
@@ -70,6 +77,15 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch provides device memory and streams, so the library must share its
+    # HIP runtime: import torch (and let it initialise the device) before the
+    # library pulls in libamdhip64.so.7, which the loader then resolves to
+    # torch's already loaded copy.
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"sd3 HIP library not built: {path} (run python -m "
                            "paper_1808_09571_amd.build)")
@@ -87,6 +103,13 @@ def load(path: str = LIB_PATH):
     lib.sd3_intersects.argtypes = [ctypes.c_void_p, P(Geoms), P(Geoms), ctypes.c_void_p,
                                    P(Opts), P(Stats), ctypes.c_void_p]
     lib.sd3_intersects.restype = ctypes.c_int
+    vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+    lib.sd3_mlp_forward.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.sd3_mlp_forward.restype = ctypes.c_int
+    lib.sd3_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.sd3_mlp_loss_grad.restype = ctypes.c_int
+    lib.sd3_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
+    lib.sd3_adam_step.restype = ctypes.c_int
     lib.sd3_validate.argtypes = [P(Geoms)]
     lib.sd3_validate.restype = ctypes.c_int
     lib.sd3_status_string.argtypes = [ctypes.c_int]
@@ -167,11 +190,18 @@ class Context:
         raise SD3Error(st, self.lib.sd3_last_error(self.handle).decode())
 
     @staticmethod
-    def _opts(precision, order, timing=False):
+    def _opts(precision, order, timing=False, ranker=None, log=None):
         o = Opts()
         o.precision = PREC[precision]
         o.order = ORDER[order]
         o.timing = 1 if timing else 0
+        if ranker is not None:
+            assert ranker.is_cuda and ranker.dtype.itemsize == 4 and ranker.numel() == MLP_NPARAM
+            o.ranker = ranker.data_ptr()
+        if log is not None:
+            assert log.is_cuda and log.dim() == 2 and log.shape[1] == LOG_STRIDE
+            o.log = log.data_ptr()
+            o.log_cap = log.shape[0]
         return o
 
     def _stream(self, a: Batch):
@@ -192,12 +222,15 @@ class Context:
         return d, h, (d.ctypes.data if want_dist else None), h.ctypes.data
 
     def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                 timing=False):
-        """Row-wise 3D distance (and the exact intersects flag as a by-product)."""
+                 timing=False, ranker=None, log=None):
+        """Row-wise 3D distance (and the exact intersects flag as a by-product).
+        order="learned" needs ``ranker`` (float32 [MLP_NPARAM] on the device);
+        ``log`` (float32 [cap, LOG_STRIDE] on the device) receives one training
+        record per dequeued tile pair."""
         ga, gb = a.geoms(), b.geoms()
         d, h, dp, hp = self._outputs(a, True)
         s = Stats()
-        o = self._opts(precision, order, timing)
+        o = self._opts(precision, order, timing, ranker, log)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
@@ -216,6 +249,53 @@ class Context:
         if st != 0:
             self._raise(st)
         return (h, s.as_dict()) if stats else h
+
+
+def _dev(t, n=None, dtype_size=4):
+    assert t.is_cuda and t.is_contiguous() and t.element_size() == dtype_size, "device float32"
+    if n is not None:
+        assert t.numel() == n
+    return t.data_ptr()
+
+
+class Ranker:
+    """Hand-written HIP training kernels of the tile-pair ranker MLP, driven
+    through the C-ABI (sd3_mlp_forward, sd3_mlp_loss_grad, sd3_adam_step)."""
+
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        self.lib = ctx.lib
+
+    def _stream(self, t):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+    def forward(self, params, x):
+        import torch
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        st = self.lib.sd3_mlp_forward(self.ctx.handle, _dev(params, MLP_NPARAM), _dev(x), n,
+                                      _dev(y), self._stream(x))
+        if st != 0:
+            self.ctx._raise(st)
+        return y
+
+    def loss_grad(self, params, x, t):
+        import torch
+        n = x.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+        st = self.lib.sd3_mlp_loss_grad(self.ctx.handle, _dev(params, MLP_NPARAM), _dev(x),
+                                        _dev(t, n), n, _dev(loss), _dev(grad), self._stream(x))
+        if st != 0:
+            self.ctx._raise(st)
+        return loss, grad
+
+    def adam(self, p, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        st = self.lib.sd3_adam_step(self.ctx.handle, _dev(p), _dev(g), _dev(m), _dev(v), p.numel(),
+                                    int(step), lr, beta1, beta2, eps, self._stream(p))
+        if st != 0:
+            self.ctx._raise(st)
 
 
 def validate(batch: Batch) -> int:

@@ -1,0 +1,124 @@
+"""GPU tests of the learned tile-pair ranking (seed round of sd3_distance).
+
+* The hand-written forward / backward / Adam kernels against the FP64 numpy
+  reference (oracle/mlp.py, itself pinned by finite differences).
+* Results never depend on the order: learned, box-bound and no seeding give
+  identical bits.
+* A network trained on logs of the method's own runs evaluates no more tile
+  pairs than the box-bound order on a held-out workload.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import mlp
+from paper_1808_09571_amd import ranker, sd3, synth
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sd3.Context(0)
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:0")
+
+
+def _data(seed, n):
+    g = np.random.default_rng(seed)
+    p = (g.normal(size=mlp.NPARAM) * 0.2).astype(np.float32)
+    X = g.normal(size=(n, mlp.NIN)).astype(np.float32)
+    t = g.normal(size=n).astype(np.float32)
+    return p, X, t
+
+
+@pytest.mark.parametrize("n", [1, 257, 3000])
+def test_forward_and_gradient_match_fp64_reference(ctx, n):
+    p, X, t = _data(n, n)
+    r = sd3.Ranker(ctx)
+    y = r.forward(_dev(p), _dev(X)).cpu().numpy()
+    y_ref, _ = mlp.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.all(np.abs(y - y_ref) <= 1e-4 * (1.0 + np.abs(y_ref)))
+    loss, g = r.loss_grad(_dev(p), _dev(X), _dev(t))
+    l_ref, g_ref = mlp.loss_grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    g = g.cpu().numpy()
+    assert abs(float(loss.item()) - l_ref) <= 1e-4 * max(1.0, l_ref)
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * max(1e-6, np.linalg.norm(g_ref))
+    assert np.all(np.abs(g - g_ref) <= 1e-4 * np.abs(g_ref).max() + 1e-6)
+
+
+def test_adam_matches_reference(ctx):
+    g = np.random.default_rng(3)
+    p = g.normal(size=mlp.NPARAM)
+    m = np.zeros(mlp.NPARAM)
+    v = np.zeros(mlp.NPARAM)
+    pd, md, vd = _dev(p), _dev(m), _dev(v)
+    r = sd3.Ranker(ctx)
+    for step in range(1, 4):
+        gr = g.normal(size=mlp.NPARAM)
+        r.adam(pd, _dev(gr), md, vd, step, lr=1e-2)
+        p, m, v = mlp.adam(p, gr, m, v, step, lr=1e-2)
+    assert np.allclose(pd.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss(ctx):
+    g = np.random.default_rng(5)
+    X = g.normal(size=(20000, mlp.NIN)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] - X[:, 3]).astype(np.float32)
+    p, hist = ranker.train(ctx, _dev(X), _dev(t), steps=400, batch=2048, lr=3e-3)
+    assert hist[-1][1] < 0.25 * hist[0][1]
+
+
+def _workloads():
+    A, B = [], []
+    for s in range(6):
+        a, b = synth.config_icospheres(s)
+        A.append(a)
+        B.append(b)
+    ta, tb = synth.config_tube_blob_batch(rows=12, seed=8, tube_tri=(200, 2000),
+                                          blob_tri=(1000, 6000), aim_range=1.5)
+    tin_a, tin_b = synth.config_tin_pair(n=96, extent=187.5, amplitude=20.0, gap=0.01,
+                                         seeds=(7, 8))
+    return [(A, B), (ta, tb), ([tin_a], [tin_b])]
+
+
+def test_order_never_changes_results(ctx):
+    import torch
+    rnd = torch.from_numpy(_data(9, 1)[0]).to("cuda:0")
+    for ba, bb in ranker.to_batches(_workloads()):
+        ref = None
+        for prec in ("fp32", "fp64"):
+            for order, w in (("none", None), ("bound", None), ("learned", rnd)):
+                d, h = ctx.distance(ba, bb, precision=prec, order=order, ranker=w)
+                got = (d.cpu().numpy().view(np.int64).copy(), h.cpu().numpy().copy())
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_logging_records(ctx):
+    ba, bb = ranker.to_batches(_workloads()[2:])[0]
+    X, t = ranker.collect(ctx, [(ba, bb)], cap=1 << 16)
+    X, t = X.cpu().numpy(), t.cpu().numpy()
+    assert X.shape[0] > 10 and np.all(np.isfinite(X)) and np.all(np.isfinite(t))
+    assert np.all(X[:, 8] > 0) and np.all(X[:, 8] <= 1)  # triangle fractions
+
+
+def test_trained_ranker_gain_on_heldout(ctx):
+    pairs = [([a], [b]) for a, b in (synth.config_tin_pair(n=192, extent=375.0, gap=g, seeds=s)
+                                     for g, s in ((0.01, (51, 52)), (0.003, (53, 54))))]
+    X, t = ranker.collect(ctx, ranker.to_batches(pairs))
+    params, hist = ranker.train(ctx, X, t, steps=600, batch=4096)
+    assert hist[-1][1] < hist[0][1]
+    A, B = synth.config_tin_pair(n=256, extent=500.0, gap=0.01, seeds=(55, 56))
+    ba, bb = ranker.to_batches([([A], [B])])[0]
+    ev = ranker.evaluate(ctx, ba, bb, params)
+    for o in ev:
+        assert np.array_equal(ev[o]["dist"].view(np.int64), ev["none"]["dist"].view(np.int64))
+    print({o: ev[o]["tile_pairs_evaluated"] for o in ev})
+    assert ev["learned"]["tile_pairs_evaluated"] <= ev["bound"]["tile_pairs_evaluated"]
