@@ -127,7 +127,14 @@ typedef struct sd3_stats {
        [6] final reduction and download */
     double ms_phase[7];
     int64_t logged;                /* training-log records produced (may exceed log_cap) */
-    int64_t reserved[3];
+    /* with opts.timing: device time summed over the launches of selected
+       kernels, and their launch counts: [0] radix-sort scatter, [1] tile
+       building, [2] tile-pair box filter, [3] main triangle-pair pass */
+    double ms_kernel[4];
+    int64_t n_kernel[4];
+    int64_t sort_items;            /* keys per radix pass (both sides) */
+    int32_t sort_key_bytes;        /* 4 or 8 */
+    int32_t sort_passes;
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;

@@ -42,11 +42,13 @@ struct sd3_ctx {
     SideState side[2];
     DevBuf rows, wi_off, queue, qlb, rescue, exact, counters, scalars, flags, out_d, out_h;
     DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb;
-    DevBuf mlp;  // ranker training scratch
+    DevBuf mlp;    // ranker training scratch
+    DevBuf wlist;  // compacted work items
     void *pin = nullptr;  // pinned host staging: offsets up, counters down
     size_t pin_cap = 0;
     int pairs_grid[2][2] = {{0, 0}, {0, 0}};
     hipEvent_t ev[8] = {};
+    KernelEvents *kev = nullptr;  // created on the first timed call
 };
 
 namespace {
@@ -346,7 +348,17 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             PB.hist = (uint32_t *)ensure(ctx->hist, sizeof(uint32_t) * 256 * nb);
             PB.part = (uint32_t *)ensure(ctx->part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
         }
-        launch_prep(A, B, PB, key_bits(G), s);
+        KernelEvents *kev = nullptr;
+        if (opts.timing) {
+            if (!ctx->kev) {
+                ctx->kev = new KernelEvents();
+                for (auto &row : ctx->kev->ev)
+                    for (auto &e : row) check(hipEventCreate(&e), "hipEventCreate");
+            }
+            kev = ctx->kev;
+            for (int c = 0; c < KE_CLASSES; c++) kev->n[c] = 0;
+        }
+        launch_prep(A, B, PB, key_bits(G), s, kev);
         QueueGeo Q{};
         Q.wi_off = ds + 6 * G1;
         Q.blkA = ds + 7 * G1;
@@ -354,6 +366,7 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         Q.gA = (GroupBox *)ensure(ctx->grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
         Q.gB = (GroupBox *)ensure(ctx->grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
         Q.wi_lb = (float *)ensure(ctx->wi_lb, sizeof(float) * (P.wi[G] + 1));
+        Q.wlist = (int32_t *)ensure(ctx->wlist, sizeof(int32_t) * (P.wi[G] + 1));
         launch_group_boxes(A, Q.blkA, P.blkA[G], 64, Q.gA, s);
         launch_group_boxes(B, Q.chkB, P.chkB[G], 256, Q.gB, s);
         RowState *rows = (RowState *)ensure(ctx->rows, sizeof(RowState) * (G > 0 ? G : 1));
@@ -376,6 +389,7 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         L.rhead = sc + 3;
         L.xcount = sc + 4;
         L.counters = (unsigned long long *)(sc + 16);
+        Q.wcount = sc + 8;  // [8] seeding, [9] filtering
         L.seed_pass = 0;
         L.log = mode == 0 ? opts.log : nullptr;
         L.log_cap = (unsigned long long)opts.log_cap;
@@ -396,10 +410,13 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         if (mode == 0) launch_row_scale(rows, G, s);
         // seed round: single queue pass, distance only
         const bool seed = mode == 0 && opts.order != SD3_ORDER_NONE && n_wi <= per_pass;
+        Q.compact = n_wi <= per_pass ? 1 : 0;
         for (int64_t w0 = 0; w0 < n_wi; w0 += per_pass) {
             int64_t nw = std::min(per_pass, n_wi - w0);
             if (w0 > 0) launch_reset_queue(L, s);
+            if (kev) kev->begin(KE_FILTER, s);
             launch_queue(A, B, Q, nw, w0, rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
+            if (kev) kev->end(KE_FILTER, s);
             if (seed) {
                 int2 *sq = (int2 *)ensure(ctx->seedq, sizeof(int2) * (G + 1));
                 float *sl = (float *)ensure(ctx->seedlb, sizeof(float) * (G + 1));
@@ -416,7 +433,9 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
                 launch_pairs(A, B, rows, LS, prec, mode, grid_pairs, s);
             }
             if (w0 == 0) clk.mark(3);
+            if (kev) kev->begin(KE_PAIRS, s);
             launch_pairs(A, B, rows, L, prec, mode, grid_pairs, s);
+            if (kev) kev->end(KE_PAIRS, s);
             if (n_wi > per_pass) {
                 unsigned int *qh = (unsigned int *)readback_area(ctx);
                 check(hipMemcpyAsync(qh, L.qcount, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "D2H qcount");
@@ -489,6 +508,20 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             stats->ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             clk.read(stats->ms_phase);
+            if (kev)
+                for (int c = 0; c < KE_CLASSES; c++) {
+                    double ms = 0.0;
+                    for (int i = 0; i < std::min(kev->n[c], 16); i++) {
+                        float f = 0.0f;
+                        check(hipEventElapsedTime(&f, kev->ev[c][2 * i], kev->ev[c][2 * i + 1]), "elapsed");
+                        ms += f;
+                    }
+                    stats->ms_kernel[c] = ms;
+                    stats->n_kernel[c] = std::min(kev->n[c], 16);
+                }
+            stats->sort_items = A.nt + B.nt;
+            stats->sort_key_bytes = key_bits(G) + 1 <= 32 ? 4 : 8;
+            stats->sort_passes = (key_bits(G) + 1 + 7) / 8;
         }
     } catch (const HipError &e) {
         (void)hipGetLastError();
@@ -579,12 +612,19 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
     DevBuf *bs[] = {&ctx->rows, &ctx->wi_off, &ctx->queue, &ctx->qlb, &ctx->rescue, &ctx->exact,
                     &ctx->counters, &ctx->scalars, &ctx->flags, &ctx->out_d, &ctx->out_h,
                     &ctx->keys0, &ctx->keys1, &ctx->vals0, &ctx->vals1, &ctx->hist, &ctx->part,
-                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb, &ctx->seedq, &ctx->seedlb, &ctx->mlp};
+                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb, &ctx->seedq, &ctx->seedlb, &ctx->mlp,
+                    &ctx->wlist};
     for (DevBuf *b : bs) release(*b);
     for (hipEvent_t &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     release(ctx->small);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->kev) {
+        for (auto &row : ctx->kev->ev)
+            for (auto &e : row)
+                if (e) (void)hipEventDestroy(e);
+        delete ctx->kev;
+    }
     delete ctx;
     return SD3_OK;
 }

@@ -21,6 +21,21 @@ struct SideBufs {
     TileMeta *meta;              // [NT]
 };
 
+// Optional HIP-event brackets around selected kernel launches (timing mode):
+// per kernel class, up to 16 (begin, end) pairs per call.
+enum : int { KE_SCATTER = 0, KE_TILES = 1, KE_FILTER = 2, KE_PAIRS = 3, KE_CLASSES = 4 };
+struct KernelEvents {
+    hipEvent_t ev[KE_CLASSES][32];
+    int n[KE_CLASSES];
+    void begin(int c, hipStream_t s) {
+        if (n[c] < 16) (void)hipEventRecord(ev[c][2 * n[c]], s);
+    }
+    void end(int c, hipStream_t s) {
+        if (n[c] < 16) (void)hipEventRecord(ev[c][2 * n[c] + 1], s);
+        n[c]++;
+    }
+};
+
 // Sort buffers shared by both sides (device).
 struct PrepBufs {
     uint64_t *keys[2];  // [ntA + ntB] ping-pong
@@ -72,7 +87,8 @@ enum : uint32_t { V_NONFINITE = 1, V_RANGE = 2, V_INDEX = 4 };
 void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
                      const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
                      hipStream_t s);
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s);
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
+                 KernelEvents *kev);
 void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
                       const unsigned long long *boxB, hipStream_t s);
 // Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
@@ -88,6 +104,9 @@ struct QueueGeo {
     const int64_t *chkB;    // [G+1] B-chunk offsets
     GroupBox *gA, *gB;
     float *wi_lb;           // [n_wi]
+    int32_t *wlist;         // [n_wi] compacted work items
+    unsigned int *wcount;   // [2] device counts (seeding, filtering); zeroed per call
+    int compact;            // filter through the compacted list (single queue pass)
 };
 
 void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngroups, int gs,

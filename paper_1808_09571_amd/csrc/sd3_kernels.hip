@@ -206,7 +206,8 @@ __global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, cons
 // wave with ballots.
 constexpr int RS_ITEMS = 4096;
 
-__global__ void k_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+template <typename KT>
+__global__ void k_hist(const KT *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -268,69 +269,151 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
     }
 }
 
-__global__ void k_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout,
-                          int64_t n, int shift, const uint32_t *hist, const uint32_t *part,
-                          int nblocks) {
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wcnt[4][256];
-    int tid = threadIdx.x, w = tid >> 6;
-    int64_t e = (int64_t)tid * nblocks + blockIdx.x;
-    base[tid] = hist[e] + part[e / SCAN_CHUNK];
-    int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
-    for (int r = 0; r < RS_ITEMS / 256; r++) {
-        for (int k = 0; k < 4; k++) wcnt[k][tid] = 0;
-        __syncthreads();
-        int64_t i = b0 + r * 256 + tid;
+// Stable scatter of one radix pass.  Wave w of a block ranks the block's
+// quarter [w*Q, (w+1)*Q) in rounds of 64 items (8 ballots find the lanes with
+// the same digit); per-wave running digit counts live in LDS, so ranking
+// needs no block-wide barrier.  The block then places its items in LDS in
+// digit order and writes each digit's run to consecutive global addresses.
+template <typename KT>
+__global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *vin, KT *kout,
+                                                 int32_t *vout, int64_t n, int shift,
+                                                 const uint32_t *hist, const uint32_t *part,
+                                                 int nblocks) {
+    constexpr int Q = RS_ITEMS / 4;   // items per wave
+    constexpr int R = Q / 64;         // rounds per wave
+    __shared__ uint32_t wc[4][256];   // per-wave digit counts, then per-wave offsets
+    __shared__ uint32_t gbase[256];   // global position of the block's first item of each digit
+    __shared__ uint32_t loff[256];    // block-local position of each digit's first item
+    __shared__ KT skey[RS_ITEMS];
+    __shared__ int32_t sval[RS_ITEMS];
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
+    {
+        int64_t e = (int64_t)tid * nblocks + blockIdx.x;
+        gbase[tid] = hist[e] + part[e / SCAN_CHUNK];
+    }
+    for (int k = 0; k < 4; k++) wc[k][tid] = 0;
+    __syncthreads();
+    KT key[R];
+    int32_t val[R];
+    uint32_t rk[R];
+    // issue every load of this thread before ranking (one memory latency)
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int64_t i = b0 + w * Q + r * 64 + lane;
+        key[r] = i < n ? kin[i] : (KT)0;
+        val[r] = i < n ? vin[i] : 0;
+    }
+    for (int r = 0; r < R; r++) {
+        int64_t i = b0 + w * Q + r * 64 + lane;
         bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0;
-        int32_t val = valid ? vin[i] : 0;
-        uint32_t d = (uint32_t)((key >> shift) & 255);
+        uint32_t d = (uint32_t)((key[r] >> shift) & 255);
         unsigned long long peers = __ballot(valid);
         for (int bit = 0; bit < 8; bit++) {
             unsigned long long m = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? m : ~m;
         }
+        uint32_t before = valid ? wc[w][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
         uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        rk[r] = valid ? before + rank : 0xffffffffu;
+        if (valid && rank == 0) wc[w][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digit totals -> block-local offsets (thread = digit), then per-wave offsets
+    {
+        uint32_t c0 = wc[0][tid], c1 = wc[1][tid], c2 = wc[2][tid], c3 = wc[3][tid];
+        uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t inc = wave_incl_scan(tot);
+        __shared__ uint32_t wsum[4];
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
-        if (valid) {
-            uint32_t pos = base[d] + rank;
-            for (int k = 0; k < w; k++) pos += wcnt[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-        __syncthreads();
+        uint32_t pre = inc - tot;
+        for (int k = 0; k < w; k++) pre += wsum[k];
+        loff[tid] = pre;
+        wc[0][tid] = pre;
+        wc[1][tid] = pre + c0;
+        wc[2][tid] = pre + c0 + c1;
+        wc[3][tid] = pre + c0 + c1 + c2;
+    }
+    __syncthreads();
+    for (int r = 0; r < R; r++) {
+        if (rk[r] == 0xffffffffu) continue;
+        uint32_t d = (uint32_t)((key[r] >> shift) & 255);
+        uint32_t slot = wc[w][d] + rk[r];
+        skey[slot] = key[r];
+        sval[slot] = val[r];
+    }
+    __syncthreads();
+    const int nvalid = (int)min((int64_t)RS_ITEMS, n - b0);
+    for (int j = tid; j < nvalid; j += 256) {
+        KT k = skey[j];
+        uint32_t d = (uint32_t)((k >> shift) & 255);
+        uint32_t pos = gbase[d] + (uint32_t)j - loff[d];
+        kout[pos] = k;
+        vout[pos] = sval[j];
     }
 }
 
 // Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
-static int radix_sort(uint64_t **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
-                      int bits, hipStream_t s) {
+template <typename KT>
+static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
+                      int bits, hipStream_t s, KernelEvents *kev) {
     int cur = 0;
     if (n <= 1) return cur;
     int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
     int64_t total = (int64_t)nb * 256;
     int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
+        hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
         hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+        if (kev) kev->begin(KE_SCATTER, s);
+        hipLaunchKernelGGL(k_scatter<KT>, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
                            keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb);
+        if (kev) kev->end(KE_SCATTER, s);
         cur ^= 1;
     }
     return cur;
 }
 
+// 32-bit keys (one word per item) whenever side, row and Morton bits fit.
+__global__ void k_narrow_keys(const uint64_t *in, uint32_t *out, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (uint32_t)in[i];
+}
+
 // One wave per tile: gather the tile's triangles in sorted order, write the
 // FP64 and FP32 SoA copies and the tile metadata.
-__global__ void k_tiles(const double *xyz, const int32_t *tri, const int64_t *v_off,
-                        const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t NT,
-                        const int32_t *sorted, float *t32, double *t64, TileMeta *meta) {
+struct TileJob {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off, *t_off, *tile_off;
+    int64_t G, NT;
+    const int32_t *sorted;
+    float *t32;
+    double *t64;
+    TileMeta *meta;
+};
+
+__device__ void tile_one(const double *xyz, const int32_t *tri, const int64_t *v_off,
+                         const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t t,
+                         const int32_t *sorted, float *t32, double *t64, TileMeta *meta);
+
+// Both sides in one launch: waves [0, NT_A) build A's tiles, the rest B's.
+__global__ void k_tiles(TileJob A, TileJob B) {
     int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= NT) return;
+    if (t < A.NT)
+        tile_one(A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, t, A.sorted, A.t32, A.t64, A.meta);
+    else if (t - A.NT < B.NT)
+        tile_one(B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, t - A.NT, B.sorted, B.t32, B.t64,
+                 B.meta);
+}
+
+__device__ void tile_one(const double *xyz, const int32_t *tri, const int64_t *v_off,
+                         const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t t,
+                         const int32_t *sorted, float *t32, double *t64, TileMeta *meta) {
     int j = lane_id();
     int64_t g = find_row(tile_off, G, t);
     int64_t i = t - tile_off[g];
@@ -403,19 +486,31 @@ static void morton(SideBufs &S, uint64_t side_key, uint64_t *keys, int32_t *vals
 
 // Both sides are sorted together (the side is the top key bit), so one
 // sequence of sort launches covers 2x the items.
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s) {
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
+                 KernelEvents *kev) {
     if (A.G == 0) return;
     rowbox(A, s);
     rowbox(B, s);
     morton(A, 0ull, P.keys[0], P.vals[0], s);
     morton(B, 1ull << key_bits, P.keys[0] + A.nt, P.vals[0] + A.nt, s);
-    int cur = radix_sort(P.keys, P.vals, P.hist, P.part, A.nt + B.nt, key_bits + 1, s);
-    if (A.NT > 0)
-        hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT, 4)), dim3(256), 0, s, A.xyz, A.tri, A.v_off,
-                           A.t_off, A.tile_off, A.G, A.NT, P.vals[cur], A.t32, A.t64, A.meta);
-    if (B.NT > 0)
-        hipLaunchKernelGGL(k_tiles, dim3(grid_for(B.NT, 4)), dim3(256), 0, s, B.xyz, B.tri, B.v_off,
-                           B.t_off, B.tile_off, B.G, B.NT, P.vals[cur] + A.nt, B.t32, B.t64, B.meta);
+    const int64_t n = A.nt + B.nt;
+    int cur;
+    if (key_bits + 1 <= 32) {
+        uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
+        if (n > 0)
+            hipLaunchKernelGGL(k_narrow_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.keys[0], k32[0], n);
+        cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
+    } else {
+        cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
+    }
+    if (kev) kev->begin(KE_TILES, s);
+    if (A.NT + B.NT > 0) {
+        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, P.vals[cur], A.t32, A.t64, A.meta};
+        TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, P.vals[cur] + A.nt, B.t32,
+                   B.t64, B.meta};
+        hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
+    }
+    if (kev) kev->end(KE_TILES, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,20 +633,59 @@ __global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t 
                           const int64_t *wi_off, int64_t G, int64_t n_wi, RowState *rows,
                           float *wi_lb, int update_ub) {
     int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (wi >= n_wi) return;
-    int64_t g = find_row(wi_off, G, wi);
-    int64_t local = wi - wi_off[g];
-    int64_t nB = tB[g + 1] - tB[g];
-    int64_t nbc = (nB + 255) / 256;
-    const GroupBox &a = gA[blkA[g] + local / nbc];
-    const GroupBox &b = gB[chkB[g] + local % nbc];
-    double g2 = box_gap2(a.lo, a.hi, b.lo, b.hi);
-    wi_lb[wi] = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
-    if (update_ub) {
+    // lanes past the end stay in the wave for the reduction below; lane 0 of
+    // a wave is past the end only when the whole wave is
+    if (__shfl((int)(wi < n_wi), 0) == 0) return;
+    const bool valid = wi < n_wi;
+    int64_t g = -1;
+    double u = __builtin_inf();
+    if (valid) {
+        g = find_row(wi_off, G, wi);
+        int64_t local = wi - wi_off[g];
+        int64_t nB = tB[g + 1] - tB[g];
+        int64_t nbc = (nB + 255) / 256;
+        const GroupBox &a = gA[blkA[g] + local / nbc];
+        const GroupBox &b = gB[chkB[g] + local % nbc];
+        double g2 = box_gap2(a.lo, a.hi, b.lo, b.hi);
+        wi_lb[wi] = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
         double dx = a.rep[0] - b.rep[0], dy = a.rep[1] - b.rep[1], dz = a.rep[2] - b.rep[2];
-        double u = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 8.0 * U64);
-        if (u < bits_to_double(load_acq(&rows[g].ub))) atomic_min_pos(&rows[g].ub, u);
+        u = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 8.0 * U64);
     }
+    if (!update_ub) return;
+    const int64_t g0 = __shfl(g, 0);
+    if (__all(!valid || g == g0)) {
+        // one row for the whole wave: one atomic instead of 64
+        u = wave_min(u);
+        if (lane_id() == 0 && u < bits_to_double(load_acq(&rows[g0].ub))) atomic_min_pos(&rows[g0].ub, u);
+    } else if (valid && u < bits_to_double(load_acq(&rows[g].ub))) {
+        atomic_min_pos(&rows[g].ub, u);
+    }
+}
+
+// The work items whose group bound may still hold the row minimum (distance:
+// lower bound <= ub + m; intersects: overlapping groups), compacted so that
+// the tile-level kernels only launch useful workgroups.
+__global__ void k_wi_compact(const float *wi_lb, const int64_t *wi_off, int64_t G, int64_t n_wi,
+                             const RowState *rows, int mode, int32_t *list, unsigned int *count) {
+    int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool keep = false;
+    if (wi < n_wi) {
+        int64_t g = find_row(wi_off, G, wi);
+        double lb = (double)wi_lb[wi];
+        if (mode == 1) {
+            keep = lb <= 0.0;
+        } else {
+            const RowState &R = rows[g];
+            double ub = bits_to_double(R.ub);
+            keep = lb <= ub + row_margin(R, ub);
+        }
+    }
+    unsigned long long m = __ballot(keep);
+    if (m == 0) return;
+    unsigned int base = 0;
+    if (lane_id() == 0) base = atomicAdd(count, (unsigned int)__popcll(m));
+    base = __shfl(base, 0);
+    if (keep) list[base + __popcll(m & lanes_below())] = (int32_t)wi;
 }
 
 // True when the whole work item can be skipped.  The row bound is read by
@@ -577,11 +711,14 @@ __device__ __forceinline__ bool wi_pruned(const float *wi_lb, int64_t wi, const 
 // distance from above.
 __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileMeta *mB,
                                                  const int64_t *tA, const int64_t *tB,
-                                                 const int64_t *wi_off, int64_t G, int64_t wi0,
-                                                 RowState *rows, const float *wi_lb) {
+                                                 const int64_t *wi_off, int64_t G,
+                                                 RowState *rows, const float *wi_lb,
+                                                 const int32_t *wlist, const unsigned int *wcount) {
     __shared__ double rep[64][3];
-    WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
-    if (wi_pruned(wi_lb, wi0 + blockIdx.x, rows[w.g], 0)) return;
+    if (blockIdx.x >= *wcount) return;
+    const int64_t wi = wlist[blockIdx.x];
+    WorkItem w = decode_item(wi_off, G, wi, tA, tB);
+    if (wi_pruned(wi_lb, wi, rows[w.g], 0)) return;
     if (threadIdx.x < w.na)
         for (int k = 0; k < 3; k++) rep[threadIdx.x][k] = mA[w.a0 + threadIdx.x].rep[k];
     __syncthreads();
@@ -614,10 +751,18 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
                                                 const int64_t *wi_off, int64_t G, int64_t wi0,
                                                 const RowState *rows, int mode, int2 *queue,
                                                 float *qlb, unsigned int *qcount,
-                                                unsigned int qcap, const float *wi_lb) {
+                                                unsigned int qcap, const float *wi_lb,
+                                                const int32_t *wlist, const unsigned int *wcount) {
     __shared__ double box[64][6];
-    WorkItem w = decode_item(wi_off, G, wi0 + blockIdx.x, tA, tB);
-    if (wi_pruned(wi_lb, wi0 + blockIdx.x, rows[w.g], mode)) return;
+    int64_t wi;
+    if (wlist) {
+        if (blockIdx.x >= *wcount) return;
+        wi = wlist[blockIdx.x];
+    } else {
+        wi = wi0 + blockIdx.x;
+    }
+    WorkItem w = decode_item(wi_off, G, wi, tA, tB);
+    if (wi_pruned(wi_lb, wi, rows[w.g], mode)) return;
     if (threadIdx.x < w.na)
         for (int k = 0; k < 3; k++) {
             box[threadIdx.x][k] = mA[w.a0 + threadIdx.x].lo[k];
@@ -668,18 +813,34 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
 void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
                   int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s) {
     if (n_wi <= 0) return;
+    const unsigned nb = (unsigned)n_wi;
     if (what == Q_SEED || what == Q_GROUPS) {
         hipLaunchKernelGGL(k_wi_seed, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.gA, Q.gB, Q.blkA,
                            Q.chkB, A.tile_off, B.tile_off, Q.wi_off, A.G, n_wi, rows, Q.wi_lb,
                            what == Q_SEED ? 1 : 0);
-        if (what == Q_SEED)
-            hipLaunchKernelGGL(k_ub_seed, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta,
-                               A.tile_off, B.tile_off, Q.wi_off, A.G, wi_begin, rows, Q.wi_lb);
+        if (what == Q_SEED) {
+            hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
+                               Q.wi_off, A.G, n_wi, rows, 0, Q.wlist, Q.wcount);
+            hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                               B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, Q.wlist, Q.wcount);
+        }
         return;
     }
-    hipLaunchKernelGGL(k_filter, dim3((unsigned)n_wi), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
-                       B.tile_off, Q.wi_off, A.G, wi_begin, rows, what == Q_FILTER_DIST ? 0 : 1,
-                       L.queue, L.qlb, L.qcount, L.qcap, Q.wi_lb);
+    const int mode = what == Q_FILTER_DIST ? 0 : 1;
+    if (Q.compact) {
+        // single pass over all work items: compact the survivors of the group
+        // bound first (the count is read on the device)
+        hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
+                           Q.wi_off, A.G, n_wi, rows, mode, Q.wlist, Q.wcount + 1);
+        hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                           B.tile_off, Q.wi_off, A.G, (int64_t)0, rows, mode, L.queue, L.qlb,
+                           L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1);
+    } else {
+        hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                           B.tile_off, Q.wi_off, A.G, wi_begin, rows, mode, L.queue, L.qlb,
+                           L.qcount, L.qcap, Q.wi_lb, (const int32_t *)nullptr,
+                           (const unsigned int *)nullptr);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -52,13 +52,20 @@ class Stats(ctypes.Structure):
                 ("tri_pairs_fp32", ctypes.c_int64), ("tri_pairs_fp64", ctypes.c_int64),
                 ("rescued", ctypes.c_int64), ("exact", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7),
-                ("logged", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("logged", ctypes.c_int64), ("ms_kernel", ctypes.c_double * 4),
+                ("n_kernel", ctypes.c_int64 * 4), ("sort_items", ctypes.c_int64),
+                ("sort_key_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32)]
+
+    KERNELS = ("scatter", "tiles", "filter", "pairs")
 
     PHASES = ("upload", "prep", "queue", "pairs", "rescue", "exact", "finalize")
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ms_phase", "reserved")}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("ms_phase", "ms_kernel", "n_kernel")}
         d["ms_phase"] = dict(zip(self.PHASES, list(self.ms_phase)))
+        d["ms_kernel"] = dict(zip(self.KERNELS, list(self.ms_kernel)))
+        d["n_kernel"] = dict(zip(self.KERNELS, list(self.n_kernel)))
         return d
 
 
