@@ -27,7 +27,8 @@
  * geometry pair per table row, Sec. 3.1 "whole column" processing).
  *
  * Thread safety: a context may be used by one host thread at a time.  Calls are
- * synchronous: they return after the results are in `out`.
+ * synchronous (they return after the results are in `out`), except graph
+ * launches (sd3_graph_launch).
  */
 #ifndef SD3_H
 #define SD3_H
@@ -102,13 +103,26 @@ typedef struct sd3_opts {
     int32_t order;       /* SD3_ORDER_* */
     int32_t timing;      /* nonzero: record HIP events around each phase on the
                             call's stream and report their durations in stats */
-    int32_t reserved0;
+    int32_t tile;        /* triangles per tile: SD3_TILE_32/64/128, or
+                            SD3_TILE_AUTO (0): the size sd3_autotune chose for
+                            this kind of workload on this context, else 64 */
     const float *ranker; /* device, SD3_MLP_NPARAM floats (SD3_ORDER_LEARNED) */
     float *log;          /* device or NULL: one record per tile pair dequeued by
                             sd3_distance, SD3_LOG_STRIDE floats each */
     int64_t log_cap;     /* records `log` can hold; extra records are dropped */
-    int64_t reserved[4];
+    int64_t queue_cap;   /* tile pairs the candidate queue holds per pass (0: 2^27);
+                            larger workloads are processed in several passes */
+    int64_t reserved[3];
 } sd3_opts;
+
+#define SD3_TILE_AUTO 0
+#define SD3_TILE_32 32
+#define SD3_TILE_64 64
+#define SD3_TILE_128 128
+
+/* Operator of a graph or a tuning run. */
+#define SD3_KIND_DISTANCE 0
+#define SD3_KIND_INTERSECTS 1
 
 /* Work counters of the last call (all tile and triangle counts summed over rows). */
 typedef struct sd3_stats {
@@ -135,6 +149,8 @@ typedef struct sd3_stats {
     int64_t sort_items;            /* keys per radix pass (both sides) */
     int32_t sort_key_bytes;        /* 4 or 8 */
     int32_t sort_passes;
+    int32_t tile;                  /* triangles per tile used by the call */
+    int32_t queue_passes;          /* candidate-queue passes */
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;
@@ -191,6 +207,57 @@ sd3_status sd3_mlp_loss_grad(sd3_ctx *ctx, const float *params, const float *x, 
                              int64_t n, float *loss, float *grad, void *stream);
 sd3_status sd3_adam_step(sd3_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t count,
                          int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Batched replay through a HIP graph.  sd3_graph_create plans one call of
+ * `kind` (SD3_KIND_DISTANCE: dist and optional hit; SD3_KIND_INTERSECTS: hit)
+ * over device-resident batches (mem == SD3_MEM_DEVICE) and records every
+ * kernel of it -- validation, sort and tiles, bounds and queue, the
+ * persistent triangle-pair pass over all rows, rescue, exact arithmetic, final
+ * reduction -- into one graph with its own device work space, so that a
+ * launch costs one graph launch and no host synchronisation.
+ *   - The batch shapes (offsets, counts), the device pointers and the options
+ *     are fixed at creation; the contents of xyz / tri / ranker may change
+ *     between launches.  The offsets are copied at creation.
+ *   - The contents are validated at creation (errors as for sd3_distance) and
+ *     again on the device by every launch: a launch over invalid contents, or
+ *     one whose work lists overflow, leaves the outputs untouched and
+ *     sd3_graph_result reports the error.  Vertex indices are clamped into
+ *     their row before use, so invalid contents never address other memory.
+ *   - opts.timing and opts.log are not supported (SD3_E_INVALID_ARG).
+ *   - The graph keeps `ctx` (for its device) and must be destroyed before it.
+ * sd3_graph_launch enqueues one replay on `stream` (hipStream_t, NULL: the
+ * default stream) and returns at once.  sd3_graph_result waits for `stream`
+ * and returns the status of the last replay enqueued on it (stats may be
+ * NULL; timing fields are zero).  Launches of one graph must not overlap:
+ * they share its work space.
+ */
+typedef struct sd3_graph sd3_graph;
+sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
+                            double *dist, uint8_t *hit, const sd3_opts *opts, sd3_graph **out);
+sd3_status sd3_graph_launch(sd3_graph *graph, void *stream);
+sd3_status sd3_graph_result(sd3_graph *graph, sd3_stats *stats, void *stream);
+sd3_status sd3_graph_destroy(sd3_graph *graph);
+
+/*
+ * Tile-size autotuner.  Runs the call `kind` on the given batches once per
+ * candidate tile size (32, 64, 128 triangles) for 1 + reps repetitions, keeps
+ * the median wall time of the last reps, and records the fastest size in ctx
+ * for this kind of workload (operator, precision, order, and the binary
+ * magnitudes of the row count and of the mean triangles per row): later calls
+ * with opts->tile == SD3_TILE_AUTO on a workload of the same kind use it.
+ * Results do not depend on the tile size.  report may be NULL.
+ * Errors: those of sd3_distance / sd3_intersects; reps < 1 is
+ * SD3_E_INVALID_ARG.
+ */
+typedef struct sd3_tune_report {
+    int32_t n;       /* candidates timed */
+    int32_t best;    /* tile size chosen */
+    int32_t tile[4]; /* candidate tile sizes */
+    double ms[4];    /* median wall time of one call for each candidate */
+} sd3_tune_report;
+sd3_status sd3_autotune(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
+                        const sd3_opts *opts, int32_t reps, sd3_tune_report *report, void *stream);
 
 /* Host-side validation of a batch whose xyz/tri are host memory (the checks
  * the two operators run before any launch); needs no device. */

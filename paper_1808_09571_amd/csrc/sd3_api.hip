@@ -1,9 +1,11 @@
 // sd3 C-ABI: argument checks, device buffers and the pipeline of one call.
+#include <algorithm>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,12 +23,37 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
 struct SideState {
-    DevBuf xyz, tri, v_off, t_off, tile_off, rowbox, t32, t64, meta;
+    DevBuf xyz, tri, rowbox, t32, t64, meta;
+};
+
+// Device work space of one call: a context owns one, and every graph owns its
+// own, so that replays never share buffers with eager calls.
+struct Workspace {
+    SideState side[2];
+    DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb, wlist;
+    void release_all() {
+        for (auto &sd : side) {
+            DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.meta};
+            for (DevBuf *b : bs) release(*b);
+        }
+        DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
+                        &vals0, &vals1, &hist, &part, &small, &grpA, &grpB, &wi_lb, &seedq,
+                        &seedlb, &wlist};
+        for (DevBuf *b : bs) release(*b);
+    }
 };
 
 struct Plan {
     int64_t G = 0;
+    int tk = TK_DEFAULT;                // triangles per tile
     std::vector<int64_t> tileA, tileB;  // [G+1] tile offsets
     std::vector<int64_t> wi;            // [G+1] work-item offsets
     std::vector<int64_t> blkA, chkB;    // [G+1] A-block (64 tiles) / B-chunk (256 tiles) offsets
@@ -39,14 +66,12 @@ struct sd3_ctx {
     int device = 0;
     int cus = 0;
     std::string err;
-    SideState side[2];
-    DevBuf rows, wi_off, queue, qlb, rescue, exact, counters, scalars, flags, out_d, out_h;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb;
-    DevBuf mlp;    // ranker training scratch
-    DevBuf wlist;  // compacted work items
+    Workspace ws;
+    DevBuf mlp;           // ranker training scratch
     void *pin = nullptr;  // pinned host staging: offsets up, counters down
     size_t pin_cap = 0;
-    int pairs_grid[2][2] = {{0, 0}, {0, 0}};
+    int pairs_grid[2][2][3] = {};         // [precision][mode][tile size 32/64/128]
+    std::map<uint64_t, int> tuned;        // workload key -> tile size (sd3_autotune)
     hipEvent_t ev[8] = {};
     KernelEvents *kev = nullptr;  // created on the first timed call
 };
@@ -54,8 +79,13 @@ struct sd3_ctx {
 namespace {
 
 constexpr unsigned int QUEUE_BUDGET = 1u << 27;   // tile pairs per queue pass
+constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
 constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
 constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic
+// device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
+// head [4] exact count [6] seed count [7] seed head [8] [9] work-item counts
+// [12] [13] validation flags of a and b; the counters follow at byte 64
+constexpr size_t SCALAR_BYTES = 64 + sizeof(unsigned long long) * C_NCOUNTERS;
 
 struct HipError {
     hipError_t e;
@@ -104,12 +134,6 @@ char *ensure_pinned(sd3_ctx *ctx, size_t bytes) {
 
 char *readback_area(sd3_ctx *ctx) { return (char *)ctx->pin + ctx->pin_cap - 512; }
 
-void release(DevBuf &b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-}
-
 sd3_status fail(sd3_ctx *ctx, sd3_status s, const std::string &msg) {
     if (ctx) ctx->err = msg;
     return s;
@@ -152,6 +176,12 @@ sd3_status check_geoms(const sd3_geoms *g, std::string &msg) {
         msg = "xyz or tri is NULL";
         return SD3_E_INVALID_ARG;
     }
+    for (int64_t i = 0; i < g->count; i++) {
+        if (g->t_off[i + 1] > g->t_off[i] && g->v_off[i + 1] == g->v_off[i]) {
+            msg = "row " + std::to_string(i) + " has triangles but no vertices";
+            return SD3_E_INDEX_RANGE;
+        }
+    }
     return SD3_OK;
 }
 
@@ -183,37 +213,67 @@ sd3_status check_host_data(const sd3_geoms *g, std::string &msg) {
     return SD3_OK;
 }
 
-int64_t tiles_of(int64_t nt) { return (nt + K - 1) / K; }
+int64_t tiles_of(int64_t nt, int tk) { return (nt + tk - 1) / tk; }
 
-// Upload (host inputs) or reference (device inputs) one side and size its
-// buffers.  Offsets were staged already.  No kernel reads the data before it
-// has been validated.
-void setup_side(sd3_ctx *ctx, int which, const sd3_geoms *g, int64_t NT, const int64_t *d_offs,
-                SideBufs &S, hipStream_t s) {
-    SideState &st = ctx->side[which];
-    int64_t G = g->count, nv = g->v_off[G], nt = g->t_off[G];
-    S.G = G;
-    S.nv = nv;
-    S.nt = nt;
-    S.NT = NT;
-    if (g->mem == SD3_MEM_HOST) {
-        double *x = (double *)ensure(st.xyz, sizeof(double) * 3 * nv);
-        int32_t *t = (int32_t *)ensure(st.tri, sizeof(int32_t) * 3 * nt);
-        if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
-        if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
-        S.xyz = x;
-        S.tri = t;
-    } else {
-        S.xyz = g->xyz;
-        S.tri = g->tri;
+int tk_index(int tk) { return tk == 32 ? 0 : (tk == 64 ? 1 : 2); }
+
+int ilog2(uint64_t x) {
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        r++;
     }
-    S.v_off = d_offs;
-    S.t_off = d_offs + (G + 1);
-    S.tile_off = d_offs + 2 * (G + 1);
-    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * (G > 0 ? G : 1));
-    S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * K * S.NT);
-    S.t64 = (double *)ensure(st.t64, sizeof(double) * 9 * K * S.NT);
-    S.meta = (TileMeta *)ensure(st.meta, sizeof(TileMeta) * S.NT);
+    return r;
+}
+
+// Workload class of the autotuner: operator, precision, order, and the
+// binary magnitudes of the row count and of the mean triangles per row.
+uint64_t workload_key(const sd3_opts &o, int mode, const sd3_geoms *a, const sd3_geoms *b) {
+    int64_t G = a->count;
+    int64_t tri = a->t_off[G] + b->t_off[G];
+    int64_t mean = G > 0 ? tri / G : 0;
+    return (uint64_t)mode | ((uint64_t)o.precision << 2) | ((uint64_t)o.order << 4) |
+           ((uint64_t)ilog2((uint64_t)G + 1) << 8) | ((uint64_t)ilog2((uint64_t)mean + 1) << 16);
+}
+
+int choose_tile(const sd3_ctx *ctx, const sd3_opts &o, int mode, const sd3_geoms *a,
+                const sd3_geoms *b) {
+    if (o.tile != SD3_TILE_AUTO) return o.tile;
+    auto it = ctx->tuned.find(workload_key(o, mode, a, b));
+    return it != ctx->tuned.end() ? it->second : TK_DEFAULT;
+}
+
+// Argument checks of the two operators and of graph creation.
+sd3_status check_call(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, const double *dist,
+                      const uint8_t *hit, const sd3_opts *opts_in, int mode, sd3_opts &opts) {
+    std::string msg;
+    sd3_status st = check_geoms(a, msg);
+    if (st == SD3_OK) st = check_geoms(b, msg);
+    if (st != SD3_OK) return fail(ctx, st, msg);
+    if (a->count != b->count) return fail(ctx, SD3_E_INVALID_ARG, "batches differ in count");
+    if (a->mem != b->mem) return fail(ctx, SD3_E_INVALID_ARG, "batches differ in memory kind");
+    if ((mode == 0 && !dist) || (mode == 1 && !hit))
+        return fail(ctx, SD3_E_INVALID_ARG, "output pointer is NULL");
+    sd3_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.precision != SD3_PREC_FP32_RESCUE && opts.precision != SD3_PREC_FP64)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown precision");
+    if (opts.order != SD3_ORDER_BOUND && opts.order != SD3_ORDER_NONE &&
+        opts.order != SD3_ORDER_LEARNED)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown order");
+    if (opts.order == SD3_ORDER_LEARNED && !opts.ranker)
+        return fail(ctx, SD3_E_INVALID_ARG, "SD3_ORDER_LEARNED needs opts.ranker");
+    if (opts.tile != SD3_TILE_AUTO && !tile_size_ok(opts.tile))
+        return fail(ctx, SD3_E_INVALID_ARG, "tile must be 0, 32, 64 or 128");
+    if (opts.queue_cap < 0) return fail(ctx, SD3_E_INVALID_ARG, "queue_cap < 0");
+    if (opts.log && (opts.log_cap < 0 || a->mem != SD3_MEM_DEVICE))
+        return fail(ctx, SD3_E_INVALID_ARG, "log needs a device buffer and log_cap >= 0");
+    if (a->mem == SD3_MEM_HOST) {
+        st = check_host_data(a, msg);
+        if (st == SD3_OK) st = check_host_data(b, msg);
+        if (st != SD3_OK) return fail(ctx, st, msg);
+    }
+    return SD3_OK;
 }
 
 // Morton key bits: 30 for the code plus enough to keep rows apart.
@@ -221,23 +281,6 @@ int key_bits(int64_t G) {
     int rowbits = 0;
     while (((int64_t)1 << rowbits) < G) rowbits++;
     return 30 + rowbits;
-}
-
-// Validate device-resident data on the device (one synchronisation).
-sd3_status validate_device(sd3_ctx *ctx, const sd3_geoms *a, const SideBufs &A,
-                           const sd3_geoms *b, const SideBufs &B, hipStream_t s) {
-    uint32_t *flags = (uint32_t *)ensure(ctx->flags, 256);
-    check(hipMemsetAsync(flags, 0, 2 * sizeof(uint32_t), s), "memset flags");
-    launch_validate(a->xyz, A.nv, a->tri, A.nt, A.v_off, A.t_off, A.G, flags, s);
-    launch_validate(b->xyz, B.nv, b->tri, B.nt, B.v_off, B.t_off, B.G, flags + 1, s);
-    uint32_t *h = (uint32_t *)readback_area(ctx);
-    check(hipMemcpyAsync(h, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "D2H flags");
-    check(hipStreamSynchronize(s), "sync");
-    uint32_t f = h[0] | h[1];
-    if (f & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
-    if (f & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
-    if (f & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside its row");
-    return SD3_OK;
 }
 
 // Phase events (opts.timing): ev[0] at the start, ev[k+1] at the end of phase k.
@@ -259,95 +302,310 @@ struct PhaseClock {
     }
 };
 
+// One planned call: host plan and the device views of its work space.
+struct Call {
+    int mode = 0;
+    sd3_opts opts{};
+    Plan P;
+    SideBufs A{}, B{};
+    PrepBufs PB{};
+    QueueGeo Q{};
+    Lists L{};
+    RowState *rows = nullptr;
+    unsigned int *sc = nullptr;  // device scalars + counters (SCALAR_BYTES)
+    uint32_t *flags = nullptr;   // sc + 12: validation flags of a, b
+    int64_t n_wi = 0, per_pass = 0;
+    int passes = 0;
+    bool seed = false;
+    int grid_pairs = 0;
+    int2 *seedq = nullptr;
+    float *seedlb = nullptr;
+    double *dd = nullptr;  // device outputs
+    uint8_t *hd = nullptr;
+};
+
+// Upload (host inputs) or reference (device inputs) one side and size its
+// buffers.  No kernel reads the data here.
+void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk,
+                const int64_t *d_offs, SideBufs &S, hipStream_t s) {
+    SideState &st = ws.side[which];
+    int64_t G = g->count, nv = g->v_off[G], nt = g->t_off[G];
+    S.G = G;
+    S.nv = nv;
+    S.nt = nt;
+    S.NT = NT;
+    S.tk = tk;
+    if (g->mem == SD3_MEM_HOST) {
+        double *x = (double *)ensure(st.xyz, sizeof(double) * 3 * nv);
+        int32_t *t = (int32_t *)ensure(st.tri, sizeof(int32_t) * 3 * nt);
+        if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
+        if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
+        S.xyz = x;
+        S.tri = t;
+    } else {
+        S.xyz = g->xyz;
+        S.tri = g->tri;
+    }
+    S.v_off = d_offs;
+    S.t_off = d_offs + (G + 1);
+    S.tile_off = d_offs + 2 * (G + 1);
+    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * (G > 0 ? G : 1));
+    S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * tk * S.NT);
+    S.t64 = (double *)ensure(st.t64, sizeof(double) * 9 * tk * S.NT);
+    S.meta = (TileMeta *)ensure(st.meta, sizeof(TileMeta) * S.NT);
+}
+
+// Plans a call: tiles and work items per row, buffer sizes in `ws`, offsets
+// (and host inputs) staged on stream s.  Launches no kernel.
+void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms *b,
+               const sd3_opts &opts, int mode, int tk, double *dist, uint8_t *hit, Call &C,
+               hipStream_t s) {
+    const int64_t G = a->count;
+    C.mode = mode;
+    C.opts = opts;
+    Plan &P = C.P;
+    P.G = G;
+    P.tk = tk;
+    P.tileA.assign(G + 1, 0);
+    P.tileB.assign(G + 1, 0);
+    P.wi.assign(G + 1, 0);
+    P.blkA.assign(G + 1, 0);
+    P.chkB.assign(G + 1, 0);
+    for (int64_t g = 0; g < G; g++) {
+        int64_t na = tiles_of(a->t_off[g + 1] - a->t_off[g], tk);
+        int64_t nb = tiles_of(b->t_off[g + 1] - b->t_off[g], tk);
+        P.tileA[g + 1] = P.tileA[g] + na;
+        P.tileB[g + 1] = P.tileB[g] + nb;
+        P.blkA[g + 1] = P.blkA[g] + (na + 63) / 64;
+        P.chkB[g + 1] = P.chkB[g] + (nb + 255) / 256;
+        // a row with an empty side has no work items
+        P.wi[g + 1] = P.wi[g] + (na > 0 && nb > 0 ? ((na + 63) / 64) * ((nb + 255) / 256) : 0);
+        P.potential += na * nb;
+    }
+    // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
+    // B v_off | B t_off | B tiles | work items | A blocks | B chunks]
+    const int64_t G1 = G + 1;
+    int64_t *hs = (int64_t *)ensure_pinned(ctx, sizeof(int64_t) * 9 * G1);
+    memcpy(hs, a->v_off, sizeof(int64_t) * G1);
+    memcpy(hs + G1, a->t_off, sizeof(int64_t) * G1);
+    memcpy(hs + 2 * G1, P.tileA.data(), sizeof(int64_t) * G1);
+    memcpy(hs + 3 * G1, b->v_off, sizeof(int64_t) * G1);
+    memcpy(hs + 4 * G1, b->t_off, sizeof(int64_t) * G1);
+    memcpy(hs + 5 * G1, P.tileB.data(), sizeof(int64_t) * G1);
+    memcpy(hs + 6 * G1, P.wi.data(), sizeof(int64_t) * G1);
+    memcpy(hs + 7 * G1, P.blkA.data(), sizeof(int64_t) * G1);
+    memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
+    int64_t *ds = (int64_t *)ensure(ws.small, sizeof(int64_t) * 9 * G1);
+    check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
+    setup_side(ws, 0, a, P.tileA[G], tk, ds, C.A, s);
+    setup_side(ws, 1, b, P.tileB[G], tk, ds + 3 * G1, C.B, s);
+    {
+        int64_t n = C.A.nt + C.B.nt;
+        int64_t nb = (n + 4095) / 4096 + 1;
+        C.PB.keys[0] = (uint64_t *)ensure(ws.keys0, sizeof(uint64_t) * n);
+        C.PB.keys[1] = (uint64_t *)ensure(ws.keys1, sizeof(uint64_t) * n);
+        C.PB.vals[0] = (int32_t *)ensure(ws.vals0, sizeof(int32_t) * n);
+        C.PB.vals[1] = (int32_t *)ensure(ws.vals1, sizeof(int32_t) * n);
+        C.PB.hist = (uint32_t *)ensure(ws.hist, sizeof(uint32_t) * 256 * nb);
+        C.PB.part = (uint32_t *)ensure(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
+    }
+    QueueGeo &Q = C.Q;
+    Q.wi_off = ds + 6 * G1;
+    Q.blkA = ds + 7 * G1;
+    Q.chkB = ds + 8 * G1;
+    Q.gA = (GroupBox *)ensure(ws.grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
+    Q.gB = (GroupBox *)ensure(ws.grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
+    Q.wi_lb = (float *)ensure(ws.wi_lb, sizeof(float) * (P.wi[G] + 1));
+    Q.wlist = (int32_t *)ensure(ws.wlist, sizeof(int32_t) * (P.wi[G] + 1));
+    C.rows = (RowState *)ensure(ws.rows, sizeof(RowState) * (G > 0 ? G : 1));
+
+    Lists &L = C.L;
+    const int64_t budget = opts.queue_cap > 0 ? std::max<int64_t>(opts.queue_cap, QUEUE_MIN) : QUEUE_BUDGET;
+    unsigned int qcap = (unsigned int)std::min<int64_t>(std::max<int64_t>(P.potential, 1), budget);
+    L.queue = (int2 *)ensure(ws.queue, sizeof(int2) * qcap);
+    L.qlb = (float *)ensure(ws.qlb, sizeof(float) * qcap);
+    L.qcap = qcap;
+    L.rescue = (Rescue *)ensure(ws.rescue, sizeof(Rescue) * RESCUE_CAP);
+    L.rcap = RESCUE_CAP;
+    L.exact = (ExactItem *)ensure(ws.exact, sizeof(ExactItem) * EXACT_CAP);
+    L.xcap = EXACT_CAP;
+    unsigned int *sc = (unsigned int *)ensure(ws.scalars, SCALAR_BYTES);
+    C.sc = sc;
+    C.flags = sc + 12;
+    L.qcount = sc;
+    L.qhead = sc + 1;
+    L.rcount = sc + 2;
+    L.rhead = sc + 3;
+    L.xcount = sc + 4;
+    L.counters = (unsigned long long *)(sc + 16);
+    Q.wcount = sc + 8;  // [8] seeding, [9] filtering
+    L.seed_pass = 0;
+    L.log = mode == 0 ? opts.log : nullptr;
+    L.log_cap = (unsigned long long)opts.log_cap;
+    L.log_count = L.counters + C_LOGGED;
+
+    const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
+    int &gp = ctx->pairs_grid[prec][mode][tk_index(tk)];
+    if (gp == 0) gp = ctx->cus * pairs_blocks_per_cu(prec, mode, tk);
+    C.grid_pairs = gp;
+    // the queue holds at most qcap tile pairs: split the work items into
+    // passes whose potential tile pairs fit
+    C.n_wi = P.wi[G];
+    C.per_pass = P.potential <= (int64_t)qcap ? std::max<int64_t>(C.n_wi, 1)
+                                              : std::max<int64_t>(1, qcap / QUEUE_MIN);
+    C.passes = (int)((C.n_wi + C.per_pass - 1) / C.per_pass);
+    Q.compact = C.n_wi <= C.per_pass ? 1 : 0;
+    C.seed = mode == 0 && opts.order != SD3_ORDER_NONE && C.n_wi > 0;
+    if (C.seed) {
+        C.seedq = (int2 *)ensure(ws.seedq, sizeof(int2) * (G + 1));
+        C.seedlb = (float *)ensure(ws.seedlb, sizeof(float) * (G + 1));
+    }
+    if (a->mem == SD3_MEM_DEVICE) {
+        C.dd = dist;
+        C.hd = hit;
+    } else {
+        char *ob = (char *)ensure(ws.out_d, (sizeof(double) + 8) * (G > 0 ? G : 1));
+        C.dd = dist ? (double *)ob : nullptr;
+        C.hd = hit ? (uint8_t *)(ob + sizeof(double) * G) : nullptr;
+    }
+}
+
+// Device validation of device-resident inputs (flags in the scalar block).
+void enqueue_validate(const Call &C, const sd3_geoms *a, hipStream_t s) {
+    launch_fill_u32(C.flags, 2, 0u, s);
+    if (a->mem != SD3_MEM_DEVICE) return;  // host inputs were checked on the host
+    launch_validate(C.A.xyz, C.A.nv, C.A.tri, C.A.nt, C.A.v_off, C.A.t_off, C.A.G, C.flags, s);
+    launch_validate(C.B.xyz, C.B.nv, C.B.tri, C.B.nt, C.B.v_off, C.B.t_off, C.B.G, C.flags + 1, s);
+}
+
+// Every kernel of the call after validation, in stream order, with no host
+// synchronisation (graph capture records exactly this).
+void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, KernelEvents *kev) {
+    auto mark = [&](int k) {
+        if (clk) clk->mark(k);
+    };
+    SideBufs &A = C.A, &B = C.B;
+    QueueGeo &Q = C.Q;
+    Lists &L = C.L;
+    const int64_t G = C.P.G;
+    const int mode = C.mode;
+    const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
+    launch_prep(A, B, C.PB, key_bits(G), s, kev);
+    launch_group_boxes(A, Q.blkA, C.P.blkA[G], 64, Q.gA, s);
+    launch_group_boxes(B, Q.chkB, C.P.chkB[G], 256, Q.gB, s);
+    launch_rows_init(C.rows, G, A.rowbox, B.rowbox, s);
+    launch_reset_lists(L, s);
+    mark(2);
+    launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
+    if (mode == 0) launch_row_scale(C.rows, G, s);
+    for (int64_t w0 = 0; w0 < C.n_wi; w0 += C.per_pass) {
+        int64_t nw = std::min(C.per_pass, C.n_wi - w0);
+        if (w0 > 0) launch_reset_queue(L, s);
+        if (kev) kev->begin(KE_FILTER, s);
+        launch_queue(A, B, Q, nw, w0, C.rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
+        if (kev) kev->end(KE_FILTER, s);
+        if (C.seed) {
+            // seed round of this pass: each row's best-ranked queued tile pair
+            // is evaluated first (box bound or ranker order)
+            Lists LS = L;
+            LS.queue = C.seedq;
+            LS.qlb = C.seedlb;
+            LS.qcount = C.sc + 6;
+            LS.qhead = C.sc + 7;
+            LS.qcap = (unsigned int)(G > 0 ? G : 1);
+            LS.seed_pass = 1;
+            if (w0 > 0) launch_seed_reset(C.rows, G, LS.qcount, LS.qhead, s);
+            launch_rank(A, B, C.rows, L, C.opts.order == SD3_ORDER_LEARNED ? C.opts.ranker : nullptr,
+                        ctx->cus * 2, s);
+            launch_seed_build(C.rows, G, L, C.seedq, C.seedlb, LS.qcount, s);
+            launch_pairs(A, B, C.rows, LS, prec, mode, C.grid_pairs, s);
+        }
+        if (w0 == 0) mark(3);
+        if (kev) kev->begin(KE_PAIRS, s);
+        launch_pairs(A, B, C.rows, L, prec, mode, C.grid_pairs, s);
+        if (kev) kev->end(KE_PAIRS, s);
+    }
+    if (C.n_wi == 0) mark(3);
+    mark(4);
+    if (prec == 0) launch_rescue(A, B, C.rows, L, mode, ctx->cus * 4, s);
+    mark(5);
+    launch_exact(A, B, C.rows, L, mode, 64, s);
+    mark(6);
+    launch_finalize(C.rows, G, C.dd, C.hd, L, C.flags, s);
+}
+
+sd3_status flags_status(sd3_ctx *ctx, const unsigned int *sc_h) {
+    uint32_t f = sc_h[12] | sc_h[13];
+    if (f & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
+    if (f & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
+    if (f & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside its row");
+    return SD3_OK;
+}
+
+// Status of a finished call from its scalars and counters (read back).
+sd3_status call_status(sd3_ctx *ctx, const Call &C, const unsigned int *sc_h,
+                       const unsigned long long *cnt_h) {
+    sd3_status st = flags_status(ctx, sc_h);
+    if (st != SD3_OK) return st;
+    if (sc_h[0] > C.L.qcap || cnt_h[C_QUEUE_OVF] != 0) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
+    if (sc_h[2] > C.L.rcap) return fail(ctx, SD3_E_CAPACITY, "rescue list overflow");
+    if (sc_h[4] > C.L.xcap) return fail(ctx, SD3_E_CAPACITY, "exact list overflow");
+    return SD3_OK;
+}
+
+void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long long *cnt_h,
+                 sd3_stats *stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->tile_pairs_total = C.P.potential;
+    stats->tile_pairs_candidate = (int64_t)(cnt_h[C_TP_CAND] + sc_h[0]);
+    stats->tile_pairs_evaluated = (int64_t)cnt_h[C_TP_EVAL];
+    stats->tri_pairs_boxed = (int64_t)cnt_h[C_TRI_BOXED];
+    stats->tri_pairs_fp32 = (int64_t)cnt_h[C_TRI32];
+    stats->tri_pairs_fp64 = (int64_t)cnt_h[C_TRI64];
+    stats->rescued = (int64_t)cnt_h[C_RESCUED];
+    stats->exact = (int64_t)cnt_h[C_EXACT];
+    stats->logged = (int64_t)cnt_h[C_LOGGED];
+    stats->sort_items = C.A.nt + C.B.nt;
+    stats->sort_key_bytes = key_bits(C.P.G) + 1 <= 32 ? 4 : 8;
+    stats->sort_passes = (key_bits(C.P.G) + 1 + 7) / 8;
+    stats->tile = C.P.tk;
+    stats->queue_passes = C.passes;
+}
+
+sd3_status device_error(sd3_ctx *ctx, const HipError &e) {
+    (void)hipGetLastError();
+    if (e.e == hipErrorOutOfMemory) return fail(ctx, SD3_E_NOMEM, std::string(e.what) + ": out of device memory");
+    return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+}
+
 sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist, uint8_t *hit,
                const sd3_opts *opts_in, sd3_stats *stats, void *stream, int mode) {
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx) return SD3_E_INVALID_ARG;
     ctx->err.clear();
-    std::string msg;
-    sd3_status st = check_geoms(a, msg);
-    if (st == SD3_OK) st = check_geoms(b, msg);
-    if (st != SD3_OK) return fail(ctx, st, msg);
-    if (a->count != b->count) return fail(ctx, SD3_E_INVALID_ARG, "batches differ in count");
-    if (a->mem != b->mem) return fail(ctx, SD3_E_INVALID_ARG, "batches differ in memory kind");
-    if ((mode == 0 && !dist) || (mode == 1 && !hit))
-        return fail(ctx, SD3_E_INVALID_ARG, "output pointer is NULL");
     sd3_opts opts;
-    sd3_default_opts(&opts);
-    if (opts_in) opts = *opts_in;
-    if (opts.precision != SD3_PREC_FP32_RESCUE && opts.precision != SD3_PREC_FP64)
-        return fail(ctx, SD3_E_INVALID_ARG, "unknown precision");
-    if (opts.order != SD3_ORDER_BOUND && opts.order != SD3_ORDER_NONE &&
-        opts.order != SD3_ORDER_LEARNED)
-        return fail(ctx, SD3_E_INVALID_ARG, "unknown order");
-    if (opts.order == SD3_ORDER_LEARNED && !opts.ranker)
-        return fail(ctx, SD3_E_INVALID_ARG, "SD3_ORDER_LEARNED needs opts.ranker");
-    if (opts.log && (opts.log_cap < 0 || a->mem != SD3_MEM_DEVICE))
-        return fail(ctx, SD3_E_INVALID_ARG, "log needs a device buffer and log_cap >= 0");
-    if (a->mem == SD3_MEM_HOST) {
-        st = check_host_data(a, msg);
-        if (st == SD3_OK) st = check_host_data(b, msg);
-        if (st != SD3_OK) return fail(ctx, st, msg);
-    }
-    const int64_t G = a->count;
+    sd3_status st = check_call(ctx, a, b, dist, hit, opts_in, mode, opts);
+    if (st != SD3_OK) return st;
+    const int tk = choose_tile(ctx, opts, mode, a, b);
     hipStream_t s = (hipStream_t)stream;
     try {
         check(hipSetDevice(ctx->device), "hipSetDevice");
-        // plan: tiles per row and queue work items
-        Plan P;
-        P.G = G;
-        P.tileA.assign(G + 1, 0);
-        P.tileB.assign(G + 1, 0);
-        P.wi.assign(G + 1, 0);
-        P.blkA.assign(G + 1, 0);
-        P.chkB.assign(G + 1, 0);
-        for (int64_t g = 0; g < G; g++) {
-            int64_t na = tiles_of(a->t_off[g + 1] - a->t_off[g]);
-            int64_t nb = tiles_of(b->t_off[g + 1] - b->t_off[g]);
-            P.tileA[g + 1] = P.tileA[g] + na;
-            P.tileB[g + 1] = P.tileB[g] + nb;
-            P.blkA[g + 1] = P.blkA[g] + (na + 63) / 64;
-            P.chkB[g + 1] = P.chkB[g] + (nb + 255) / 256;
-            // a row with an empty side has no work items
-            P.wi[g + 1] = P.wi[g] + (na > 0 && nb > 0 ? ((na + 63) / 64) * ((nb + 255) / 256) : 0);
-            P.potential += na * nb;
-        }
         PhaseClock clk{ctx, s, opts.timing != 0};
         clk.mark(0);
-        // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
-        // B v_off | B t_off | B tiles | work items | A blocks | B chunks]
-        const int64_t G1 = G + 1;
-        int64_t *hs = (int64_t *)ensure_pinned(ctx, sizeof(int64_t) * 9 * G1);
-        memcpy(hs, a->v_off, sizeof(int64_t) * G1);
-        memcpy(hs + G1, a->t_off, sizeof(int64_t) * G1);
-        memcpy(hs + 2 * G1, P.tileA.data(), sizeof(int64_t) * G1);
-        memcpy(hs + 3 * G1, b->v_off, sizeof(int64_t) * G1);
-        memcpy(hs + 4 * G1, b->t_off, sizeof(int64_t) * G1);
-        memcpy(hs + 5 * G1, P.tileB.data(), sizeof(int64_t) * G1);
-        memcpy(hs + 6 * G1, P.wi.data(), sizeof(int64_t) * G1);
-        memcpy(hs + 7 * G1, P.blkA.data(), sizeof(int64_t) * G1);
-        memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
-        int64_t *ds = (int64_t *)ensure(ctx->small, sizeof(int64_t) * 9 * G1);
-        check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
-        SideBufs A{}, B{};
-        setup_side(ctx, 0, a, P.tileA[G], ds, A, s);
-        setup_side(ctx, 1, b, P.tileB[G], ds + 3 * G1, B, s);
+        Call C;
+        plan_call(ctx, ctx->ws, a, b, opts, mode, tk, dist, hit, C, s);
+        char *rb = readback_area(ctx);
+        const unsigned int *sc_h = (const unsigned int *)rb;
+        const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
+        enqueue_validate(C, a, s);
         if (a->mem == SD3_MEM_DEVICE) {
-            st = validate_device(ctx, a, A, b, B, s);
+            // device inputs are validated before any kernel reads them
+            check(hipMemcpyAsync(rb, C.sc, 64, hipMemcpyDeviceToHost, s), "D2H flags");
+            check(hipStreamSynchronize(s), "sync");
+            st = flags_status(ctx, sc_h);
             if (st != SD3_OK) return st;
         }
         clk.mark(1);
-        PrepBufs PB{};
-        {
-            int64_t n = A.nt + B.nt;
-            int64_t nb = (n + 4095) / 4096 + 1;
-            PB.keys[0] = (uint64_t *)ensure(ctx->keys0, sizeof(uint64_t) * n);
-            PB.keys[1] = (uint64_t *)ensure(ctx->keys1, sizeof(uint64_t) * n);
-            PB.vals[0] = (int32_t *)ensure(ctx->vals0, sizeof(int32_t) * n);
-            PB.vals[1] = (int32_t *)ensure(ctx->vals1, sizeof(int32_t) * n);
-            PB.hist = (uint32_t *)ensure(ctx->hist, sizeof(uint32_t) * 256 * nb);
-            PB.part = (uint32_t *)ensure(ctx->part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
-        }
         KernelEvents *kev = nullptr;
         if (opts.timing) {
             if (!ctx->kev) {
@@ -358,153 +616,27 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
             kev = ctx->kev;
             for (int c = 0; c < KE_CLASSES; c++) kev->n[c] = 0;
         }
-        launch_prep(A, B, PB, key_bits(G), s, kev);
-        QueueGeo Q{};
-        Q.wi_off = ds + 6 * G1;
-        Q.blkA = ds + 7 * G1;
-        Q.chkB = ds + 8 * G1;
-        Q.gA = (GroupBox *)ensure(ctx->grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
-        Q.gB = (GroupBox *)ensure(ctx->grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
-        Q.wi_lb = (float *)ensure(ctx->wi_lb, sizeof(float) * (P.wi[G] + 1));
-        Q.wlist = (int32_t *)ensure(ctx->wlist, sizeof(int32_t) * (P.wi[G] + 1));
-        launch_group_boxes(A, Q.blkA, P.blkA[G], 64, Q.gA, s);
-        launch_group_boxes(B, Q.chkB, P.chkB[G], 256, Q.gB, s);
-        RowState *rows = (RowState *)ensure(ctx->rows, sizeof(RowState) * (G > 0 ? G : 1));
-        launch_rows_init(rows, G, A.rowbox, B.rowbox, s);
-
-        Lists L{};
-        unsigned int qcap = (unsigned int)std::min<int64_t>(std::max<int64_t>(P.potential, 1), QUEUE_BUDGET);
-        L.queue = (int2 *)ensure(ctx->queue, sizeof(int2) * qcap);
-        L.qlb = (float *)ensure(ctx->qlb, sizeof(float) * qcap);
-        L.qcap = qcap;
-        L.rescue = (Rescue *)ensure(ctx->rescue, sizeof(Rescue) * RESCUE_CAP);
-        L.rcap = RESCUE_CAP;
-        L.exact = (ExactItem *)ensure(ctx->exact, sizeof(ExactItem) * EXACT_CAP);
-        L.xcap = EXACT_CAP;
-        // device scalars (64 B) followed by the counters, read back in one copy
-        unsigned int *sc = (unsigned int *)ensure(ctx->scalars, 64 + sizeof(unsigned long long) * C_NCOUNTERS);
-        L.qcount = sc;
-        L.qhead = sc + 1;
-        L.rcount = sc + 2;
-        L.rhead = sc + 3;
-        L.xcount = sc + 4;
-        L.counters = (unsigned long long *)(sc + 16);
-        Q.wcount = sc + 8;  // [8] seeding, [9] filtering
-        L.seed_pass = 0;
-        L.log = mode == 0 ? opts.log : nullptr;
-        L.log_cap = (unsigned long long)opts.log_cap;
-        L.log_count = L.counters + C_LOGGED;
-        launch_reset_lists(L, s);
-        clk.mark(2);
-        const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
-        int &gp = ctx->pairs_grid[prec][mode];
-        if (gp == 0) gp = ctx->cus * pairs_blocks_per_cu(prec, mode);
-        const int grid_pairs = gp;
-        // the queue holds at most qcap tile pairs: split the work items into
-        // passes whose potential tile pairs fit
-        int64_t n_wi = P.wi[G];
-        int64_t per_pass = P.potential <= (int64_t)qcap ? std::max<int64_t>(n_wi, 1)
-                                                        : std::max<int64_t>(1, qcap / (64 * 256));
-        launch_queue(A, B, Q, n_wi, 0, rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
-        std::vector<unsigned long long> cand_total(1, 0);
-        if (mode == 0) launch_row_scale(rows, G, s);
-        // seed round: single queue pass, distance only
-        const bool seed = mode == 0 && opts.order != SD3_ORDER_NONE && n_wi <= per_pass;
-        Q.compact = n_wi <= per_pass ? 1 : 0;
-        for (int64_t w0 = 0; w0 < n_wi; w0 += per_pass) {
-            int64_t nw = std::min(per_pass, n_wi - w0);
-            if (w0 > 0) launch_reset_queue(L, s);
-            if (kev) kev->begin(KE_FILTER, s);
-            launch_queue(A, B, Q, nw, w0, rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
-            if (kev) kev->end(KE_FILTER, s);
-            if (seed) {
-                int2 *sq = (int2 *)ensure(ctx->seedq, sizeof(int2) * (G + 1));
-                float *sl = (float *)ensure(ctx->seedlb, sizeof(float) * (G + 1));
-                launch_rank(A, B, rows, L, opts.order == SD3_ORDER_LEARNED ? opts.ranker : nullptr,
-                            ctx->cus * 2, s);
-                Lists LS = L;
-                LS.queue = sq;
-                LS.qlb = sl;
-                LS.qcount = sc + 6;
-                LS.qhead = sc + 7;
-                LS.qcap = (unsigned int)(G > 0 ? G : 1);
-                LS.seed_pass = 1;
-                launch_seed_build(rows, G, L, sq, sl, LS.qcount, s);
-                launch_pairs(A, B, rows, LS, prec, mode, grid_pairs, s);
-            }
-            if (w0 == 0) clk.mark(3);
-            if (kev) kev->begin(KE_PAIRS, s);
-            launch_pairs(A, B, rows, L, prec, mode, grid_pairs, s);
-            if (kev) kev->end(KE_PAIRS, s);
-            if (n_wi > per_pass) {
-                unsigned int *qh = (unsigned int *)readback_area(ctx);
-                check(hipMemcpyAsync(qh, L.qcount, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "D2H qcount");
-                check(hipStreamSynchronize(s), "sync");
-                unsigned int qc = *qh;
-                if (qc > qcap) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
-                cand_total[0] += qc;
-            }
-        }
-        if (n_wi == 0) clk.mark(3);
-        clk.mark(4);
-        if (prec == 0) launch_rescue(A, B, rows, L, mode, ctx->cus * 4, s);
-        clk.mark(5);
-        launch_exact(A, B, rows, L, mode, 64, s);
-        clk.mark(6);
-        // counters first: an overflow is reported before any output is written
-        char *rb = readback_area(ctx);
-        check(hipMemcpyAsync(rb, sc, 64 + sizeof(unsigned long long) * C_NCOUNTERS, hipMemcpyDeviceToHost, s),
-              "D2H counters");
-        const unsigned int *sc_h = (const unsigned int *)rb;
-        const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
+        enqueue_pipeline(ctx, C, s, &clk, kev);
+        if (a->mem == SD3_MEM_DEVICE) clk.mark(7);
+        // scalars and counters: an error leaves the outputs untouched (the
+        // final kernel did not write them)
+        check(hipMemcpyAsync(rb, C.sc, SCALAR_BYTES, hipMemcpyDeviceToHost, s), "D2H counters");
         check(hipStreamSynchronize(s), "sync");
         check(hipGetLastError(), "kernel launch");
-        if (n_wi <= per_pass) {
-            if (sc_h[0] > qcap) return fail(ctx, SD3_E_CAPACITY, "tile-pair queue overflow");
-            cand_total[0] = sc_h[0];
-        }
-        if (sc_h[2] > L.rcap) return fail(ctx, SD3_E_CAPACITY, "rescue list overflow");
-        if (sc_h[4] > L.xcap) return fail(ctx, SD3_E_CAPACITY, "exact list overflow");
-        // outputs
-        double *dd = nullptr;
-        uint8_t *hd = nullptr;
-        if (a->mem == SD3_MEM_DEVICE) {
-            dd = dist;
-            hd = hit;
-        } else {
-            char *ob = (char *)ensure(ctx->out_d, (sizeof(double) + 8) * (G > 0 ? G : 1));
-            dd = dist ? (double *)ob : nullptr;
-            hd = hit ? (uint8_t *)(ob + sizeof(double) * G) : nullptr;
-        }
-        launch_finalize(rows, G, dd, hd, s);
+        st = call_status(ctx, C, sc_h, cnt_h);
+        if (st != SD3_OK) return st;
+        const int64_t G = C.P.G;
         if (a->mem == SD3_MEM_HOST && G > 0) {
-            if (dist) check(hipMemcpyAsync(dist, dd, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H dist");
-            if (hit) check(hipMemcpyAsync(hit, hd, G, hipMemcpyDeviceToHost, s), "D2H hit");
-        }
-        clk.mark(7);
-        check(hipStreamSynchronize(s), "sync");
-        if (getenv("SD3_DEBUG_ROWS") && G > 0) {
-            std::vector<RowState> rh(std::min<int64_t>(G, 4));
-            check(hipMemcpy(rh.data(), rows, sizeof(RowState) * rh.size(), hipMemcpyDeviceToHost), "D2H rows");
-            for (size_t g = 0; g < rh.size(); g++) {
-                double ub, d2;
-                memcpy(&ub, &rh[g].ub, 8);
-                memcpy(&d2, &rh[g].d2, 8);
-                fprintf(stderr, "sd3 row %zu: ub %.17g d2 %.17g hit %u seed_q %d margin %.3g scale %.17g\n", g,
-                        ub, d2, rh[g].hit, rh[g].seed_q, rh[g].margin_scale, rh[g].scale);
-            }
+            if (dist) check(hipMemcpyAsync(dist, C.dd, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H dist");
+            if (hit) check(hipMemcpyAsync(hit, C.hd, G, hipMemcpyDeviceToHost, s), "D2H hit");
+            clk.mark(7);
+            check(hipStreamSynchronize(s), "sync");
+        } else if (a->mem == SD3_MEM_HOST) {
+            clk.mark(7);
+            check(hipStreamSynchronize(s), "sync");
         }
         if (stats) {
-            memset(stats, 0, sizeof(*stats));
-            stats->tile_pairs_total = P.potential;
-            stats->tile_pairs_candidate = (int64_t)cand_total[0];
-            stats->tile_pairs_evaluated = (int64_t)cnt_h[C_TP_EVAL];
-            stats->tri_pairs_boxed = (int64_t)cnt_h[C_TRI_BOXED];
-            stats->tri_pairs_fp32 = (int64_t)cnt_h[C_TRI32];
-            stats->tri_pairs_fp64 = (int64_t)cnt_h[C_TRI64];
-            stats->rescued = (int64_t)cnt_h[C_RESCUED];
-            stats->exact = (int64_t)cnt_h[C_EXACT];
-            stats->logged = (int64_t)cnt_h[C_LOGGED];
+            fill_counts(C, sc_h, cnt_h, stats);
             stats->ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             clk.read(stats->ms_phase);
@@ -519,14 +651,9 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
                     stats->ms_kernel[c] = ms;
                     stats->n_kernel[c] = std::min(kev->n[c], 16);
                 }
-            stats->sort_items = A.nt + B.nt;
-            stats->sort_key_bytes = key_bits(G) + 1 <= 32 ? 4 : 8;
-            stats->sort_passes = (key_bits(G) + 1 + 7) / 8;
         }
     } catch (const HipError &e) {
-        (void)hipGetLastError();
-        if (e.e == hipErrorOutOfMemory) return fail(ctx, SD3_E_NOMEM, std::string(e.what) + ": out of device memory");
-        return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+        return device_error(ctx, e);
     } catch (const std::bad_alloc &) {
         return fail(ctx, SD3_E_NOMEM, "host allocation failed");
     } catch (...) {
@@ -536,6 +663,16 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
 }
 
 }  // namespace
+
+struct sd3_graph {
+    sd3_ctx *ctx = nullptr;
+    Workspace ws;
+    Call C;
+    hipStream_t cs = nullptr;  // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *pin = nullptr;  // pinned readback of scalars and counters
+};
 
 namespace {
 
@@ -604,20 +741,10 @@ sd3_status sd3_create(sd3_ctx **out, int device) {
 sd3_status sd3_destroy(sd3_ctx *ctx) {
     if (!ctx) return SD3_OK;
     (void)hipSetDevice(ctx->device);
-    for (auto &sd : ctx->side) {
-        DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.v_off, &sd.t_off, &sd.tile_off, &sd.rowbox,
-                        &sd.t32, &sd.t64, &sd.meta};
-        for (DevBuf *b : bs) release(*b);
-    }
-    DevBuf *bs[] = {&ctx->rows, &ctx->wi_off, &ctx->queue, &ctx->qlb, &ctx->rescue, &ctx->exact,
-                    &ctx->counters, &ctx->scalars, &ctx->flags, &ctx->out_d, &ctx->out_h,
-                    &ctx->keys0, &ctx->keys1, &ctx->vals0, &ctx->vals1, &ctx->hist, &ctx->part,
-                    &ctx->grpA, &ctx->grpB, &ctx->wi_lb, &ctx->seedq, &ctx->seedlb, &ctx->mlp,
-                    &ctx->wlist};
-    for (DevBuf *b : bs) release(*b);
+    ctx->ws.release_all();
+    release(ctx->mlp);
     for (hipEvent_t &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
-    release(ctx->small);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     if (ctx->kev) {
         for (auto &row : ctx->kev->ev)
@@ -637,6 +764,182 @@ sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, do
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
                           const sd3_opts *opts, sd3_stats *stats, void *stream) {
     return run(ctx, a, b, nullptr, hit, opts, stats, stream, 1);
+}
+
+sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
+                            double *dist, uint8_t *hit, const sd3_opts *opts_in, sd3_graph **out) {
+    if (!ctx || !out) return SD3_E_INVALID_ARG;
+    *out = nullptr;
+    ctx->err.clear();
+    if (kind != SD3_KIND_DISTANCE && kind != SD3_KIND_INTERSECTS)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown kind");
+    const int mode = kind == SD3_KIND_DISTANCE ? 0 : 1;
+    if (mode == 1) dist = nullptr;
+    sd3_opts opts;
+    sd3_status st = check_call(ctx, a, b, dist, hit, opts_in, mode, opts);
+    if (st != SD3_OK) return st;
+    if (a->mem != SD3_MEM_DEVICE) return fail(ctx, SD3_E_INVALID_ARG, "graphs need device-resident batches");
+    if (opts.timing || opts.log) return fail(ctx, SD3_E_INVALID_ARG, "graphs support neither timing nor log");
+    const int tk = choose_tile(ctx, opts, mode, a, b);
+    sd3_graph *g = new (std::nothrow) sd3_graph();
+    if (!g) return fail(ctx, SD3_E_NOMEM, "host allocation failed");
+    g->ctx = ctx;
+    bool capturing = false;
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        check(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "hipStreamCreate");
+        check(hipHostMalloc(&g->pin, SCALAR_BYTES, hipHostMallocDefault), "hipHostMalloc");
+        plan_call(ctx, g->ws, a, b, opts, mode, tk, dist, hit, g->C, g->cs);
+        // validate the current contents once, before anything reads them
+        enqueue_validate(g->C, a, g->cs);
+        check(hipMemcpyAsync(g->pin, g->C.sc, 64, hipMemcpyDeviceToHost, g->cs), "D2H flags");
+        check(hipStreamSynchronize(g->cs), "sync");
+        st = flags_status(ctx, (const unsigned int *)g->pin);
+        if (st == SD3_OK) {
+            check(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            capturing = true;
+            enqueue_validate(g->C, a, g->cs);
+            enqueue_pipeline(ctx, g->C, g->cs, nullptr, nullptr);
+            capturing = false;
+            check(hipStreamEndCapture(g->cs, &g->graph), "hipStreamEndCapture");
+            check(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+    } catch (const HipError &e) {
+        if (capturing) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(g->cs, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+        }
+        st = device_error(ctx, e);
+    } catch (const std::bad_alloc &) {
+        st = fail(ctx, SD3_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        st = fail(ctx, SD3_E_DEVICE, "unexpected error");
+    }
+    if (st != SD3_OK) {
+        std::string keep = ctx->err;
+        sd3_graph_destroy(g);
+        ctx->err = keep;
+        return st;
+    }
+    *out = g;
+    return SD3_OK;
+}
+
+sd3_status sd3_graph_launch(sd3_graph *g, void *stream) {
+    if (!g || !g->exec) return SD3_E_INVALID_ARG;
+    sd3_ctx *ctx = g->ctx;
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        check(hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+    } catch (const HipError &e) {
+        return device_error(ctx, e);
+    }
+    return SD3_OK;
+}
+
+sd3_status sd3_graph_result(sd3_graph *g, sd3_stats *stats, void *stream) {
+    if (!g || !g->exec) return SD3_E_INVALID_ARG;
+    sd3_ctx *ctx = g->ctx;
+    ctx->err.clear();
+    const unsigned int *sc_h = (const unsigned int *)g->pin;
+    const unsigned long long *cnt_h = (const unsigned long long *)((char *)g->pin + 64);
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t s = (hipStream_t)stream;
+        check(hipMemcpyAsync(g->pin, g->C.sc, SCALAR_BYTES, hipMemcpyDeviceToHost, s), "D2H counters");
+        check(hipStreamSynchronize(s), "sync");
+    } catch (const HipError &e) {
+        return device_error(ctx, e);
+    }
+    sd3_status st = call_status(ctx, g->C, sc_h, cnt_h);
+    if (st != SD3_OK) return st;
+    if (stats) fill_counts(g->C, sc_h, cnt_h, stats);
+    return SD3_OK;
+}
+
+sd3_status sd3_graph_destroy(sd3_graph *g) {
+    if (!g) return SD3_OK;
+    (void)hipSetDevice(g->ctx->device);
+    if (g->cs) (void)hipStreamSynchronize(g->cs);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cs) (void)hipStreamDestroy(g->cs);
+    if (g->pin) (void)hipHostFree(g->pin);
+    g->ws.release_all();
+    delete g;
+    return SD3_OK;
+}
+
+sd3_status sd3_autotune(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
+                        const sd3_opts *opts_in, int32_t reps, sd3_tune_report *report,
+                        void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    ctx->err.clear();
+    if (kind != SD3_KIND_DISTANCE && kind != SD3_KIND_INTERSECTS)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown kind");
+    if (reps < 1) return fail(ctx, SD3_E_INVALID_ARG, "reps < 1");
+    const int mode = kind == SD3_KIND_DISTANCE ? 0 : 1;
+    sd3_opts opts;
+    sd3_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    opts.timing = 0;
+    opts.log = nullptr;
+    std::string msg;
+    sd3_status st = check_geoms(a, msg);
+    if (st == SD3_OK) st = check_geoms(b, msg);
+    if (st != SD3_OK) return fail(ctx, st, msg);
+    if (a->count != b->count) return fail(ctx, SD3_E_INVALID_ARG, "batches differ in count");
+    const int64_t G = a->count;
+    // scratch outputs of the tuning calls
+    std::vector<double> hd_dist;
+    std::vector<uint8_t> hd_hit;
+    double *dist = nullptr;
+    uint8_t *hit = nullptr;
+    DevBuf dev_out;
+    try {
+        if (a->mem == SD3_MEM_DEVICE) {
+            check(hipSetDevice(ctx->device), "hipSetDevice");
+            char *o = (char *)ensure(dev_out, (sizeof(double) + 1) * (G > 0 ? G : 1));
+            dist = (double *)o;
+            hit = (uint8_t *)(o + sizeof(double) * (G > 0 ? G : 1));
+        } else {
+            hd_dist.resize(G > 0 ? G : 1);
+            hd_hit.resize(G > 0 ? G : 1);
+            dist = hd_dist.data();
+            hit = hd_hit.data();
+        }
+    } catch (const HipError &e) {
+        return device_error(ctx, e);
+    }
+    const int cand[3] = {32, 64, 128};
+    sd3_tune_report rep{};
+    double best_ms = 0.0;
+    for (int c = 0; c < 3; c++) {
+        opts.tile = cand[c];
+        std::vector<double> ms;
+        for (int r = 0; r <= reps && st == SD3_OK; r++) {
+            auto t0 = std::chrono::steady_clock::now();
+            st = run(ctx, a, b, mode == 0 ? dist : nullptr, hit, &opts, nullptr, stream, mode);
+            auto t1 = std::chrono::steady_clock::now();
+            if (r > 0) ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        if (st != SD3_OK) break;
+        std::sort(ms.begin(), ms.end());
+        rep.tile[c] = cand[c];
+        rep.ms[c] = ms[ms.size() / 2];
+        rep.n = c + 1;
+        if (c == 0 || rep.ms[c] < best_ms) {
+            best_ms = rep.ms[c];
+            rep.best = cand[c];
+        }
+    }
+    if (dev_out.p) release(dev_out);
+    if (st != SD3_OK) return st;
+    opts.tile = SD3_TILE_AUTO;
+    ctx->tuned[workload_key(opts, mode, a, b)] = rep.best;
+    if (report) *report = rep;
+    return SD3_OK;
 }
 
 sd3_status sd3_mlp_forward(sd3_ctx *ctx, const float *params, const float *x, int64_t n, float *y,

@@ -5,9 +5,11 @@
 
 namespace sd3 {
 
-// Triangles per tile: one tile is one wave's worth of triangles, so a tile
-// reduction is a single wave reduction and a tile pair is K*K = 4096 tests.
-constexpr int K = 64;
+// Triangles per tile (TK): 32, 64 (default) or 128, chosen per call.  A tile
+// is built by one wave, and a tile pair is TK*TK triangle-pair tests.
+constexpr int TK_DEFAULT = 64;
+constexpr int TK_MAX = 128;
+__host__ __device__ constexpr bool tile_size_ok(int tk) { return tk == 32 || tk == 64 || tk == 128; }
 constexpr int WG = 256;  // threads per workgroup in the tile-pair kernels
 
 constexpr double U64 = 1.1102230246251565e-16;  // 2^-53

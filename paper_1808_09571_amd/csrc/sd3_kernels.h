@@ -15,9 +15,10 @@ struct SideBufs {
     const int64_t *t_off;     // [G+1]
     const int64_t *tile_off;  // [G+1]
     int64_t G, nv, nt, NT;
+    int tk;                      // triangles per tile
     unsigned long long *rowbox;  // [G*6] ordered bits: lo xyz (min), hi xyz (max)
-    float *t32;                  // [NT*9*K]
-    double *t64;                 // [NT*9*K]
+    float *t32;                  // [NT*9*tk]: tile t, coordinate c, slot j at (t*9+c)*tk+j
+    double *t64;                 // [NT*9*tk]
     TileMeta *meta;              // [NT]
 };
 
@@ -84,6 +85,15 @@ struct Lists {
 // Validation flags.
 enum : uint32_t { V_NONFINITE = 1, V_RANGE = 2, V_INDEX = 4 };
 
+// A call failed on the device when either side's validation flags are set or
+// a work list overflowed (queue: this pass or an earlier one).
+__device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vflags) {
+    return (vflags && (vflags[0] | vflags[1]) != 0) || *L.qcount > L.qcap ||
+           L.counters[C_QUEUE_OVF] != 0 || *L.rcount > L.rcap || *L.xcount > L.xcap;
+}
+
+void launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
+
 void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
                      const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
                      hipStream_t s);
@@ -118,10 +128,7 @@ void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngrou
 enum : int { Q_SEED = 0, Q_GROUPS = 1, Q_FILTER_DIST = 2, Q_FILTER_HIT = 3 };
 void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
                   int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s);
-void launch_sort_queue(Lists &L, uint64_t *tmp_keys, int32_t *tmp_vals, uint64_t *keys2,
-                       int32_t *vals2, uint32_t *hist, int2 *queue2, float *qlb2,
-                       unsigned int n_max, hipStream_t s);
-int pairs_blocks_per_cu(int precision, int mode);
+int pairs_blocks_per_cu(int precision, int mode, int tk);
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
                   int mode, int grid, hipStream_t s);
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
@@ -134,9 +141,12 @@ void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
 void launch_row_scale(RowState *rows, int64_t G, hipStream_t s);
 void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
                  const float *ranker, int grid, hipStream_t s);
+void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount, unsigned int *seedhead,
+                       hipStream_t s);
 void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
                        unsigned int *seedcount, hipStream_t s);
-void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, hipStream_t s);
+void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
+                     const uint32_t *vflags, hipStream_t s);
 void launch_reset_lists(Lists &L, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);
 

@@ -26,6 +26,15 @@ __device__ __forceinline__ int64_t find_row(const int64_t *off, int64_t G, int64
     return lo;
 }
 
+// Vertex index of corner k of triangle t, local to its row of nvr vertices.
+// An index outside the row reads vertex 0 instead: kernels that run before the
+// validation flags are read (graph replays) never address memory outside the
+// row, and the flags keep such a call from writing results.
+__device__ __forceinline__ int64_t corner(const int32_t *tri, int64_t t, int k, int64_t nvr) {
+    int32_t v = tri[3 * t + k];
+    return (v >= 0 && (int64_t)v < nvr) ? (int64_t)v : 0;
+}
+
 __device__ __forceinline__ unsigned long long load_acq(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -65,6 +74,15 @@ __global__ void k_validate_tri(const int32_t *tri, int64_t nt, const int64_t *v_
         }
     }
     if (f) atomicOr(flags, f);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int n, uint32_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
 void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
@@ -179,10 +197,11 @@ __global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, cons
          t += (int64_t)gridDim.x * blockDim.x) {
         int64_t g = find_row(t_off, G, t);
         const double *X = xyz + 3 * v_off[g];
+        const int64_t nvr = v_off[g + 1] - v_off[g];
         uint32_t q[3];
         double cen[3] = {0.0, 0.0, 0.0};
         for (int v = 0; v < 3; v++) {
-            const double *p = X + 3 * (int64_t)tri[3 * t + v];
+            const double *p = X + 3 * corner(tri, t, v, nvr);
             cen[0] += p[0];
             cen[1] += p[1];
             cen[2] += p[2];
@@ -384,87 +403,100 @@ __global__ void k_narrow_keys(const uint64_t *in, uint32_t *out, int64_t n) {
     if (i < n) out[i] = (uint32_t)in[i];
 }
 
-// One wave per tile: gather the tile's triangles in sorted order, write the
-// FP64 and FP32 SoA copies and the tile metadata.
+// Tiles: gather each tile's triangles in sorted order and write the FP64 and
+// FP32 SoA copies and the tile metadata.
 struct TileJob {
     const double *xyz;
     const int32_t *tri;
     const int64_t *v_off, *t_off, *tile_off;
     int64_t G, NT;
+    int tk;
     const int32_t *sorted;
     float *t32;
     double *t64;
     TileMeta *meta;
 };
 
-__device__ void tile_one(const double *xyz, const int32_t *tri, const int64_t *v_off,
-                         const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t t,
-                         const int32_t *sorted, float *t32, double *t64, TileMeta *meta);
-
-// Both sides in one launch: waves [0, NT_A) build A's tiles, the rest B's.
-__global__ void k_tiles(TileJob A, TileJob B) {
-    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t < A.NT)
-        tile_one(A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, t, A.sorted, A.t32, A.t64, A.meta);
-    else if (t - A.NT < B.NT)
-        tile_one(B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, t - A.NT, B.sorted, B.t32, B.t64,
-                 B.meta);
-}
-
-__device__ void tile_one(const double *xyz, const int32_t *tri, const int64_t *v_off,
-                         const int64_t *t_off, const int64_t *tile_off, int64_t G, int64_t t,
-                         const int32_t *sorted, float *t32, double *t64, TileMeta *meta) {
-    int j = lane_id();
-    int64_t g = find_row(tile_off, G, t);
-    int64_t i = t - tile_off[g];
-    int64_t ntr = t_off[g + 1] - t_off[g];
-    int n = (int)min((int64_t)K, ntr - i * K);
-    int64_t pos = t_off[g] + i * K + (j < n ? j : n - 1);
-    int64_t tid = sorted[pos];
-    const double *X = xyz + 3 * v_off[g];
-    double v[9];
-    for (int k = 0; k < 3; k++) {
-        const double *p = X + 3 * (int64_t)tri[3 * tid + k];
-        v[3 * k] = p[0];
-        v[3 * k + 1] = p[1];
-        v[3 * k + 2] = p[2];
-    }
-    for (int c = 0; c < 9; c++) t64[(t * 9 + c) * K + j] = v[c];
+// Lane l of the wave owns slots l and l + 64 (the second only for tk = 128);
+// slots past the tile's last triangle repeat it, and slots past tk are not
+// written.
+__device__ void tile_one(const TileJob &J, int64_t t) {
+    const int lane = lane_id(), tk = J.tk;
+    const int64_t g = find_row(J.tile_off, J.G, t);
+    const int64_t i = t - J.tile_off[g];
+    const int64_t ntr = J.t_off[g + 1] - J.t_off[g];
+    const int n = (int)min((int64_t)tk, ntr - i * tk);
+    const double *X = J.xyz + 3 * J.v_off[g];
+    const int64_t nvr = J.v_off[g + 1] - J.v_off[g];
+    double v[2][9];
     double lo[3], hi[3], o[3];
     for (int k = 0; k < 3; k++) {
-        lo[k] = wave_min(fmin(v[k], fmin(v[3 + k], v[6 + k])));
-        hi[k] = wave_max(fmax(v[k], fmax(v[3 + k], v[6 + k])));
+        lo[k] = __builtin_inf();
+        hi[k] = -__builtin_inf();
+    }
+    for (int r = 0; r < 2; r++) {
+        const int j = lane + 64 * r;
+        const int64_t tri_id = J.sorted[J.t_off[g] + i * tk + min(j, n - 1)];
+        for (int k = 0; k < 3; k++) {
+            const double *p = X + 3 * corner(J.tri, tri_id, k, nvr);
+            v[r][3 * k] = p[0];
+            v[r][3 * k + 1] = p[1];
+            v[r][3 * k + 2] = p[2];
+        }
+        if (j < tk) {
+            for (int c = 0; c < 9; c++) J.t64[(t * 9 + c) * tk + j] = v[r][c];
+            for (int k = 0; k < 3; k++) {
+                lo[k] = fmin(lo[k], fmin(v[r][k], fmin(v[r][3 + k], v[r][6 + k])));
+                hi[k] = fmax(hi[k], fmax(v[r][k], fmax(v[r][3 + k], v[r][6 + k])));
+            }
+        }
+    }
+    for (int k = 0; k < 3; k++) {
+        lo[k] = wave_min(lo[k]);
+        hi[k] = wave_max(hi[k]);
         o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
     }
     double err = 0.0, rad = 0.0;
-    for (int vtx = 0; vtx < 3; vtx++) {
-        double e2 = 0.0;
-        for (int k = 0; k < 3; k++) {
-            double dlt = v[3 * vtx + k] - o[k];
-            float f = (float)dlt;
-            t32[(t * 9 + 3 * vtx + k) * K + j] = f;
-            double e = fabs((double)f - dlt) + U64 * fabs(dlt);
-            e2 += e * e;
-            rad = fmax(rad, fabs((double)f));
+    for (int r = 0; r < 2; r++) {
+        const int j = lane + 64 * r;
+        if (j >= tk) continue;
+        for (int vtx = 0; vtx < 3; vtx++) {
+            double e2 = 0.0;
+            for (int k = 0; k < 3; k++) {
+                double dlt = v[r][3 * vtx + k] - o[k];
+                float f = (float)dlt;
+                J.t32[(t * 9 + 3 * vtx + k) * tk + j] = f;
+                double e = fabs((double)f - dlt) + U64 * fabs(dlt);
+                e2 += e * e;
+                rad = fmax(rad, fabs((double)f));
+            }
+            err = fmax(err, sqrt(e2));
         }
-        err = fmax(err, sqrt(e2));
     }
     err = wave_max(err);
     rad = wave_max(rad);
-    if (j == 0) {
+    if (lane == 0) {
         TileMeta m;
         for (int k = 0; k < 3; k++) {
             m.o[k] = o[k];
             m.lo[k] = lo[k];
             m.hi[k] = hi[k];
-            m.rep[k] = v[k];
+            m.rep[k] = v[0][k];
         }
         m.eps = (float)(err * (1.0 + 0x1p-20) + 0x1p-1000);
         m.rad = (float)rad;
         m.row = (int32_t)g;
         m.n = n;
-        meta[t] = m;
+        J.meta[t] = m;
     }
+}
+
+// Both sides in one launch, one wave per tile: waves [0, NT_A) build A's
+// tiles, the rest B's.
+__global__ void k_tiles(TileJob A, TileJob B) {
+    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t < A.NT) tile_one(A, t);
+    else if (t - A.NT < B.NT) tile_one(B, t - A.NT);
 }
 
 static void rowbox(SideBufs &S, hipStream_t s) {
@@ -505,9 +537,10 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_
     }
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
-        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, P.vals[cur], A.t32, A.t64, A.meta};
-        TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, P.vals[cur] + A.nt, B.t32,
-                   B.t64, B.meta};
+        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
+                   A.t64, A.meta};
+        TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, P.vals[cur] + A.nt,
+                   B.t32, B.t64, B.meta};
         hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
     }
     if (kev) kev->end(KE_TILES, s);
@@ -881,7 +914,7 @@ __device__ __forceinline__ TP32 tp32_consts(const TileMeta &a, const TileMeta &b
 // Ranker features of a tile pair, length-normalised by the row scale (the
 // vertex-pair upper bound after seeding) and compressed with log2(1 + x):
 // box lower bound, the two tiles' box extents, box-centre distance, and the
-// two real triangle counts.
+// two real triangle counts (in units of 64 triangles).
 __device__ __forceinline__ void tp_features(const TileMeta &a, const TileMeta &b, double scale,
                                             float lbf, float *f) {
     double s = scale > 0.0 ? 1.0 / scale : 1.0;
@@ -894,8 +927,8 @@ __device__ __forceinline__ void tp_features(const TileMeta &a, const TileMeta &b
         c2 += d * d;
     }
     f[7] = log2f(1.0f + (float)(sqrt(c2) * s));
-    f[8] = (float)a.n * (1.0f / K);
-    f[9] = (float)b.n * (1.0f / K);
+    f[8] = (float)a.n * (1.0f / 64.0f);
+    f[9] = (float)b.n * (1.0f / 64.0f);
 }
 
 // Training target: log2 of the tile pair's smallest candidate distance (or a
@@ -976,23 +1009,25 @@ __device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned
     }
 }
 
-// Stage one tile into LDS (64 threads): FP32 copies shifted by sh, or FP64.
+// Stage slot j of one tile into LDS: FP32 copies shifted by sh, or FP64.
+template <int TK>
 __device__ __forceinline__ void stage32(float *dst, const float *src_tile, const float *sh, int j) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) dst[c * K + j] = src_tile[c * K + j] + (sh ? sh[c % 3] : 0.0f);
-    tri_prep32(TriRef<float>{dst + j, K});
+    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j] + (sh ? sh[c % 3] : 0.0f);
+    tri_prep32(TriRef<float>{dst + j, TK});
 }
 
+template <int TK>
 __device__ __forceinline__ void stage64(double *dst, const double *src_tile, int j) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) dst[c * K + j] = src_tile[c * K + j];
-    tri_prep64(TriRef<double>{dst + j, K});
+    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j];
+    tri_prep64(TriRef<double>{dst + j, TK});
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        double x0 = dst[(F_V + k) * K + j], x1 = dst[(F_V + 3 + k) * K + j],
-               x2 = dst[(F_V + 6 + k) * K + j];
-        dst[(F_LO + k) * K + j] = fmin(x0, fmin(x1, x2));
-        dst[(F_HI + k) * K + j] = fmax(x0, fmax(x1, x2));
+        double x0 = dst[(F_V + k) * TK + j], x1 = dst[(F_V + 3 + k) * TK + j],
+               x2 = dst[(F_V + 6 + k) * TK + j];
+        dst[(F_LO + k) * TK + j] = fmin(x0, fmin(x1, x2));
+        dst[(F_HI + k) * TK + j] = fmax(x0, fmax(x1, x2));
     }
 }
 
@@ -1024,16 +1059,19 @@ __device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, un
     }
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, int TK>
 __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *t64A,
                                                const TileMeta *mA, const float *t32B,
                                                const double *t64B, const TileMeta *mB,
                                                RowState *rows, Lists L) {
-    constexpr int NF = PREC == 0 ? F_NTRI32 : F_NTRI32;
+    static_assert(tile_size_ok(TK), "tile size");
+    constexpr int NF = F_NTRI32;
+    // phase 1 thread layout: thread -> (A slot a, quarter/eighth/half bq of B)
+    constexpr int BQ = WG / TK, NBQ = TK / BQ;
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
-    __shared__ Tt sA[NF * K];
-    __shared__ Tt sB[NF * K];
-    __shared__ uint16_t list[K * K];
+    __shared__ Tt sA[NF * TK];
+    __shared__ Tt sB[NF * TK];
+    __shared__ uint16_t list[TK * TK];
     __shared__ TPShared S;
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned qcount = min(*L.qcount, L.qcap);
@@ -1046,31 +1084,32 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
         __syncthreads();
         if ((unsigned)S.q >= qcount) break;
         if (S.live) {
-            if (tid < 64) {
-                if (PREC == 0) stage32((float *)sA, t32A + (int64_t)S.ta * 9 * K, S.c.sh, tid);
-                else stage64((double *)sA, t64A + (int64_t)S.ta * 9 * K, tid);
-            } else if (tid < 128) {
-                if (PREC == 0) stage32((float *)sB, t32B + (int64_t)S.tb * 9 * K, nullptr, tid - 64);
-                else stage64((double *)sB, t64B + (int64_t)S.tb * 9 * K, tid - 64);
+            // threads [0, TK) stage A's slots, threads [128, 128 + TK) B's
+            if (tid < TK) {
+                if (PREC == 0) stage32<TK>((float *)sA, t32A + (int64_t)S.ta * 9 * TK, S.c.sh, tid);
+                else stage64<TK>((double *)sA, t64A + (int64_t)S.ta * 9 * TK, tid);
+            } else if (tid >= 128 && tid < 128 + TK) {
+                if (PREC == 0) stage32<TK>((float *)sB, t32B + (int64_t)S.tb * 9 * TK, nullptr, tid - 128);
+                else stage64<TK>((double *)sB, t64B + (int64_t)S.tb * 9 * TK, tid - 128);
             }
             __syncthreads();
             // phase 1: triangle boxes, compacted into the LDS list
             {
-                int a = tid & 63, bq = tid >> 6;
+                int a = tid % TK, bq = tid / TK;
                 Tt alo[3], ahi[3];
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
-                    alo[k] = sA[(F_LO + k) * K + a];
-                    ahi[k] = sA[(F_HI + k) * K + a];
+                    alo[k] = sA[(F_LO + k) * TK + a];
+                    ahi[k] = sA[(F_HI + k) * TK + a];
                 }
-                for (int jb = 0; jb < 16; jb++) {
-                    int b = bq * 16 + jb;
+                for (int jb = 0; jb < NBQ; jb++) {
+                    int b = bq * NBQ + jb;
                     bool keep = a < S.na && b < S.nb;
                     if (MODE == 0) {
                         Tt g2 = 0;
 #pragma unroll
                         for (int k = 0; k < 3; k++) {
-                            Tt gp = fmax(fmax(sB[(F_LO + k) * K + b] - ahi[k], alo[k] - sB[(F_HI + k) * K + b]), (Tt)0);
+                            Tt gp = fmax(fmax(sB[(F_LO + k) * TK + b] - ahi[k], alo[k] - sB[(F_HI + k) * TK + b]), (Tt)0);
                             g2 += gp * gp;
                         }
                         if (PREC == 0) keep = keep && (float)g2 <= S.T2f;
@@ -1079,8 +1118,8 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                         Tt tol = PREC == 0 ? (Tt)S.c.box_tol : (Tt)0;
 #pragma unroll
                         for (int k = 0; k < 3; k++)
-                            keep = keep && sB[(F_LO + k) * K + b] - ahi[k] <= tol &&
-                                   alo[k] - sB[(F_HI + k) * K + b] <= tol;
+                            keep = keep && sB[(F_LO + k) * TK + b] - ahi[k] <= tol &&
+                                   alo[k] - sB[(F_HI + k) * TK + b] <= tol;
                     }
                     list_push(keep, a, b, list, &S.cnt);
                 }
@@ -1095,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
             for (unsigned k = tid; k < cnt; k += 256) {
                 int a = list[k] & 255, b = list[k] >> 8;
                 if (PREC == 0) {
-                    TriRef<float> TA{(float *)sA + a, K}, TB{(float *)sB + b, K};
+                    TriRef<float> TA{(float *)sA + a, TK}, TB{(float *)sB + b, TK};
                     if (MODE == 0) {
                         Pair32 r = pair32(TA, TB, S.c.elb);
                         tmin = fmin(tmin, (Tt)r.d2);
@@ -1115,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                         n_resc += c == 2;
                     }
                 } else {
-                    TriRef<double> TA{(double *)sA + a, K}, TB{(double *)sB + b, K};
+                    TriRef<double> TA{(double *)sA + a, TK}, TB{(double *)sB + b, TK};
                     // distance and intersects both use the full FP64 pair
                     // test: its separating-plane certificate settles the
                     // disjoint pairs whose orientation signs are exact zeros
@@ -1180,40 +1219,51 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     }
 }
 
-int pairs_blocks_per_cu(int precision, int mode) {
+template <int P, int M>
+static int occupancy_tk(int tk) {
     int n = 0;
-    hipError_t e;
-    if (precision == 0 && mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<0, 0>, WG, 0);
-    else if (precision == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<0, 1>, WG, 0);
-    else if (mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<1, 0>, WG, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<1, 1>, WG, 0);
-    if (e != hipSuccess || n < 1) n = 1;
-    return n;
+    hipError_t e = tk == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 32>, WG, 0)
+                   : tk == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 64>, WG, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 128>, WG, 0);
+    return e == hipSuccess && n >= 1 ? n : 1;
+}
+
+int pairs_blocks_per_cu(int precision, int mode, int tk) {
+    if (precision == 0) return mode == 0 ? occupancy_tk<0, 0>(tk) : occupancy_tk<0, 1>(tk);
+    return mode == 0 ? occupancy_tk<1, 0>(tk) : occupancy_tk<1, 1>(tk);
+}
+
+template <int P, int M>
+static void launch_pairs_tk(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int grid,
+                            hipStream_t s) {
+#define SD3_LAUNCH_PAIRS(T)                                                                          \
+    hipLaunchKernelGGL((k_pairs<P, M, T>), dim3(grid), dim3(WG), 0, s, A.t32, A.t64, A.meta, B.t32, \
+                       B.t64, B.meta, rows, L)
+    if (A.tk == 32) SD3_LAUNCH_PAIRS(32);
+    else if (A.tk == 64) SD3_LAUNCH_PAIRS(64);
+    else SD3_LAUNCH_PAIRS(128);
+#undef SD3_LAUNCH_PAIRS
 }
 
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
                   int mode, int grid, hipStream_t s) {
-#define SD3_LAUNCH_PAIRS(P, M)                                                                   \
-    hipLaunchKernelGGL((k_pairs<P, M>), dim3(grid), dim3(WG), 0, s, A.t32, A.t64, A.meta, B.t32, \
-                       B.t64, B.meta, rows, L)
-    if (precision == 0 && mode == 0) SD3_LAUNCH_PAIRS(0, 0);
-    else if (precision == 0) SD3_LAUNCH_PAIRS(0, 1);
-    else if (mode == 0) SD3_LAUNCH_PAIRS(1, 0);
-    else SD3_LAUNCH_PAIRS(1, 1);
-#undef SD3_LAUNCH_PAIRS
+    if (precision == 0 && mode == 0) launch_pairs_tk<0, 0>(A, B, rows, L, grid, s);
+    else if (precision == 0) launch_pairs_tk<0, 1>(A, B, rows, L, grid, s);
+    else if (mode == 0) launch_pairs_tk<1, 0>(A, B, rows, L, grid, s);
+    else launch_pairs_tk<1, 1>(A, B, rows, L, grid, s);
 }
 
 // ---------------------------------------------------------------------------
 // a5: FP64 rescue of the pairs the FP32 bounds did not settle
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_tri64(const double *t64, int tile, int slot, double *out) {
+__device__ __forceinline__ void load_tri64(const double *t64, int tk, int tile, int slot, double *out) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) out[c] = t64[((int64_t)tile * 9 + c) * K + slot];
+    for (int c = 0; c < 9; c++) out[c] = t64[((int64_t)tile * 9 + c) * tk + slot];
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMeta *mA,
-                                                const double *t64B, RowState *rows, Lists L) {
+                                                const double *t64B, RowState *rows, Lists L, int tk) {
     const unsigned n = min(*L.rcount, L.rcap);
     unsigned long long n64 = 0, nex = 0;
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1226,8 +1276,8 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
             double ub = bits_to_double(load_acq(&R->ub));
             if ((double)e.lb > ub + row_margin(*R, ub)) continue;
             double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(t64A, e.ta, a, ta);
-            load_tri64(t64B, e.tb, b, tb);
+            load_tri64(t64A, tk, e.ta, a, ta);
+            load_tri64(t64B, tk, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             Pair64 r = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1});
@@ -1246,8 +1296,8 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
             }
         } else {
             double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(t64A, e.ta, a, ta);
-            load_tri64(t64B, e.tb, b, tb);
+            load_tri64(t64A, tk, e.ta, a, ta);
+            load_tri64(t64B, tk, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             int f = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1}).status;
@@ -1272,9 +1322,9 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                    int grid, hipStream_t s) {
     if (mode == 0)
-        hipLaunchKernelGGL(k_rescue<0>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L);
+        hipLaunchKernelGGL(k_rescue<0>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L, A.tk);
     else
-        hipLaunchKernelGGL(k_rescue<1>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L);
+        hipLaunchKernelGGL(k_rescue<1>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L, A.tk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,15 +1332,15 @@ void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_exact(const double *t64A, const TileMeta *mA,
                                               const double *t64B, RowState *rows, Lists L,
-                                              int mode) {
+                                              int mode, int tk) {
     const unsigned n = min(*L.xcount, L.xcap);
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         ExactItem e = L.exact[i];
         RowState *R = rows + mA[e.ta].row;
         if (load_acq32(&R->hit)) continue;
         double va[9], vb[9];
-        load_tri64(t64A, e.ta, e.slots & 0xffff, va);
-        load_tri64(t64B, e.tb, e.slots >> 16, vb);
+        load_tri64(t64A, tk, e.ta, e.slots & 0xffff, va);
+        load_tri64(t64B, tk, e.tb, e.slots >> 16, vb);
         if (ex::tri_tri_exact(va, vb)) {
             atomicOr(&R->hit, 1u);
             atomic_min_pos(&R->d2, 0.0);
@@ -1302,7 +1352,7 @@ __global__ __launch_bounds__(64) void k_exact(const double *t64A, const TileMeta
 
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                   int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, A.t64, A.meta, B.t64, rows, L, mode);
+    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, A.t64, A.meta, B.t64, rows, L, mode, A.tk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1406,6 +1456,26 @@ __global__ void k_seed_build(RowState *rows, int64_t G, Lists L, int2 *seedq, fl
     seedlb[i] = L.qlb[q];
 }
 
+// Before each queue pass's seed round: no row has a choice yet, and the seed
+// list is empty.
+__global__ void k_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount,
+                             unsigned int *seedhead) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g == 0) {
+        *seedcount = 0;
+        *seedhead = 0;
+    }
+    if (g >= G) return;
+    rows[g].best = ~0ull;
+    rows[g].seed_q = -1;
+}
+
+void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount, unsigned int *seedhead,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_seed_reset, dim3(grid_for(G > 0 ? G : 1, 256)), dim3(256), 0, s, rows, G,
+                       seedcount, seedhead);
+}
+
 void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
                        unsigned int *seedcount, hipStream_t s) {
     if (G > 0)
@@ -1416,22 +1486,30 @@ void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *
 // ---------------------------------------------------------------------------
 // final reduction
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit) {
+// Writes the results unless the call failed on the device: a validation flag
+// is set or a work list overflowed (its count passed its capacity), in which
+// case the outputs stay untouched and the host reports the error.
+__global__ void k_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists L,
+                           const uint32_t *vflags) {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= G) return;
+    if (call_failed(L, vflags)) return;
     bool h = rows[g].hit != 0;
     if (dist) dist[g] = h ? 0.0 : sqrt(bits_to_double(rows[g].d2));
     if (hit) hit[g] = h ? 1 : 0;
 }
 
-void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, hipStream_t s) {
+void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
+                     const uint32_t *vflags, hipStream_t s) {
     if (G > 0)
-        hipLaunchKernelGGL(k_finalize, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, dist, hit);
+        hipLaunchKernelGGL(k_finalize, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, dist, hit, L,
+                           vflags);
 }
 
 __global__ void k_reset_lists(Lists L) {
     int i = threadIdx.x;
-    if (i < 16) L.qcount[i] = 0;  // the 16 device scalars (queue, rescue, exact, seed)
+    if (i < 12) L.qcount[i] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
+                                  // items); 12-13 hold the validation flags
     if (i < C_NCOUNTERS) L.counters[i] = 0;
 }
 
@@ -1439,8 +1517,13 @@ void launch_reset_lists(Lists &L, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_lists, dim3(1), dim3(64), 0, s, L);
 }
 
+// Between queue passes: the finished pass's count goes to the candidate
+// counter (an overflow is remembered) before the queue is emptied.
 __global__ void k_reset_queue(Lists L) {
     if (threadIdx.x == 0) {
+        unsigned int q = *L.qcount;
+        L.counters[C_TP_CAND] += q;
+        if (q > L.qcap) L.counters[C_QUEUE_OVF] += 1;
         *L.qcount = 0;
         *L.qhead = 0;
     }
@@ -1450,7 +1533,5 @@ void launch_reset_queue(Lists &L, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, L);
 }
 
-void launch_sort_queue(Lists &, uint64_t *, int32_t *, uint64_t *, int32_t *, uint32_t *, int2 *,
-                       float *, unsigned int, hipStream_t) {}
 
 }  // namespace sd3

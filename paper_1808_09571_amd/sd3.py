@@ -29,9 +29,13 @@ STATUS = {
     8: "SD3_E_CAPACITY",
 }
 
+KIND = {"distance": 0, "intersects": 1}
+TILES = (32, 64, 128)
+
 EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
-           "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step", "sd3_validate",
-           "sd3_status_string", "sd3_last_error"]
+           "sd3_graph_create", "sd3_graph_launch", "sd3_graph_result", "sd3_graph_destroy",
+           "sd3_autotune", "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step",
+           "sd3_validate", "sd3_status_string", "sd3_last_error"]
 
 
 class Geoms(ctypes.Structure):
@@ -41,9 +45,10 @@ class Geoms(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("ranker", ctypes.c_void_p), ("log", ctypes.c_void_p),
-                ("log_cap", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+                ("log_cap", ctypes.c_int64), ("queue_cap", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -54,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7),
                 ("logged", ctypes.c_int64), ("ms_kernel", ctypes.c_double * 4),
                 ("n_kernel", ctypes.c_int64 * 4), ("sort_items", ctypes.c_int64),
-                ("sort_key_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32)]
+                ("sort_key_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("queue_passes", ctypes.c_int32)]
 
     KERNELS = ("scatter", "tiles", "filter", "pairs")
 
@@ -67,6 +73,11 @@ class Stats(ctypes.Structure):
         d["ms_kernel"] = dict(zip(self.KERNELS, list(self.ms_kernel)))
         d["n_kernel"] = dict(zip(self.KERNELS, list(self.n_kernel)))
         return d
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("tile", ctypes.c_int32 * 4),
+                ("ms", ctypes.c_double * 4)]
 
 
 class SD3Error(RuntimeError):
@@ -119,6 +130,16 @@ def load(path: str = LIB_PATH):
     lib.sd3_adam_step.restype = ctypes.c_int
     lib.sd3_validate.argtypes = [P(Geoms)]
     lib.sd3_validate.restype = ctypes.c_int
+    lib.sd3_graph_create.argtypes = [vp, i32, P(Geoms), P(Geoms), vp, vp, P(Opts), P(vp)]
+    lib.sd3_graph_create.restype = ctypes.c_int
+    lib.sd3_graph_launch.argtypes = [vp, vp]
+    lib.sd3_graph_launch.restype = ctypes.c_int
+    lib.sd3_graph_result.argtypes = [vp, P(Stats), vp]
+    lib.sd3_graph_result.restype = ctypes.c_int
+    lib.sd3_graph_destroy.argtypes = [vp]
+    lib.sd3_graph_destroy.restype = ctypes.c_int
+    lib.sd3_autotune.argtypes = [vp, i32, P(Geoms), P(Geoms), P(Opts), i32, P(TuneReport), vp]
+    lib.sd3_autotune.restype = ctypes.c_int
     lib.sd3_status_string.argtypes = [ctypes.c_int]
     lib.sd3_status_string.restype = ctypes.c_char_p
     lib.sd3_last_error.argtypes = [ctypes.c_void_p]
@@ -197,11 +218,13 @@ class Context:
         raise SD3Error(st, self.lib.sd3_last_error(self.handle).decode())
 
     @staticmethod
-    def _opts(precision, order, timing=False, ranker=None, log=None):
+    def _opts(precision, order, timing=False, ranker=None, log=None, tile=0, queue_cap=0):
         o = Opts()
         o.precision = PREC[precision]
         o.order = ORDER[order]
         o.timing = 1 if timing else 0
+        o.tile = int(tile)
+        o.queue_cap = int(queue_cap)
         if ranker is not None:
             assert ranker.is_cuda and ranker.dtype.itemsize == 4 and ranker.numel() == MLP_NPARAM
             o.ranker = ranker.data_ptr()
@@ -229,15 +252,16 @@ class Context:
         return d, h, (d.ctypes.data if want_dist else None), h.ctypes.data
 
     def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                 timing=False, ranker=None, log=None):
+                 timing=False, ranker=None, log=None, tile=0, queue_cap=0):
         """Row-wise 3D distance (and the exact intersects flag as a by-product).
         order="learned" needs ``ranker`` (float32 [MLP_NPARAM] on the device);
         ``log`` (float32 [cap, LOG_STRIDE] on the device) receives one training
-        record per dequeued tile pair."""
+        record per dequeued tile pair.  ``tile``: 32, 64, 128, or 0 (tuned or
+        64); ``queue_cap``: candidate tile pairs per queue pass (0: default)."""
         ga, gb = a.geoms(), b.geoms()
         d, h, dp, hp = self._outputs(a, True)
         s = Stats()
-        o = self._opts(precision, order, timing, ranker, log)
+        o = self._opts(precision, order, timing, ranker, log, tile, queue_cap)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
@@ -245,17 +269,93 @@ class Context:
         return (d, h, s.as_dict()) if stats else (d, h)
 
     def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                   timing=False):
+                   timing=False, tile=0, queue_cap=0):
         """Row-wise exact 3D intersects."""
         ga, gb = a.geoms(), b.geoms()
         _, h, _, hp = self._outputs(a, False)
         s = Stats()
-        o = self._opts(precision, order, timing)
+        o = self._opts(precision, order, timing, tile=tile, queue_cap=queue_cap)
         st = self.lib.sd3_intersects(self.handle, ctypes.byref(ga), ctypes.byref(gb), hp,
                                      ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
             self._raise(st)
         return (h, s.as_dict()) if stats else h
+
+
+    def graph(self, kind, a: Batch, b: Batch, precision="fp32", order="bound", ranker=None,
+              tile=0, queue_cap=0):
+        """A HIP graph of one whole call over device batches (see Graph)."""
+        return Graph(self, kind, a, b, precision, order, ranker, tile, queue_cap)
+
+    def autotune(self, kind, a: Batch, b: Batch, precision="fp32", order="bound", ranker=None,
+                 reps=3, queue_cap=0):
+        """Time every tile size on this workload, remember the fastest for
+        calls with tile=0, and return {"best": size, "ms": {size: median ms}}."""
+        ga, gb = a.geoms(), b.geoms()
+        o = self._opts(precision, order, ranker=ranker, queue_cap=queue_cap)
+        r = TuneReport()
+        st = self.lib.sd3_autotune(self.handle, KIND[kind], ctypes.byref(ga), ctypes.byref(gb),
+                                   ctypes.byref(o), int(reps), ctypes.byref(r), self._stream(a))
+        if st != 0:
+            self._raise(st)
+        return {"best": r.best, "ms": {r.tile[i]: r.ms[i] for i in range(r.n)}}
+
+
+class Graph:
+    """One call (``kind`` "distance" or "intersects") recorded as a HIP graph
+    over device-resident batches: ``launch()`` replays it on the current
+    stream without host synchronisation, ``result()`` waits and checks it.
+    The outputs ``dist`` (distance) and ``hit`` are fixed device tensors that
+    every replay overwrites; the batches' contents may change between
+    replays, their shapes may not."""
+
+    def __init__(self, ctx: Context, kind, a: Batch, b: Batch, precision, order, ranker, tile,
+                 queue_cap):
+        import torch
+        assert a.on_device and b.on_device, "graphs need device batches"
+        self.ctx, self.lib = ctx, ctx.lib
+        self._keep = (a, b, ranker)  # the graph reads these buffers on every replay
+        dev = a.xyz.device
+        self.dist = torch.empty(a.count, dtype=torch.float64, device=dev) if kind == "distance" else None
+        self.hit = torch.empty(a.count, dtype=torch.uint8, device=dev)
+        self._ga, self._gb = a.geoms(), b.geoms()
+        o = Context._opts(precision, order, ranker=ranker, tile=tile, queue_cap=queue_cap)
+        h = ctypes.c_void_p()
+        st = self.lib.sd3_graph_create(ctx.handle, KIND[kind], ctypes.byref(self._ga),
+                                       ctypes.byref(self._gb),
+                                       self.dist.data_ptr() if self.dist is not None else None,
+                                       self.hit.data_ptr(), ctypes.byref(o), ctypes.byref(h))
+        if st != 0:
+            ctx._raise(st)
+        self.handle = h
+        self.device = dev
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def launch(self):
+        st = self.lib.sd3_graph_launch(self.handle, self._stream())
+        if st != 0:
+            self.ctx._raise(st)
+
+    def result(self, stats=False):
+        s = Stats()
+        st = self.lib.sd3_graph_result(self.handle, ctypes.byref(s), self._stream())
+        if st != 0:
+            self.ctx._raise(st)
+        return s.as_dict() if stats else None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sd3_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _dev(t, n=None, dtype_size=4):

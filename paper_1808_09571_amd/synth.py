@@ -134,13 +134,11 @@ def geodesic_sphere(freq: int):
     loc = -np.ones((n + 1, n + 1), dtype=np.int64)
     loc[ii, jj] = np.arange(ii.size)
     # local triangles on the lattice
-    tl = []
-    for i in range(n):
-        for j in range(n - i):
-            tl.append((loc[i, j], loc[i + 1, j], loc[i, j + 1]))
-            if i + j + 1 < n:
-                tl.append((loc[i + 1, j], loc[i + 1, j + 1], loc[i, j + 1]))
-    tl = np.asarray(tl, dtype=np.int64)
+    ui, uj = np.nonzero(np.add.outer(np.arange(n), np.arange(n)) < n)         # i + j < n
+    di, dj = np.nonzero(np.add.outer(np.arange(n), np.arange(n)) + 1 < n)     # i + j + 1 < n
+    up = np.stack([loc[ui, uj], loc[ui + 1, uj], loc[ui, uj + 1]], axis=1)
+    down = np.stack([loc[di + 1, dj], loc[di + 1, dj + 1], loc[di, dj + 1]], axis=1)
+    tl = np.concatenate([up, down])
     pts = []
     tris = []
     base = 0
@@ -280,21 +278,36 @@ def _perp(d):
     return _unit(np.cross(d, a))
 
 
+def _cross3(a, b):
+    return (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+
+
+def _unit3(v):
+    n = math.sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2])
+    return (v[0] / n, v[1] / n, v[2] / n)
+
+
 def polyline(n_seg, g: np.random.Generator, start, direction, step=(0.2, 0.4),
              max_turn_deg=5.0):
     """Gently curving 3D polyline: ``n_seg`` steps of length U[step], each turning by
-    at most ``max_turn_deg`` about a random axis."""
-    pts = [np.asarray(start, dtype=np.float64)]
-    d = _unit(np.asarray(direction, dtype=np.float64))
-    for _ in range(n_seg):
-        ang = math.radians(g.uniform(0.0, max_turn_deg))
-        ax = _perp(d)
-        phi = g.uniform(0.0, 2 * math.pi)
-        b = np.cross(d, ax)
-        ax = math.cos(phi) * ax + math.sin(phi) * b
-        d = _unit(math.cos(ang) * d + math.sin(ang) * ax)
-        pts.append(pts[-1] + g.uniform(*step) * d)
-    return np.asarray(pts)
+    at most ``max_turn_deg`` about a random axis (plain float arithmetic per
+    step; the random draws are made in bulk)."""
+    ang = np.radians(g.uniform(0.0, max_turn_deg, size=n_seg)).tolist()
+    phi = g.uniform(0.0, 2 * math.pi, size=n_seg).tolist()
+    stp = g.uniform(step[0], step[1], size=n_seg).tolist()
+    pts = [tuple(float(x) for x in start)]
+    d = _unit3(tuple(float(x) for x in direction))
+    for s in range(n_seg):
+        ref = (1.0, 0.0, 0.0) if abs(d[0]) < 0.9 else (0.0, 1.0, 0.0)
+        ax = _unit3(_cross3(d, ref))
+        b = _cross3(d, ax)
+        c, sn = math.cos(phi[s]), math.sin(phi[s])
+        ax = (c * ax[0] + sn * b[0], c * ax[1] + sn * b[1], c * ax[2] + sn * b[2])
+        ca, sa = math.cos(ang[s]), math.sin(ang[s])
+        d = _unit3((ca * d[0] + sa * ax[0], ca * d[1] + sa * ax[1], ca * d[2] + sa * ax[2]))
+        p = pts[-1]
+        pts.append((p[0] + stp[s] * d[0], p[1] + stp[s] * d[1], p[2] + stp[s] * d[2]))
+    return np.asarray(pts, dtype=np.float64)
 
 
 def tube(path, radius=0.05, sides=16):
@@ -318,19 +331,19 @@ def tube(path, radius=0.05, sides=16):
     ring = (np.cos(th)[None, :, None] * nrm[:, None, :] +
             np.sin(th)[None, :, None] * bin_[:, None, :]) * radius
     xyz = (path[:, None, :] + ring).reshape(-1, 3)
-    tri = []
-    for i in range(m - 1):
-        for k in range(sides):
-            a = i * sides + k
-            b = i * sides + (k + 1) % sides
-            c = a + sides
-            d = b + sides
-            tri += [(a, b, d), (a, d, c)]
+    i, k = np.meshgrid(np.arange(m - 1), np.arange(sides), indexing="ij")
+    a = (i * sides + k).reshape(-1)
+    b = (i * sides + (k + 1) % sides).reshape(-1)
+    c, d = a + sides, b + sides
+    side_tri = np.empty((2 * a.size, 3), dtype=np.int64)
+    side_tri[0::2] = np.stack([a, b, d], axis=1)
+    side_tri[1::2] = np.stack([a, d, c], axis=1)
     last = (m - 1) * sides
-    for k in range(1, sides - 1):
-        tri.append((0, k + 1, k))
-        tri.append((last, last + k, last + k + 1))
-    return xyz, np.asarray(tri, dtype=np.int32)
+    kk = np.arange(1, sides - 1)
+    caps = np.empty((2 * kk.size, 3), dtype=np.int64)
+    caps[0::2] = np.stack([np.zeros_like(kk), kk + 1, kk], axis=1)
+    caps[1::2] = np.stack([np.full_like(kk, last), last + kk, last + kk + 1], axis=1)
+    return xyz, np.concatenate([side_tri, caps]).astype(np.int32)
 
 
 def blob(n_tri_target, radius, center, seed, noise=0.3):

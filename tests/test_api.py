@@ -125,3 +125,64 @@ def test_create_without_gfx950_fails_cleanly(lib):
     h = ctypes.c_void_p(123)
     st = lib.sd3_create(ctypes.byref(h), 0)
     assert sd3.STATUS[st] == "SD3_E_NO_DEVICE" and h.value is None
+
+
+def test_graph_and_tune_entry_points_reject_null(lib):
+    assert sd3.STATUS[lib.sd3_graph_launch(None, None)] == "SD3_E_INVALID_ARG"
+    assert sd3.STATUS[lib.sd3_graph_result(None, None, None)] == "SD3_E_INVALID_ARG"
+    assert lib.sd3_graph_destroy(None) == 0
+    b = _batch([synth.cube()])
+    ga, gb = b.geoms(), b.geoms()
+    h = ctypes.c_void_p(7)
+    st = lib.sd3_graph_create(None, 0, ctypes.byref(ga), ctypes.byref(gb), None, None, None,
+                              ctypes.byref(h))
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+    st = lib.sd3_autotune(None, 0, ctypes.byref(ga), ctypes.byref(gb), None, 1, None, None)
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+
+
+def test_row_with_triangles_but_no_vertices_is_an_index_error():
+    xyz = np.zeros((3, 3))
+    tri = np.array([[0, 1, 2], [0, 1, 2]], dtype=np.int32)
+    b = sd3.Batch(xyz.reshape(-1), tri.reshape(-1), np.array([0, 3, 3], dtype=np.int64),
+                  np.array([0, 1, 2], dtype=np.int64))
+    assert sd3.STATUS[sd3.validate(b)] == "SD3_E_INDEX_RANGE"
+
+
+LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "sd3.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+    printf("sd3_opts %zu\nsd3_stats %zu\nsd3_geoms %zu\nsd3_tune_report %zu\n", sizeof(sd3_opts),
+           sizeof(sd3_stats), sizeof(sd3_geoms), sizeof(sd3_tune_report));
+    F(sd3_opts, tile); F(sd3_opts, ranker); F(sd3_opts, log_cap); F(sd3_opts, queue_cap);
+    F(sd3_stats, ms_total); F(sd3_stats, logged); F(sd3_stats, ms_kernel); F(sd3_stats, sort_items);
+    F(sd3_stats, tile); F(sd3_stats, queue_passes);
+    F(sd3_geoms, count); F(sd3_geoms, mem);
+    F(sd3_tune_report, best); F(sd3_tune_report, ms);
+    return 0;
+}
+"""
+
+
+def test_binding_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's sizes and offsets
+    (compiled with the host C compiler against include/sd3.h)."""
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+               if line)
+    py = {"sd3_opts": sd3.Opts, "sd3_stats": sd3.Stats, "sd3_geoms": sd3.Geoms,
+          "sd3_tune_report": sd3.TuneReport}
+    for k, v in got.items():
+        if "." in k:
+            t, m = k.split(".")
+            assert getattr(py[t], m).offset == int(v), k
+        else:
+            assert ctypes.sizeof(py[k]) == int(v), k
