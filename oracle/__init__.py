@@ -135,6 +135,12 @@ def vertex_face_d2(p, x, y, z, lib=None) -> float:
     return float(lib.sd3o_vertex_face_d2(*[q[1] for q in ps]))
 
 
+def default_threads():
+    """OMP_NUM_THREADS when set (the host's CPU share), else every core."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
+
+
 def mesh(A, B, mode="all", want="distance", threads=None, lib=None):
     """Distance and intersects between meshes A=(xyz, tri) and B.
 
@@ -152,7 +158,7 @@ def mesh(A, B, mode="all", want="distance", threads=None, lib=None):
         if t.size and (t.min() < 0 or t.max() >= x.size // 3):
             raise ValueError("triangle index out of range")
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     d = ctypes.c_double(math.nan)
     h = ctypes.c_int(0)
     tests = lib.sd3o_mesh(xa.ctypes.data_as(_D), ta.ctypes.data_as(_I32), ta.size // 3,

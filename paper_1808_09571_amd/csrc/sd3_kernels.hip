@@ -954,6 +954,7 @@ struct TPShared {
     int q, live, ta, tb, g, na, nb, logged;
     float lbf;
     double ub, m;
+    double ub_now;    // row upper bound + margin after this tile pair (rescue limit)
     float T2f;        // FP32 triangle-box cull threshold (squared)
     double T2d;       // FP64 triangle-box cull threshold (squared)
     TP32 c;
@@ -1031,15 +1032,22 @@ __device__ __forceinline__ void stage64(double *dst, const double *src_tile, int
     }
 }
 
-// Ballot-compacted append of (a | b << 8) to the LDS pair list.
-__device__ __forceinline__ void list_push(bool keep, int a, int b, uint16_t *list,
+// Ballot-compacted append of (a | b << 8) to the LDS pair list (the upper 16
+// bits of an entry are filled later with the pair's lower bound).
+__device__ __forceinline__ void list_push(bool keep, int a, int b, uint32_t *list,
                                           unsigned int *cnt) {
     unsigned long long m = __ballot(keep);
     if (m == 0) return;
     unsigned int base = 0;
     if (lane_id() == 0) base = atomicAdd(cnt, (unsigned int)__popcll(m));
     base = __shfl(base, 0);
-    if (keep) list[base + __popcll(m & lanes_below())] = (uint16_t)(a | (b << 8));
+    if (keep) list[base + __popcll(m & lanes_below())] = (uint32_t)(a | (b << 8));
+}
+
+// A lower bound rounded down to its upper 16 bits (negative bounds become 0:
+// such pairs are rescued whatever the upper bound).
+__device__ __forceinline__ uint32_t lb_down16(float lb) {
+    return __float_as_uint(fmaxf(lb, 0.0f)) >> 16;
 }
 
 // Append to a global list with one atomic per wave (divergence-safe).
@@ -1071,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
     __shared__ Tt sA[NF * TK];
     __shared__ Tt sB[NF * TK];
-    __shared__ uint16_t list[TK * TK];
+    __shared__ uint32_t list[TK * TK];
     __shared__ TPShared S;
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned qcount = min(*L.qcount, L.qcap);
@@ -1132,16 +1140,15 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
             // phase 2: full tests of the surviving pairs
             Tt tmin = (Tt)__builtin_inf();
             for (unsigned k = tid; k < cnt; k += 256) {
-                int a = list[k] & 255, b = list[k] >> 8;
+                int a = list[k] & 255, b = (list[k] >> 8) & 255;
                 if (PREC == 0) {
                     TriRef<float> TA{(float *)sA + a, TK}, TB{(float *)sB + b, TK};
                     if (MODE == 0) {
+                        // the rescue decision waits for this tile pair's own
+                        // upper bound (below): keep the lower bound
                         Pair32 r = pair32(TA, TB, S.c.elb);
                         tmin = fmin(tmin, (Tt)r.d2);
-                        bool resc = (double)r.lb <= S.ub + S.m;
-                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), r.lb};
-                        global_push(resc, it, L.rescue, L.rcount, L.rcap);
-                        n_resc += resc;
+                        list[k] = (uint32_t)(a | (b << 8)) | (lb_down16(r.lb) << 16);
                     } else {
                         int c = isect32(TA, TB, S.c.eps_f);
                         // not settled by planes and crossings: a certified
@@ -1183,6 +1190,11 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                             double U = sqrt((double)dm) * (1.0 + 4.0 * U32) + (double)S.c.eu;
                             atomic_min_pos(&R->ub, U * (1.0 + 4.0 * U64));
                         }
+                        // the row's upper bound now (this tile pair's and every
+                        // earlier result): only pairs that may still beat it
+                        // are rescued
+                        double ub_now = bits_to_double(load_acq(&R->ub));
+                        S.ub_now = ub_now + row_margin(*R, ub_now);
                     } else {
                         double dm = fmin(fmin(S.redd[0], S.redd[1]), fmin(S.redd[2], S.redd[3]));
                         if (dm < __builtin_inf()) {
@@ -1200,6 +1212,21 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                         double T2 = PREC == 0 ? (double)S.T2f : S.T2d;
                         double out = sqrt(fmin(dm, T2));
                         log_tile_pair(L, mA[S.ta], mB[S.tb], R->scale, S.lbf, out, S.g);
+                    }
+                }
+                if (PREC == 0) {
+                    // phase 3: rescue the pairs whose lower bound does not
+                    // exceed the row's upper bound plus margin
+                    __syncthreads();
+                    const double lim = S.ub_now;
+                    for (unsigned k = tid; k < cnt; k += 256) {
+                        uint32_t e = list[k];
+                        float lb = __uint_as_float((e >> 16) << 16);
+                        bool resc = (double)lb <= lim;
+                        int a = e & 255, b = (e >> 8) & 255;
+                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), lb};
+                        global_push(resc, it, L.rescue, L.rcount, L.rcap);
+                        n_resc += resc;
                     }
                 }
             }
