@@ -30,7 +30,7 @@ void release(DevBuf &b) {
 }
 
 struct SideState {
-    DevBuf xyz, tri, rowbox, t32, t64, meta;
+    DevBuf xyz, tri, rowbox, t32, t64, ids, meta;
 };
 
 // Device work space of one call: a context owns one, and every graph owns its
@@ -41,7 +41,7 @@ struct Workspace {
     DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb, wlist;
     void release_all() {
         for (auto &sd : side) {
-            DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.meta};
+            DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
@@ -326,7 +326,7 @@ struct Call {
 
 // Upload (host inputs) or reference (device inputs) one side and size its
 // buffers.  No kernel reads the data here.
-void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk,
+void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk, bool fp64,
                 const int64_t *d_offs, SideBufs &S, hipStream_t s) {
     SideState &st = ws.side[which];
     int64_t G = g->count, nv = g->v_off[G], nt = g->t_off[G];
@@ -351,7 +351,10 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     S.tile_off = d_offs + 2 * (G + 1);
     S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * (G > 0 ? G : 1));
     S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * tk * S.NT);
-    S.t64 = (double *)ensure(st.t64, sizeof(double) * 9 * tk * S.NT);
+    // FP64 tile copies only for the plain FP64 pass; the FP32 path keeps the
+    // triangle id of each slot and gathers FP64 vertices for its few rescues
+    S.t64 = fp64 ? (double *)ensure(st.t64, sizeof(double) * 9 * tk * S.NT) : nullptr;
+    S.ids = fp64 ? nullptr : (int32_t *)ensure(st.ids, sizeof(int32_t) * tk * S.NT);
     S.meta = (TileMeta *)ensure(st.meta, sizeof(TileMeta) * S.NT);
 }
 
@@ -397,8 +400,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
     int64_t *ds = (int64_t *)ensure(ws.small, sizeof(int64_t) * 9 * G1);
     check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
-    setup_side(ws, 0, a, P.tileA[G], tk, ds, C.A, s);
-    setup_side(ws, 1, b, P.tileB[G], tk, ds + 3 * G1, C.B, s);
+    const bool fp64 = opts.precision == SD3_PREC_FP64;
+    setup_side(ws, 0, a, P.tileA[G], tk, fp64, ds, C.A, s);
+    setup_side(ws, 1, b, P.tileB[G], tk, fp64, ds + 3 * G1, C.B, s);
     {
         int64_t n = C.A.nt + C.B.nt;
         int64_t nb = (n + 4095) / 4096 + 1;
@@ -470,13 +474,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     }
 }
 
-// Device validation of device-resident inputs (flags in the scalar block).
-void enqueue_validate(const Call &C, const sd3_geoms *a, hipStream_t s) {
-    launch_fill_u32(C.flags, 2, 0u, s);
-    if (a->mem != SD3_MEM_DEVICE) return;  // host inputs were checked on the host
-    launch_validate(C.A.xyz, C.A.nv, C.A.tri, C.A.nt, C.A.v_off, C.A.t_off, C.A.G, C.flags, s);
-    launch_validate(C.B.xyz, C.B.nv, C.B.tri, C.B.nt, C.B.v_off, C.B.t_off, C.B.G, C.flags + 1, s);
-}
+// Device validation (flags in the scalar block) fused with the row boxes: the
+// first kernels of every call (host inputs were also checked on the host).
+void enqueue_validate(Call &C, hipStream_t s) { launch_validate_rowbox(C.A, C.B, C.flags, s); }
 
 // Every kernel of the call after validation, in stream order, with no host
 // synchronisation (graph capture records exactly this).
@@ -491,10 +491,8 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int mode = C.mode;
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
     launch_prep(A, B, C.PB, key_bits(G), s, kev);
-    launch_group_boxes(A, Q.blkA, C.P.blkA[G], 64, Q.gA, s);
-    launch_group_boxes(B, Q.chkB, C.P.chkB[G], 256, Q.gB, s);
-    launch_rows_init(C.rows, G, A.rowbox, B.rowbox, s);
-    launch_reset_lists(L, s);
+    launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
+    launch_rows_init(C.rows, G, A.rowbox, B.rowbox, L, s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
     if (mode == 0) launch_row_scale(C.rows, G, s);
@@ -597,7 +595,7 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         char *rb = readback_area(ctx);
         const unsigned int *sc_h = (const unsigned int *)rb;
         const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
-        enqueue_validate(C, a, s);
+        enqueue_validate(C, s);
         if (a->mem == SD3_MEM_DEVICE) {
             // device inputs are validated before any kernel reads them
             check(hipMemcpyAsync(rb, C.sc, 64, hipMemcpyDeviceToHost, s), "D2H flags");
@@ -791,14 +789,14 @@ sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, cons
         check(hipHostMalloc(&g->pin, SCALAR_BYTES, hipHostMallocDefault), "hipHostMalloc");
         plan_call(ctx, g->ws, a, b, opts, mode, tk, dist, hit, g->C, g->cs);
         // validate the current contents once, before anything reads them
-        enqueue_validate(g->C, a, g->cs);
+        enqueue_validate(g->C, g->cs);
         check(hipMemcpyAsync(g->pin, g->C.sc, 64, hipMemcpyDeviceToHost, g->cs), "D2H flags");
         check(hipStreamSynchronize(g->cs), "sync");
         st = flags_status(ctx, (const unsigned int *)g->pin);
         if (st == SD3_OK) {
             check(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             capturing = true;
-            enqueue_validate(g->C, a, g->cs);
+            enqueue_validate(g->C, g->cs);
             enqueue_pipeline(ctx, g->C, g->cs, nullptr, nullptr);
             capturing = false;
             check(hipStreamEndCapture(g->cs, &g->graph), "hipStreamEndCapture");

@@ -18,7 +18,8 @@ struct SideBufs {
     int tk;                      // triangles per tile
     unsigned long long *rowbox;  // [G*6] ordered bits: lo xyz (min), hi xyz (max)
     float *t32;                  // [NT*9*tk]: tile t, coordinate c, slot j at (t*9+c)*tk+j
-    double *t64;                 // [NT*9*tk]
+    double *t64;                 // [NT*9*tk] exact copies (plain FP64 path), or nullptr
+    int32_t *ids;                // [NT*tk] triangle of each slot (FP32 path), or nullptr
     TileMeta *meta;              // [NT]
 };
 
@@ -92,15 +93,17 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
            L.counters[C_QUEUE_OVF] != 0 || *L.rcount > L.rcap || *L.xcount > L.xcap;
 }
 
-void launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
 
-void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
-                     const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
-                     hipStream_t s);
+// Validation of both sides (flags[0] for A, flags[1] for B) fused with the
+// row bounding boxes (one read of xyz): clears the flags and boxes, checks
+// every coordinate and every triangle index, and reduces the row boxes.
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream_t s);
+// Morton keys of both sides, the radix sort and the tiles.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
                  KernelEvents *kev);
+// Row state from both row boxes, and cleared work-list scalars and counters.
 void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                      const unsigned long long *boxB, hipStream_t s);
+                      const unsigned long long *boxB, Lists &L, hipStream_t s);
 // Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
 struct GroupBox {
     double lo[3], hi[3], rep[3];
@@ -119,8 +122,10 @@ struct QueueGeo {
     int compact;            // filter through the compacted list (single queue pass)
 };
 
-void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngroups, int gs,
-                        GroupBox *out, hipStream_t s);
+// Group boxes of both sides in one launch: A blocks of 64 tiles, B chunks of
+// 256 tiles.
+void launch_group_boxes(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t nblkA,
+                        int64_t nchkB, hipStream_t s);
 
 // Q_SEED: group bounds and upper bounds from vertex pairs (distance);
 // Q_GROUPS: group bounds only (intersects); Q_FILTER_DIST: keep tile pairs with
@@ -147,7 +152,6 @@ void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *
                        unsigned int *seedcount, hipStream_t s);
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
                      const uint32_t *vflags, hipStream_t s);
-void launch_reset_lists(Lists &L, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);
 
 }  // namespace sd3

@@ -50,62 +50,52 @@ static inline unsigned grid_for(int64_t n, int block) {
 // ---------------------------------------------------------------------------
 // a1: validation of device-resident inputs
 // ---------------------------------------------------------------------------
-__global__ void k_validate_xyz(const double *xyz, int64_t n, uint32_t *flags) {
-    uint32_t f = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double x = fabs(xyz[i]);
-        if (!(x <= 1.7976931348623157e308)) f |= V_NONFINITE;
-        else if (x != 0.0 && (x < 0x1p-256 || x > 0x1p256)) f |= V_RANGE;
-    }
-    if (f) atomicOr(flags, f);
+__device__ __forceinline__ uint32_t coord_flags(double v) {
+    double x = fabs(v);
+    if (!(x <= 1.7976931348623157e308)) return V_NONFINITE;
+    if (x != 0.0 && (x < 0x1p-256 || x > 0x1p256)) return V_RANGE;
+    return 0u;
 }
 
-__global__ void k_validate_tri(const int32_t *tri, int64_t nt, const int64_t *v_off,
-                               const int64_t *t_off, int64_t G, uint32_t *flags) {
-    uint32_t f = 0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int64_t g = find_row(t_off, G, t);
+// Every triangle index of both sides must lie inside its row (grid-stride
+// over A's triangles, then B's).
+__global__ void k_validate_tri(const int32_t *triA, int64_t ntA, const int64_t *voA,
+                               const int64_t *toA, const int32_t *triB, int64_t ntB,
+                               const int64_t *voB, const int64_t *toB, int64_t G, uint32_t *flags) {
+    uint32_t fa = 0, fb = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntA + ntB;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const bool sa = i < ntA;
+        const int64_t t = sa ? i : i - ntA;
+        const int32_t *tri = sa ? triA : triB;
+        const int64_t *v_off = sa ? voA : voB;
+        int64_t g = find_row(sa ? toA : toB, G, t);
         int64_t nvr = v_off[g + 1] - v_off[g];
+        uint32_t f = 0;
         for (int k = 0; k < 3; k++) {
             int32_t v = tri[3 * t + k];
-            if (v < 0 || v >= nvr) f |= V_INDEX;
+            if (v < 0 || v >= nvr) f = V_INDEX;
         }
+        if (sa) fa |= f;
+        else fb |= f;
     }
-    if (f) atomicOr(flags, f);
-}
-
-__global__ void k_fill_u32(uint32_t *p, int n, uint32_t v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-void launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
-}
-
-void launch_validate(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
-                     const int64_t *v_off, const int64_t *t_off, int64_t G, uint32_t *flags,
-                     hipStream_t s) {
-    if (nv > 0) {
-        unsigned g = grid_for(nv * 3, 256);
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(k_validate_xyz, dim3(g), dim3(256), 0, s, xyz, nv * 3, flags);
-    }
-    if (nt > 0) {
-        unsigned g = grid_for(nt, 256);
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(k_validate_tri, dim3(g), dim3(256), 0, s, tri, nt, v_off, t_off, G, flags);
-    }
+    if (fa) atomicOr(flags, fa);
+    if (fb) atomicOr(flags + 1, fb);
 }
 
 // ---------------------------------------------------------------------------
 // a2: row boxes, Morton keys, radix sort, tiles
 // ---------------------------------------------------------------------------
-__global__ void k_rowbox_init(unsigned long long *box, int64_t G) {
+// Clears the validation flags of both sides and the row boxes of both sides.
+__global__ void k_prep_init(uint32_t *flags, unsigned long long *boxA, unsigned long long *boxB,
+                            int64_t G) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < G * 6) box[i] = (i % 6) < 3 ? ~0ull : 0ull;
+    if (i < 2) flags[i] = 0u;
+    if (i < G * 6) {
+        unsigned long long v = (i % 6) < 3 ? ~0ull : 0ull;
+        boxA[i] = v;
+        boxB[i] = v;
+    }
 }
 
 // Row bounding boxes of all vertices.  Each block owns a contiguous range of
@@ -140,43 +130,88 @@ __device__ void rowbox_flush(int64_t g, unsigned long long *lo, unsigned long lo
     }
 }
 
-__global__ __launch_bounds__(256) void k_rowbox(const double *xyz, int64_t nv, const int64_t *v_off,
-                                                int64_t G, unsigned long long *box) {
+struct XyzSide {
+    const double *xyz;
+    int64_t nv;
+    const int64_t *v_off;
+    unsigned long long *box;
+    unsigned nblk;
+};
+
+// The same pass checks every coordinate (finite, magnitude range).
+__device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t *flag) {
     __shared__ unsigned long long red[4][6];
-    int64_t per = ((nv + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
-    int64_t b0 = blockIdx.x * per, b1 = min(nv, b0 + per);
+    const int64_t nv = S.nv;
+    int64_t per = ((nv + S.nblk - 1) / S.nblk + 255) / 256 * 256;
+    int64_t b0 = blk * per, b1 = min(nv, b0 + per);
     unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    uint32_t f = 0;
     int64_t cur = -1;
     for (int64_t base = b0; base < b1; base += 256) {
         int64_t last = min(base + 255, b1 - 1);
-        int64_t g0 = find_row(v_off, G, base), g1 = find_row(v_off, G, last);
+        int64_t g0 = find_row(S.v_off, G, base), g1 = find_row(S.v_off, G, last);
         int64_t i = base + threadIdx.x;
         bool valid = i <= last;
+        double x[3] = {0.0, 0.0, 0.0};
+        if (valid)
+            for (int k = 0; k < 3; k++) {
+                x[k] = S.xyz[3 * i + k];
+                f |= coord_flags(x[k]);
+            }
         if (g0 == g1) {
             if (g0 != cur) {
-                if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
+                if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
                 cur = g0;
             }
             if (valid)
                 for (int k = 0; k < 3; k++) {
-                    unsigned long long v = ordered_bits(xyz[3 * i + k]);
+                    unsigned long long v = ordered_bits(x[k]);
                     lo[k] = min(lo[k], v);
                     hi[k] = max(hi[k], v);
                 }
         } else {
-            if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
+            if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
             cur = -1;
             if (valid) {
-                int64_t g = find_row(v_off, G, i);
+                int64_t g = find_row(S.v_off, G, i);
                 for (int k = 0; k < 3; k++) {
-                    unsigned long long v = ordered_bits(xyz[3 * i + k]);
-                    atomicMin(&box[g * 6 + k], v);
-                    atomicMax(&box[g * 6 + 3 + k], v);
+                    unsigned long long v = ordered_bits(x[k]);
+                    atomicMin(&S.box[g * 6 + k], v);
+                    atomicMax(&S.box[g * 6 + 3 + k], v);
                 }
             }
         }
     }
-    if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
+    if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
+    if (f) atomicOr(flag, f);
+}
+
+// Blocks [0, A.nblk) take side A, the rest side B.
+__global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, int64_t G, uint32_t *flags) {
+    if (blockIdx.x < A.nblk) rowbox_side(A, G, blockIdx.x, flags);
+    else rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
+}
+
+static unsigned rowbox_blocks(int64_t nv) {
+    if (nv <= 0) return 0;
+    unsigned g = grid_for(nv, 2048);
+    return g > 512 ? 512 : g;
+}
+
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream_t s) {
+    const int64_t G = A.G;
+    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(G * 6 > 2 ? G * 6 : 2, 256)), dim3(256), 0, s,
+                       flags, A.rowbox, B.rowbox, G);
+    XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv)};
+    XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv)};
+    if (xa.nblk + xb.nblk > 0)
+        hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
+    if (A.nt + B.nt > 0) {
+        unsigned g = grid_for(A.nt + B.nt, 256);
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_validate_tri, dim3(g), dim3(256), 0, s, A.tri, A.nt, A.v_off, A.t_off,
+                           B.tri, B.nt, B.v_off, B.t_off, G, flags);
+    }
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -189,33 +224,46 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 }
 
 // key = side << rowbits+30 | row << 30 | 30-bit Morton code of the triangle
-// centroid in the row box; value = triangle index within its side
-__global__ void k_morton(const double *xyz, const int32_t *tri, int64_t nt, const int64_t *v_off,
-                         const int64_t *t_off, int64_t G, const unsigned long long *box,
-                         uint64_t side_key, uint64_t *keys, int32_t *vals) {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int64_t g = find_row(t_off, G, t);
-        const double *X = xyz + 3 * v_off[g];
-        const int64_t nvr = v_off[g + 1] - v_off[g];
+// centroid in the row box; value = triangle index within its side.  Both
+// sides in one launch (A's triangles, then B's), keys written at the width
+// the sort uses.
+struct MortonSide {
+    const double *xyz;
+    const int32_t *tri;
+    int64_t nt;
+    const int64_t *v_off, *t_off;
+    const unsigned long long *box;
+};
+
+template <typename KT>
+__global__ void k_morton(MortonSide A, MortonSide B, int64_t G, uint64_t side_key, KT *keys,
+                         int32_t *vals) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A.nt + B.nt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const bool sa = i < A.nt;
+        const MortonSide &S = sa ? A : B;
+        const int64_t t = sa ? i : i - A.nt;
+        int64_t g = find_row(S.t_off, G, t);
+        const double *X = S.xyz + 3 * S.v_off[g];
+        const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
         uint32_t q[3];
         double cen[3] = {0.0, 0.0, 0.0};
         for (int v = 0; v < 3; v++) {
-            const double *p = X + 3 * corner(tri, t, v, nvr);
+            const double *p = X + 3 * corner(S.tri, t, v, nvr);
             cen[0] += p[0];
             cen[1] += p[1];
             cen[2] += p[2];
         }
         for (int k = 0; k < 3; k++) {
-            double lo = from_ordered_bits(box[g * 6 + k]), hi = from_ordered_bits(box[g * 6 + 3 + k]);
+            double lo = from_ordered_bits(S.box[g * 6 + k]), hi = from_ordered_bits(S.box[g * 6 + 3 + k]);
             double c = cen[k] * (1.0 / 3.0);
             double f = hi > lo ? (c - lo) / (hi - lo) * 1024.0 : 0.0;
             int qi = (int)f;
             q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
         }
         uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-        keys[t] = side_key | ((uint64_t)g << 30) | code;
-        vals[t] = (int32_t)t;
+        keys[i] = (KT)((sa ? 0ull : side_key) | ((uint64_t)g << 30) | code);
+        vals[i] = (int32_t)t;
     }
 }
 
@@ -397,12 +445,6 @@ static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part,
     return cur;
 }
 
-// 32-bit keys (one word per item) whenever side, row and Morton bits fit.
-__global__ void k_narrow_keys(const uint64_t *in, uint32_t *out, int64_t n) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (uint32_t)in[i];
-}
-
 // Tiles: gather each tile's triangles in sorted order and write the FP64 and
 // FP32 SoA copies and the tile metadata.
 struct TileJob {
@@ -413,7 +455,8 @@ struct TileJob {
     int tk;
     const int32_t *sorted;
     float *t32;
-    double *t64;
+    double *t64;   // FP64 copies, or nullptr: then ids
+    int32_t *ids;  // triangle of each slot
     TileMeta *meta;
 };
 
@@ -444,7 +487,10 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
             v[r][3 * k + 2] = p[2];
         }
         if (j < tk) {
-            for (int c = 0; c < 9; c++) J.t64[(t * 9 + c) * tk + j] = v[r][c];
+            if (J.t64)
+                for (int c = 0; c < 9; c++) J.t64[(t * 9 + c) * tk + j] = v[r][c];
+            else
+                J.ids[t * tk + j] = (int32_t)tri_id;
             for (int k = 0; k < 3; k++) {
                 lo[k] = fmin(lo[k], fmin(v[r][k], fmin(v[r][3 + k], v[r][6 + k])));
                 hi[k] = fmax(hi[k], fmax(v[r][k], fmax(v[r][3 + k], v[r][6 + k])));
@@ -499,48 +545,36 @@ __global__ void k_tiles(TileJob A, TileJob B) {
     else if (t - A.NT < B.NT) tile_one(B, t - A.NT);
 }
 
-static void rowbox(SideBufs &S, hipStream_t s) {
-    hipLaunchKernelGGL(k_rowbox_init, dim3(grid_for(S.G * 6, 256)), dim3(256), 0, s, S.rowbox, S.G);
-    if (S.nv > 0) {
-        unsigned g = grid_for(S.nv, 2048);
-        if (g > 512) g = 512;
-        hipLaunchKernelGGL(k_rowbox, dim3(g), dim3(256), 0, s, S.xyz, S.nv, S.v_off, S.G, S.rowbox);
-    }
-}
-
-static void morton(SideBufs &S, uint64_t side_key, uint64_t *keys, int32_t *vals, hipStream_t s) {
-    if (S.nt == 0) return;
-    unsigned g = grid_for(S.nt, 256);
-    if (g > 16384) g = 16384;
-    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, s, S.xyz, S.tri, S.nt, S.v_off, S.t_off, S.G,
-                       S.rowbox, side_key, keys, vals);
-}
-
 // Both sides are sorted together (the side is the top key bit), so one
 // sequence of sort launches covers 2x the items.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
                  KernelEvents *kev) {
     if (A.G == 0) return;
-    rowbox(A, s);
-    rowbox(B, s);
-    morton(A, 0ull, P.keys[0], P.vals[0], s);
-    morton(B, 1ull << key_bits, P.keys[0] + A.nt, P.vals[0] + A.nt, s);
     const int64_t n = A.nt + B.nt;
+    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox};
+    MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox};
+    unsigned g = grid_for(n > 0 ? n : 1, 256);
+    if (g > 16384) g = 16384;
     int cur;
     if (key_bits + 1 <= 32) {
+        // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
         if (n > 0)
-            hipLaunchKernelGGL(k_narrow_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.keys[0], k32[0], n);
+            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(g), dim3(256), 0, s, ma, mb, A.G,
+                               1ull << key_bits, k32[0], P.vals[0]);
         cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     } else {
+        if (n > 0)
+            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(g), dim3(256), 0, s, ma, mb, A.G,
+                               1ull << key_bits, P.keys[0], P.vals[0]);
         cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
-                   A.t64, A.meta};
+                   A.t64, A.ids, A.meta};
         TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, P.vals[cur] + A.nt,
-                   B.t32, B.t64, B.meta};
+                   B.t32, B.t64, B.ids, B.meta};
         hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
     }
     if (kev) kev->end(KE_TILES, s);
@@ -550,8 +584,11 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_
 // row state
 // ---------------------------------------------------------------------------
 __global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                            const unsigned long long *boxB) {
+                            const unsigned long long *boxB, Lists L) {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < 12) L.qcount[g] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
+                                  // items); 12-13 hold the validation flags
+    if (g < C_NCOUNTERS) L.counters[g] = 0;
     if (g >= G) return;
     RowState r;
     r.ub = double_to_bits(__builtin_inf());
@@ -574,9 +611,9 @@ __global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long 
 }
 
 void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                      const unsigned long long *boxB, hipStream_t s) {
-    if (G > 0)
-        hipLaunchKernelGGL(k_rows_init, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, boxA, boxB);
+                      const unsigned long long *boxB, Lists &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_init, dim3(grid_for(G > 16 ? G : 16, 256)), dim3(256), 0, s, rows, G,
+                       boxA, boxB, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,11 +654,9 @@ __device__ __forceinline__ double box_gap2(const double *alo, const double *ahi,
 
 // Boxes of tile groups: 64 consecutive tiles of a row on the A side (one work
 // item's A block), 256 on the B side (one work item's B chunk).
-__global__ __launch_bounds__(256) void k_group_boxes(const TileMeta *meta, const int64_t *tile_off,
-                                                     const int64_t *grp_off, int64_t G, int gs,
-                                                     GroupBox *out) {
+__device__ void group_box(const TileMeta *meta, const int64_t *tile_off, const int64_t *grp_off,
+                          int64_t G, int gs, GroupBox *out, int64_t gid) {
     __shared__ double red[4][6];
-    int64_t gid = blockIdx.x;
     int64_t g = find_row(grp_off, G, gid);
     int64_t t0 = tile_off[g] + (gid - grp_off[g]) * gs;
     int64_t t1 = min(t0 + gs, tile_off[g + 1]);
@@ -651,11 +686,21 @@ __global__ __launch_bounds__(256) void k_group_boxes(const TileMeta *meta, const
     }
 }
 
-void launch_group_boxes(const SideBufs &S, const int64_t *grp_off, int64_t ngroups, int gs,
-                        GroupBox *out, hipStream_t s) {
-    if (ngroups > 0)
-        hipLaunchKernelGGL(k_group_boxes, dim3((unsigned)ngroups), dim3(256), 0, s, S.meta,
-                           S.tile_off, grp_off, S.G, gs, out);
+// Blocks [0, nblkA) build A's block boxes, the rest B's chunk boxes.
+__global__ __launch_bounds__(256) void k_group_boxes(const TileMeta *mA, const int64_t *tA,
+                                                     const int64_t *blkA, int64_t nblkA,
+                                                     const TileMeta *mB, const int64_t *tB,
+                                                     const int64_t *chkB, int64_t G,
+                                                     GroupBox *gA, GroupBox *gB) {
+    if ((int64_t)blockIdx.x < nblkA) group_box(mA, tA, blkA, G, 64, gA, blockIdx.x);
+    else group_box(mB, tB, chkB, G, 256, gB, blockIdx.x - nblkA);
+}
+
+void launch_group_boxes(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t nblkA,
+                        int64_t nchkB, hipStream_t s) {
+    if (nblkA + nchkB > 0)
+        hipLaunchKernelGGL(k_group_boxes, dim3((unsigned)(nblkA + nchkB)), dim3(256), 0, s, A.meta,
+                           A.tile_off, Q.blkA, nblkA, B.meta, B.tile_off, Q.chkB, A.G, Q.gA, Q.gB);
 }
 
 // Per work item: box lower bound of its (A block, B chunk) pair, kept for the
@@ -1283,14 +1328,43 @@ void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
 // ---------------------------------------------------------------------------
 // a5: FP64 rescue of the pairs the FP32 bounds did not settle
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_tri64(const double *t64, int tk, int tile, int slot, double *out) {
+// FP64 vertices of one tile slot: from the tile's exact copies when they
+// exist (plain FP64 path), else gathered through the slot's triangle id from
+// the inputs (the same values, so both give identical results).
+struct TriSrc {
+    const double *t64;
+    const int32_t *ids;
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off;
+    const TileMeta *meta;
+    int tk;
+};
+
+static TriSrc tri_src(const SideBufs &S) { return {S.t64, S.ids, S.xyz, S.tri, S.v_off, S.meta, S.tk}; }
+
+__device__ __forceinline__ void load_tri64(const TriSrc &S, int tile, int slot, double *out) {
+    if (S.t64) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) out[c] = t64[((int64_t)tile * 9 + c) * tk + slot];
+        for (int c = 0; c < 9; c++) out[c] = S.t64[((int64_t)tile * 9 + c) * S.tk + slot];
+        return;
+    }
+    const int64_t id = S.ids[(int64_t)tile * S.tk + slot];
+    const int64_t g = S.meta[tile].row;
+    const double *X = S.xyz + 3 * S.v_off[g];
+    const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const double *p = X + 3 * corner(S.tri, id, k, nvr);
+        out[3 * k] = p[0];
+        out[3 * k + 1] = p[1];
+        out[3 * k + 2] = p[2];
+    }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMeta *mA,
-                                                const double *t64B, RowState *rows, Lists L, int tk) {
+__global__ __launch_bounds__(256) void k_rescue(TriSrc SA, TriSrc SB, RowState *rows, Lists L) {
+    const TileMeta *mA = SA.meta;
     const unsigned n = min(*L.rcount, L.rcap);
     unsigned long long n64 = 0, nex = 0;
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1303,8 +1377,8 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
             double ub = bits_to_double(load_acq(&R->ub));
             if ((double)e.lb > ub + row_margin(*R, ub)) continue;
             double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(t64A, tk, e.ta, a, ta);
-            load_tri64(t64B, tk, e.tb, b, tb);
+            load_tri64(SA, e.ta, a, ta);
+            load_tri64(SB, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             Pair64 r = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1});
@@ -1323,8 +1397,8 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
             }
         } else {
             double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(t64A, tk, e.ta, a, ta);
-            load_tri64(t64B, tk, e.tb, b, tb);
+            load_tri64(SA, e.ta, a, ta);
+            load_tri64(SB, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             int f = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1}).status;
@@ -1349,25 +1423,25 @@ __global__ __launch_bounds__(256) void k_rescue(const double *t64A, const TileMe
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                    int grid, hipStream_t s) {
     if (mode == 0)
-        hipLaunchKernelGGL(k_rescue<0>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L, A.tk);
+        hipLaunchKernelGGL(k_rescue<0>, dim3(grid), dim3(256), 0, s, tri_src(A), tri_src(B), rows, L);
     else
-        hipLaunchKernelGGL(k_rescue<1>, dim3(grid), dim3(256), 0, s, A.t64, A.meta, B.t64, rows, L, A.tk);
+        hipLaunchKernelGGL(k_rescue<1>, dim3(grid), dim3(256), 0, s, tri_src(A), tri_src(B), rows, L);
 }
 
 // ---------------------------------------------------------------------------
 // exact arithmetic for the pairs the FP64 filter left undecided
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_exact(const double *t64A, const TileMeta *mA,
-                                              const double *t64B, RowState *rows, Lists L,
-                                              int mode, int tk) {
+__global__ __launch_bounds__(64) void k_exact(TriSrc SA, TriSrc SB, RowState *rows, Lists L,
+                                              int mode) {
+    const TileMeta *mA = SA.meta;
     const unsigned n = min(*L.xcount, L.xcap);
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         ExactItem e = L.exact[i];
         RowState *R = rows + mA[e.ta].row;
         if (load_acq32(&R->hit)) continue;
         double va[9], vb[9];
-        load_tri64(t64A, tk, e.ta, e.slots & 0xffff, va);
-        load_tri64(t64B, tk, e.tb, e.slots >> 16, vb);
+        load_tri64(SA, e.ta, e.slots & 0xffff, va);
+        load_tri64(SB, e.tb, e.slots >> 16, vb);
         if (ex::tri_tri_exact(va, vb)) {
             atomicOr(&R->hit, 1u);
             atomic_min_pos(&R->d2, 0.0);
@@ -1379,7 +1453,7 @@ __global__ __launch_bounds__(64) void k_exact(const double *t64A, const TileMeta
 
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                   int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, A.t64, A.meta, B.t64, rows, L, mode, A.tk);
+    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, tri_src(A), tri_src(B), rows, L, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1531,17 +1605,6 @@ void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit
     if (G > 0)
         hipLaunchKernelGGL(k_finalize, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, dist, hit, L,
                            vflags);
-}
-
-__global__ void k_reset_lists(Lists L) {
-    int i = threadIdx.x;
-    if (i < 12) L.qcount[i] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
-                                  // items); 12-13 hold the validation flags
-    if (i < C_NCOUNTERS) L.counters[i] = 0;
-}
-
-void launch_reset_lists(Lists &L, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_lists, dim3(1), dim3(64), 0, s, L);
 }
 
 // Between queue passes: the finished pass's count goes to the candidate
