@@ -276,13 +276,6 @@ sd3_status check_call(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, cons
     return SD3_OK;
 }
 
-// Morton key bits: 30 for the code plus enough to keep rows apart.
-int key_bits(int64_t G) {
-    int rowbits = 0;
-    while (((int64_t)1 << rowbits) < G) rowbits++;
-    return 30 + rowbits;
-}
-
 // Phase events (opts.timing): ev[0] at the start, ev[k+1] at the end of phase k.
 struct PhaseClock {
     sd3_ctx *ctx;
@@ -490,7 +483,7 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int64_t G = C.P.G;
     const int mode = C.mode;
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
-    launch_prep(A, B, C.PB, key_bits(G), s, kev);
+    launch_prep(A, B, C.PB, sort_key(G), s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     launch_rows_init(C.rows, G, A.rowbox, B.rowbox, L, s);
     mark(2);
@@ -564,8 +557,9 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->exact = (int64_t)cnt_h[C_EXACT];
     stats->logged = (int64_t)cnt_h[C_LOGGED];
     stats->sort_items = C.A.nt + C.B.nt;
-    stats->sort_key_bytes = key_bits(C.P.G) + 1 <= 32 ? 4 : 8;
-    stats->sort_passes = (key_bits(C.P.G) + 1 + 7) / 8;
+    const SortKey K = sort_key(C.P.G);
+    stats->sort_key_bytes = K.bits() <= 32 ? 4 : 8;
+    stats->sort_passes = (K.bits() + 7) / 8;
     stats->tile = C.P.tk;
     stats->queue_passes = C.passes;
 }

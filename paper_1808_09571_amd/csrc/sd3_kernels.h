@@ -98,8 +98,15 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
 // row bounding boxes (one read of xyz): clears the flags and boxes, checks
 // every coordinate and every triangle index, and reduces the row boxes.
 void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream_t s);
+// Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
+// `passes` 8-bit radix passes (total bits = 8 * passes at most).
+struct SortKey {
+    int rowbits, mbits, passes;
+    int bits() const { return 1 + rowbits + mbits; }
+};
+SortKey sort_key(int64_t G);
 // Morton keys of both sides, the radix sort and the tiles.
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
                  KernelEvents *kev);
 // Row state from both row boxes, and cleared work-list scalars and counters.
 void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,

@@ -223,10 +223,14 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-// key = side << rowbits+30 | row << 30 | 30-bit Morton code of the triangle
-// centroid in the row box; value = triangle index within its side.  Both
+// key = side << rowbits+mbits | row << mbits | the top mbits of the 30-bit
+// Morton code of the triangle centroid, quantised on cubic cells of the row
+// box (the largest extent / 1024 on every axis, so a flat surface spends its
+// bits on its two long axes); value = triangle index within its side.  Both
 // sides in one launch (A's triangles, then B's), keys written at the width
 // the sort uses.
+constexpr int RS_ITEMS = 4096;  // radix sort items per block
+
 struct MortonSide {
     const double *xyz;
     const int32_t *tri;
@@ -235,11 +239,20 @@ struct MortonSide {
     const unsigned long long *box;
 };
 
+// One block per radix-sort block of RS_ITEMS keys, so that the histogram of
+// the sort's first digit is counted here (written as hist[digit * nblocks +
+// block], the layout the scan expects).
 template <typename KT>
-__global__ void k_morton(MortonSide A, MortonSide B, int64_t G, uint64_t side_key, KT *keys,
-                         int32_t *vals) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A.nt + B.nt;
-         i += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_morton(MortonSide A, MortonSide B, int64_t G, int mbits,
+                                                uint64_t side_key, KT *keys, int32_t *vals,
+                                                uint32_t *hist, int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = A.nt + B.nt;
+    for (int r = 0; r < RS_ITEMS / 256; r++) {
+        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 256 + threadIdx.x;
+        if (i >= n) break;
         const bool sa = i < A.nt;
         const MortonSide &S = sa ? A : B;
         const int64_t t = sa ? i : i - A.nt;
@@ -254,24 +267,31 @@ __global__ void k_morton(MortonSide A, MortonSide B, int64_t G, uint64_t side_ke
             cen[1] += p[1];
             cen[2] += p[2];
         }
+        double lo[3], ext = 0.0;
         for (int k = 0; k < 3; k++) {
-            double lo = from_ordered_bits(S.box[g * 6 + k]), hi = from_ordered_bits(S.box[g * 6 + 3 + k]);
-            double c = cen[k] * (1.0 / 3.0);
-            double f = hi > lo ? (c - lo) / (hi - lo) * 1024.0 : 0.0;
+            lo[k] = from_ordered_bits(S.box[g * 6 + k]);
+            ext = fmax(ext, from_ordered_bits(S.box[g * 6 + 3 + k]) - lo[k]);
+        }
+        const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
+        for (int k = 0; k < 3; k++) {
+            double f = (cen[k] * (1.0 / 3.0) - lo[k]) * sc;
             int qi = (int)f;
             q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
         }
         uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-        keys[i] = (KT)((sa ? 0ull : side_key) | ((uint64_t)g << 30) | code);
+        const KT key = (KT)((sa ? 0ull : side_key) | ((uint64_t)g << mbits) | (code >> (30 - mbits)));
+        keys[i] = key;
         vals[i] = (int32_t)t;
+        atomicAdd(&h[(uint32_t)key & 255u], 1u);
     }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Stable LSD radix sort, 8-bit digits.  Blocks of 256 threads own 4096
-// consecutive items; per pass: digit histogram per block, one exclusive scan
-// over (digit, block), and a stable scatter that ranks equal digits inside a
-// wave with ballots.
-constexpr int RS_ITEMS = 4096;
+// consecutive items; per pass: digit histogram per block (the first pass's
+// comes from the key kernel), one exclusive scan over (digit, block), and a
+// stable scatter that ranks equal digits inside a wave with ballots.
 
 template <typename KT>
 __global__ void k_hist(const KT *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
@@ -323,6 +343,51 @@ __global__ __launch_bounds__(1024) void k_scan_local(uint32_t *a, int64_t total,
         run += v[k];
     }
     if (tid == 1023) part[blockIdx.x] = wbase + inc;
+}
+
+// The whole (digit, block) histogram in one block when it has at most
+// 16 * SCAN_CHUNK entries: full prefixes in place, chunk offsets zeroed.
+// Rounds of 16384 entries are staged through LDS with coalesced loads and
+// stores; thread t scans its 16 consecutive entries (a padding word after
+// every 16 keeps those reads on distinct banks).
+__global__ __launch_bounds__(1024) void k_scan_single(uint32_t *a, int64_t total, uint32_t *part,
+                                                      int nchunk) {
+    constexpr int ROUND = 16384, PER = 16;
+    __shared__ uint32_t buf[ROUND + ROUND / PER];
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry_s;
+    const int tid = threadIdx.x;
+    auto phys = [](int j) { return j + j / PER; };
+    if (tid == 0) carry_s = 0u;
+    for (int64_t base = 0; base < total; base += ROUND) {
+        for (int k = 0; k < PER; k++) {
+            int j = k * 1024 + tid;
+            buf[phys(j)] = base + j < total ? a[base + j] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[PER], sum = 0;
+        for (int k = 0; k < PER; k++) {
+            v[k] = buf[phys(tid * PER + k)];
+            sum += v[k];
+        }
+        uint32_t inc = wave_incl_scan(sum);
+        if (lane_id() == 63) wsum[tid >> 6] = inc;
+        __syncthreads();
+        uint32_t run = carry_s + inc - sum;
+        for (int w = 0; w < (tid >> 6); w++) run += wsum[w];
+        for (int k = 0; k < PER; k++) {
+            buf[phys(tid * PER + k)] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        for (int k = 0; k < PER; k++) {
+            int j = k * 1024 + tid;
+            if (base + j < total) a[base + j] = buf[phys(j)];
+        }
+        if (tid == 1023) carry_s = run;
+        __syncthreads();
+    }
+    if (tid < nchunk) part[tid] = 0u;
 }
 
 __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
@@ -424,6 +489,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
 }
 
 // Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
+// The first pass's histogram is already in `hist` (from the key kernel).
 template <typename KT>
 static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
                       int bits, hipStream_t s, KernelEvents *kev) {
@@ -433,9 +499,14 @@ static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part,
     int64_t total = (int64_t)nb * 256;
     int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
-        hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
+        if (shift > 0)
+            hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
+        if (nchunk <= 16) {
+            hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, hist, total, part, nchunk);
+        } else {
+            hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
+        }
         if (kev) kev->begin(KE_SCATTER, s);
         hipLaunchKernelGGL(k_scatter<KT>, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
                            keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb);
@@ -547,26 +618,38 @@ __global__ void k_tiles(TileJob A, TileJob B) {
 
 // Both sides are sorted together (the side is the top key bit), so one
 // sequence of sort launches covers 2x the items.
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, int key_bits, hipStream_t s,
+// The fewest 8-bit passes that keep at least 18 Morton bits (6 per axis),
+// then every remaining bit of those passes for the Morton prefix (at most 30).
+SortKey sort_key(int64_t G) {
+    SortKey K;
+    K.rowbits = 0;
+    while (((int64_t)1 << K.rowbits) < G) K.rowbits++;
+    K.passes = (1 + K.rowbits + 18 + 7) / 8;
+    K.mbits = 8 * K.passes - 1 - K.rowbits;
+    if (K.mbits > 30) K.mbits = 30;
+    return K;
+}
+
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
                  KernelEvents *kev) {
+    const int key_bits = K.rowbits + K.mbits;  // bits below the side bit
     if (A.G == 0) return;
     const int64_t n = A.nt + B.nt;
     MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox};
     MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox};
-    unsigned g = grid_for(n > 0 ? n : 1, 256);
-    if (g > 16384) g = 16384;
+    const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
     int cur;
     if (key_bits + 1 <= 32) {
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(g), dim3(256), 0, s, ma, mb, A.G,
-                               1ull << key_bits, k32[0], P.vals[0]);
+            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(256), 0, s, ma, mb, A.G, K.mbits,
+                               1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     } else {
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(g), dim3(256), 0, s, ma, mb, A.G,
-                               1ull << key_bits, P.keys[0], P.vals[0]);
+            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(256), 0, s, ma, mb, A.G, K.mbits,
+                               1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
     if (kev) kev->begin(KE_TILES, s);
@@ -995,6 +1078,31 @@ __device__ __forceinline__ void log_tile_pair(const Lists &L, const TileMeta &a,
     r[MLP_IN + 1] = __int_as_float(row);
 }
 
+// Squared gap of two boxes, without contraction, so that the value is a
+// monotone function of the bounds: a group-box pair that fails a threshold
+// contains no triangle-box pair that passes it.
+template <typename T>
+__device__ __forceinline__ T gap2_boxes(const T (&alo)[3], const T (&ahi)[3], const T (&blo)[3],
+                                        const T (&bhi)[3]) {
+#pragma clang fp contract(off)
+    T g2 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        T gp = fmax(fmax(blo[k] - ahi[k], alo[k] - bhi[k]), (T)0);
+        g2 += gp * gp;
+    }
+    return g2;
+}
+
+template <typename T>
+__device__ __forceinline__ bool overlap_boxes(const T (&alo)[3], const T (&ahi)[3], const T (&blo)[3],
+                                              const T (&bhi)[3], T tol) {
+    bool keep = true;
+#pragma unroll
+    for (int k = 0; k < 3; k++) keep = keep && blo[k] - ahi[k] <= tol && alo[k] - bhi[k] <= tol;
+    return keep;
+}
+
 struct TPShared {
     int q, live, ta, tb, g, na, nb, logged;
     float lbf;
@@ -1004,6 +1112,7 @@ struct TPShared {
     double T2d;       // FP64 triangle-box cull threshold (squared)
     TP32 c;
     unsigned int cnt;
+    unsigned int gcnt;  // surviving group pairs
     float redf[4];
     double redd[4];
 };
@@ -1016,6 +1125,7 @@ __device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned
     S.q = (int)q;
     S.live = 0;
     S.cnt = 0;
+    S.gcnt = 0;
     if (q >= qcount) return;
     int2 e = L.queue[q];
     const TileMeta &a = mA[e.x];
@@ -1119,12 +1229,15 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                                                RowState *rows, Lists L) {
     static_assert(tile_size_ok(TK), "tile size");
     constexpr int NF = F_NTRI32;
-    // phase 1 thread layout: thread -> (A slot a, quarter/eighth/half bq of B)
-    constexpr int BQ = WG / TK, NBQ = TK / BQ;
+    // groups of 8 consecutive slots: group boxes are culled first, and only
+    // surviving group pairs are expanded to triangle pairs
+    constexpr int NG = TK / 8, NGP = NG * NG;
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
     __shared__ Tt sA[NF * TK];
     __shared__ Tt sB[NF * TK];
+    __shared__ Tt gbox[2][NG][6];  // [side][group][lo xyz, hi xyz]
     __shared__ uint32_t list[TK * TK];
+    __shared__ uint32_t glist[NGP];
     __shared__ TPShared S;
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned qcount = min(*L.qcount, L.qcap);
@@ -1137,50 +1250,83 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
         __syncthreads();
         if ((unsigned)S.q >= qcount) break;
         if (S.live) {
-            // threads [0, TK) stage A's slots, threads [128, 128 + TK) B's
-            if (tid < TK) {
-                if (PREC == 0) stage32<TK>((float *)sA, t32A + (int64_t)S.ta * 9 * TK, S.c.sh, tid);
-                else stage64<TK>((double *)sA, t64A + (int64_t)S.ta * 9 * TK, tid);
-            } else if (tid >= 128 && tid < 128 + TK) {
-                if (PREC == 0) stage32<TK>((float *)sB, t32B + (int64_t)S.tb * 9 * TK, nullptr, tid - 128);
-                else stage64<TK>((double *)sB, t64B + (int64_t)S.tb * 9 * TK, tid - 128);
-            }
-            __syncthreads();
-            // phase 1: triangle boxes, compacted into the LDS list
+            // threads [0, TK) stage A's slots, threads [128, 128 + TK) B's;
+            // each group of 8 consecutive staging lanes reduces its group box
             {
-                int a = tid % TK, bq = tid / TK;
-                Tt alo[3], ahi[3];
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    alo[k] = sA[(F_LO + k) * TK + a];
-                    ahi[k] = sA[(F_HI + k) * TK + a];
+                const bool sa = tid < TK, sb = tid >= 128 && tid < 128 + TK;
+                if (sa) {
+                    if (PREC == 0) stage32<TK>((float *)sA, t32A + (int64_t)S.ta * 9 * TK, S.c.sh, tid);
+                    else stage64<TK>((double *)sA, t64A + (int64_t)S.ta * 9 * TK, tid);
+                } else if (sb) {
+                    if (PREC == 0) stage32<TK>((float *)sB, t32B + (int64_t)S.tb * 9 * TK, nullptr, tid - 128);
+                    else stage64<TK>((double *)sB, t64B + (int64_t)S.tb * 9 * TK, tid - 128);
                 }
-                for (int jb = 0; jb < NBQ; jb++) {
-                    int b = bq * NBQ + jb;
-                    bool keep = a < S.na && b < S.nb;
-                    if (MODE == 0) {
-                        Tt g2 = 0;
+                if (w == 0 || w == 2 || (TK == 128 && (w == 1 || w == 3))) {
+                    const Tt *src = tid < 128 ? sA : sB;
+                    const int j = tid & 127;
+                    Tt bx[6];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        bx[k] = (sa || sb) ? src[(F_LO + k) * TK + j] : (Tt)0;
+                        bx[3 + k] = (sa || sb) ? src[(F_HI + k) * TK + j] : (Tt)0;
+                    }
+#pragma unroll
+                    for (int o = 1; o < 8; o <<= 1)
 #pragma unroll
                         for (int k = 0; k < 3; k++) {
-                            Tt gp = fmax(fmax(sB[(F_LO + k) * TK + b] - ahi[k], alo[k] - sB[(F_HI + k) * TK + b]), (Tt)0);
-                            g2 += gp * gp;
+                            bx[k] = fmin(bx[k], __shfl_xor(bx[k], o));
+                            bx[3 + k] = fmax(bx[3 + k], __shfl_xor(bx[3 + k], o));
                         }
-                        if (PREC == 0) keep = keep && (float)g2 <= S.T2f;
-                        else keep = keep && (double)g2 <= S.T2d;
-                    } else {
-                        Tt tol = PREC == 0 ? (Tt)S.c.box_tol : (Tt)0;
+                    if ((sa || sb) && (j & 7) == 0)
 #pragma unroll
-                        for (int k = 0; k < 3; k++)
-                            keep = keep && sB[(F_LO + k) * TK + b] - ahi[k] <= tol &&
-                                   alo[k] - sB[(F_HI + k) * TK + b] <= tol;
-                    }
-                    list_push(keep, a, b, list, &S.cnt);
+                        for (int k = 0; k < 6; k++) gbox[sa ? 0 : 1][j >> 3][k] = bx[k];
                 }
+            }
+            __syncthreads();
+            // phase 1a: group-box pairs, compacted into glist
+            {
+                const int ga = tid / NG, gb = tid % NG;
+                bool keep = tid < NGP && ga * 8 < S.na && gb * 8 < S.nb;
+                if (keep) {
+                    const Tt alo[3] = {gbox[0][ga][0], gbox[0][ga][1], gbox[0][ga][2]};
+                    const Tt ahi[3] = {gbox[0][ga][3], gbox[0][ga][4], gbox[0][ga][5]};
+                    const Tt blo[3] = {gbox[1][gb][0], gbox[1][gb][1], gbox[1][gb][2]};
+                    const Tt bhi[3] = {gbox[1][gb][3], gbox[1][gb][4], gbox[1][gb][5]};
+                    if (MODE == 0) {
+                        Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
+                        if (PREC == 0) keep = (float)g2 <= S.T2f;
+                        else keep = (double)g2 <= S.T2d;
+                    } else {
+                        keep = overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)S.c.box_tol : (Tt)0);
+                    }
+                }
+                if (tid < ((NGP + 63) & ~63)) list_push(keep, ga, gb, glist, &S.gcnt);
+            }
+            __syncthreads();
+            // phase 1b: one wave per surviving group pair, lane -> (a, b)
+            const unsigned gcnt = S.gcnt;
+            for (unsigned gi = w; gi < gcnt; gi += 4) {
+                const uint32_t ge = glist[gi];
+                const int a = (int)(ge & 255) * 8 + (lane_id() >> 3);
+                const int b = (int)((ge >> 8) & 255) * 8 + (lane_id() & 7);
+                bool keep = a < S.na && b < S.nb;
+                const Tt alo[3] = {sA[F_LO * TK + a], sA[(F_LO + 1) * TK + a], sA[(F_LO + 2) * TK + a]};
+                const Tt ahi[3] = {sA[F_HI * TK + a], sA[(F_HI + 1) * TK + a], sA[(F_HI + 2) * TK + a]};
+                const Tt blo[3] = {sB[F_LO * TK + b], sB[(F_LO + 1) * TK + b], sB[(F_LO + 2) * TK + b]};
+                const Tt bhi[3] = {sB[F_HI * TK + b], sB[(F_HI + 1) * TK + b], sB[(F_HI + 2) * TK + b]};
+                if (MODE == 0) {
+                    Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
+                    if (PREC == 0) keep = keep && (float)g2 <= S.T2f;
+                    else keep = keep && (double)g2 <= S.T2d;
+                } else {
+                    keep = keep && overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)S.c.box_tol : (Tt)0);
+                }
+                list_push(keep, a, b, list, &S.cnt);
             }
             __syncthreads();
             const unsigned cnt = S.cnt;
             n_eval += tid == 0;
-            n_boxed += tid == 0 ? (unsigned long long)S.na * S.nb : 0;
+            n_boxed += tid == 0 ? (unsigned long long)NGP + 64ull * gcnt : 0;
             n_tested += tid == 0 ? cnt : 0;
             // phase 2: full tests of the surviving pairs
             Tt tmin = (Tt)__builtin_inf();
