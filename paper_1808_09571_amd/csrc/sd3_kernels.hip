@@ -239,53 +239,71 @@ struct MortonSide {
     const unsigned long long *box;
 };
 
-// One block per radix-sort block of RS_ITEMS keys, so that the histogram of
-// the sort's first digit is counted here (written as hist[digit * nblocks +
-// block], the layout the scan expects).
+// One block of 1024 threads per radix-sort block of RS_ITEMS keys, so that
+// the histogram of the sort's first digit is counted here (written as
+// hist[digit * nblocks + block], the layout the scan expects).  Each thread
+// takes 4 items and issues all their index loads, then all their vertex
+// loads, before any store.
 template <typename KT>
-__global__ __launch_bounds__(256) void k_morton(MortonSide A, MortonSide B, int64_t G, int mbits,
-                                                uint64_t side_key, KT *keys, int32_t *vals,
-                                                uint32_t *hist, int nblocks) {
+__global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, int64_t G, int mbits,
+                                                 uint64_t side_key, KT *keys, int32_t *vals,
+                                                 uint32_t *hist, int nblocks) {
+    constexpr int PER = RS_ITEMS / 1024;
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t n = A.nt + B.nt;
-    for (int r = 0; r < RS_ITEMS / 256; r++) {
-        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 256 + threadIdx.x;
-        if (i >= n) break;
-        const bool sa = i < A.nt;
-        const MortonSide &S = sa ? A : B;
-        const int64_t t = sa ? i : i - A.nt;
-        int64_t g = find_row(S.t_off, G, t);
-        const double *X = S.xyz + 3 * S.v_off[g];
-        const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
-        uint32_t q[3];
-        double cen[3] = {0.0, 0.0, 0.0};
-        for (int v = 0; v < 3; v++) {
-            const double *p = X + 3 * corner(S.tri, t, v, nvr);
-            cen[0] += p[0];
-            cen[1] += p[1];
-            cen[2] += p[2];
-        }
+    int64_t vi[PER][3], g[PER];
+    bool ok[PER], sa[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
+        ok[r] = i < n;
+        sa[r] = i < A.nt;
+        const MortonSide &S = sa[r] ? A : B;
+        const int64_t t = ok[r] ? (sa[r] ? i : i - A.nt) : 0;
+        g[r] = ok[r] ? find_row(S.t_off, G, t) : 0;
+        const int64_t nvr = S.v_off[g[r] + 1] - S.v_off[g[r]];
+#pragma unroll
+        for (int k = 0; k < 3; k++) vi[r][k] = ok[r] ? S.v_off[g[r]] + corner(S.tri, t, k, nvr) : 0;
+    }
+    double cen[PER][3];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const double *X = sa[r] ? A.xyz : B.xyz;
+        for (int c = 0; c < 3; c++) cen[r][c] = 0.0;
+        if (!ok[r]) continue;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) cen[r][c] += X[3 * vi[r][k] + c];
+    }
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        if (!ok[r]) continue;
+        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
+        const MortonSide &S = sa[r] ? A : B;
+        const int64_t gr = g[r];
         double lo[3], ext = 0.0;
         for (int k = 0; k < 3; k++) {
-            lo[k] = from_ordered_bits(S.box[g * 6 + k]);
-            ext = fmax(ext, from_ordered_bits(S.box[g * 6 + 3 + k]) - lo[k]);
+            lo[k] = from_ordered_bits(S.box[gr * 6 + k]);
+            ext = fmax(ext, from_ordered_bits(S.box[gr * 6 + 3 + k]) - lo[k]);
         }
         const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
+        uint32_t q[3];
         for (int k = 0; k < 3; k++) {
-            double f = (cen[k] * (1.0 / 3.0) - lo[k]) * sc;
+            double f = (cen[r][k] * (1.0 / 3.0) - lo[k]) * sc;
             int qi = (int)f;
             q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
         }
         uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-        const KT key = (KT)((sa ? 0ull : side_key) | ((uint64_t)g << mbits) | (code >> (30 - mbits)));
+        const KT key = (KT)((sa[r] ? 0ull : side_key) | ((uint64_t)gr << mbits) | (code >> (30 - mbits)));
         keys[i] = key;
-        vals[i] = (int32_t)t;
+        vals[i] = (int32_t)(sa[r] ? i : i - A.nt);
         atomicAdd(&h[(uint32_t)key & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Stable LSD radix sort, 8-bit digits.  Blocks of 256 threads own 4096
@@ -643,12 +661,12 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStr
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(256), 0, s, ma, mb, A.G, K.mbits,
+            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(1024), 0, s, ma, mb, A.G, K.mbits,
                                1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     } else {
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(256), 0, s, ma, mb, A.G, K.mbits,
+            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(1024), 0, s, ma, mb, A.G, K.mbits,
                                1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
@@ -1103,7 +1121,14 @@ __device__ __forceinline__ bool overlap_boxes(const T (&alo)[3], const T (&ahi)[
     return keep;
 }
 
+constexpr int QB = 8;  // most queue entries a block claims per refill
+
 struct TPShared {
+    int2 be[QB];              // prefetched queue entries, their bounds and tiles
+    float blb[QB];
+    TileMeta bmA[QB], bmB[QB];
+    unsigned bq0;             // queue index of be[0]
+    int bn, bi, qb;           // entries prefetched, next to take, entries per refill
     int q, live, ta, tb, g, na, nb, logged;
     float lbf;
     double ub, m;
@@ -1117,19 +1142,55 @@ struct TPShared {
     double redd[4];
 };
 
-// Thread 0 dequeues the next tile pair and computes its constants.
-__device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned qcount,
-                                           const TileMeta *mA, const TileMeta *mB,
-                                           RowState *rows, int precision, int mode, bool first) {
-    unsigned q = first ? (unsigned)blockIdx.x : gridDim.x + atomicAdd(L.qhead, 1u);
-    S.q = (int)q;
+// Wave 0 claims the next batch of up to S.qb queue entries (a block's first
+// batch is its static share, later ones come from the shared head) and
+// gathers the entries, their bounds and both tiles' metadata into LDS, one
+// lane per load.
+__device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned qcount,
+                                          const TileMeta *mA, const TileMeta *mB, bool first) {
+    const int lane = lane_id();
+    const unsigned qb = (unsigned)S.qb;
+    unsigned q0 = 0;
+    if (lane == 0) q0 = (first ? (unsigned)blockIdx.x : gridDim.x + atomicAdd(L.qhead, 1u)) * qb;
+    q0 = __shfl(q0, 0);
+    int ex = 0, ey = 0;
+    if ((unsigned)lane < qb && q0 + lane < qcount) {
+        const int2 e = L.queue[q0 + lane];
+        ex = e.x;
+        ey = e.y;
+        S.be[lane] = e;
+        S.blb[lane] = L.qlb[q0 + lane];
+    }
+    const int k = lane >> 1;
+    const int tx = __shfl(ex, k), ty = __shfl(ey, k);
+    if (lane < 2 * QB && (unsigned)k < qb && q0 + k < qcount) {
+        if (lane & 1) S.bmB[k] = mB[ty];
+        else S.bmA[k] = mA[tx];
+    }
+    if (lane == 0) {
+        S.bq0 = q0;
+        S.bn = q0 < qcount ? (int)min(qb, qcount - q0) : 0;
+        S.bi = 0;
+    }
+}
+
+// Thread 0 takes the next prefetched tile pair, reads its row's state and
+// computes its constants; S.q = -1 once the block's batch is empty.
+__device__ __forceinline__ void tp_pop(TPShared &S, const Lists &L, RowState *rows, int precision,
+                                       int mode) {
     S.live = 0;
     S.cnt = 0;
     S.gcnt = 0;
-    if (q >= qcount) return;
-    int2 e = L.queue[q];
-    const TileMeta &a = mA[e.x];
-    const TileMeta &b = mB[e.y];
+    if (S.bi >= S.bn) {
+        S.q = -1;
+        return;
+    }
+    const int k = S.bi++;
+    const unsigned q = S.bq0 + (unsigned)k;
+    S.q = (int)q;
+    const int2 e = S.be[k];
+    const TileMeta &a = S.bmA[k];
+    const TileMeta &b = S.bmB[k];
     RowState *R = rows + a.row;
     double ub = bits_to_double(load_acq(&R->ub));
     uint32_t hit = load_acq32(&R->hit);
@@ -1141,7 +1202,7 @@ __device__ __forceinline__ void tp_dequeue(TPShared &S, const Lists &L, unsigned
     S.nb = b.n;
     S.ub = ub;
     S.m = m;
-    S.lbf = L.qlb[q];
+    S.lbf = S.blb[k];
     S.logged = 0;
     if (hit) return;
     if (!L.seed_pass && (int)q == R->seed_q) return;  // already evaluated as the seed
@@ -1242,13 +1303,25 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned qcount = min(*L.qcount, L.qcap);
     unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0;
-    // first entry: blockIdx.x (no atomic); later entries from the shared head,
-    // which starts at gridDim.x
-    if ((unsigned)blockIdx.x >= qcount) return;
-    for (bool first = true;; first = false) {
-        if (tid == 0) tp_dequeue(S, L, qcount, mA, mB, rows, PREC, MODE, first);
+    // entries per refill: 1 for short queues (every block starts at once), up
+    // to QB for long ones (one atomic and one gather per batch)
+    if (tid == 0) {
+        S.qb = (int)max(1u, min((unsigned)QB, qcount / (gridDim.x * 4u)));
+        S.bi = 0;
+        S.bn = 0;
+    }
+    __syncthreads();
+    if ((unsigned)blockIdx.x * (unsigned)S.qb >= qcount) return;
+    bool first = true;
+    for (;;) {
+        if (S.bi >= S.bn) {  // block-uniform: written by thread 0 before the last barrier
+            if (w == 0) tp_refill(S, L, qcount, mA, mB, first);
+            first = false;
+            __syncthreads();
+        }
+        if (tid == 0) tp_pop(S, L, rows, PREC, MODE);
         __syncthreads();
-        if ((unsigned)S.q >= qcount) break;
+        if (S.q < 0) break;
         if (S.live) {
             // threads [0, TK) stage A's slots, threads [128, 128 + TK) B's;
             // each group of 8 consecutive staging lanes reduces its group box
