@@ -38,14 +38,14 @@ struct SideState {
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, small, grpA, grpB, wi_lb, seedq, seedlb, wlist;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, small, grpA, grpB, wi_lb, seedq, seedlb, wlist;
     void release_all() {
         for (auto &sd : side) {
             DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &small, &grpA, &grpB, &wi_lb, &seedq,
+                        &vals0, &vals1, &hist, &part, &rowid, &small, &grpA, &grpB, &wi_lb, &seedq,
                         &seedlb, &wlist};
         for (DevBuf *b : bs) release(*b);
     }
@@ -405,6 +405,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.vals[1] = (int32_t *)ensure(ws.vals1, sizeof(int32_t) * n);
         C.PB.hist = (uint32_t *)ensure(ws.hist, sizeof(uint32_t) * 256 * nb);
         C.PB.part = (uint32_t *)ensure(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
+        C.PB.rowid = (int32_t *)ensure(ws.rowid, sizeof(int32_t) * (n > 0 ? n : 1));
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;
@@ -469,7 +470,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
 
 // Device validation (flags in the scalar block) fused with the row boxes: the
 // first kernels of every call (host inputs were also checked on the host).
-void enqueue_validate(Call &C, hipStream_t s) { launch_validate_rowbox(C.A, C.B, C.flags, s); }
+void enqueue_validate(Call &C, hipStream_t s) { launch_validate_rowbox(C.A, C.B, C.PB, C.flags, s); }
 
 // Every kernel of the call after validation, in stream order, with no host
 // synchronisation (graph capture records exactly this).

@@ -44,6 +44,7 @@ struct PrepBufs {
     int32_t *vals[2];
     uint32_t *hist;     // [256 * blocks]
     uint32_t *part;     // [chunks]
+    int32_t *rowid;     // [ntA + ntB] row of each sort item (written by validation)
 };
 
 // Counters (device, unsigned long long[16]).
@@ -97,7 +98,7 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
 // Validation of both sides (flags[0] for A, flags[1] for B) fused with the
 // row bounding boxes (one read of xyz): clears the flags and boxes, checks
 // every coordinate and every triangle index, and reduces the row boxes.
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream_t s);
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, hipStream_t s);
 // Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
 // `passes` 8-bit radix passes (total bits = 8 * passes at most).
 struct SortKey {

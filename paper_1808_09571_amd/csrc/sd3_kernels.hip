@@ -57,30 +57,41 @@ __device__ __forceinline__ uint32_t coord_flags(double v) {
     return 0u;
 }
 
-// Every triangle index of both sides must lie inside its row (grid-stride
-// over A's triangles, then B's).
-__global__ void k_validate_tri(const int32_t *triA, int64_t ntA, const int64_t *voA,
-                               const int64_t *toA, const int32_t *triB, int64_t ntB,
-                               const int64_t *voB, const int64_t *toB, int64_t G, uint32_t *flags) {
-    uint32_t fa = 0, fb = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntA + ntB;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const bool sa = i < ntA;
-        const int64_t t = sa ? i : i - ntA;
-        const int32_t *tri = sa ? triA : triB;
-        const int64_t *v_off = sa ? voA : voB;
-        int64_t g = find_row(sa ? toA : toB, G, t);
-        int64_t nvr = v_off[g + 1] - v_off[g];
-        uint32_t f = 0;
+// Every triangle index of both sides must lie inside its row.  Blocks own
+// contiguous ranges of VT_ITEMS triangles of one side (A's blocks first);
+// one binary search finds the row of a block's first triangle and each
+// thread walks forward from it.  The row of every triangle is kept for the
+// key kernel (sort item index: A's triangles, then B's).
+constexpr int VT_ITEMS = 4096;
+
+struct TriSide {
+    const int32_t *tri;
+    int64_t nt;
+    const int64_t *v_off, *t_off;
+    unsigned nblk;
+};
+
+__global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int64_t G,
+                                                      uint32_t *flags, int32_t *rowid) {
+    __shared__ int64_t g0s;
+    const bool sa = blockIdx.x < A.nblk;
+    const TriSide &S = sa ? A : B;
+    const int64_t t0 = (int64_t)(sa ? blockIdx.x : blockIdx.x - A.nblk) * VT_ITEMS;
+    const int64_t t1 = min(S.nt, t0 + VT_ITEMS);
+    if (threadIdx.x == 0) g0s = find_row(S.t_off, G, t0);
+    __syncthreads();
+    int64_t g = g0s;
+    uint32_t f = 0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        while (S.t_off[g + 1] <= t) g++;
+        const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
         for (int k = 0; k < 3; k++) {
-            int32_t v = tri[3 * t + k];
+            int32_t v = S.tri[3 * t + k];
             if (v < 0 || v >= nvr) f = V_INDEX;
         }
-        if (sa) fa |= f;
-        else fb |= f;
+        rowid[(sa ? 0 : A.nt) + t] = (int32_t)g;
     }
-    if (fa) atomicOr(flags, fa);
-    if (fb) atomicOr(flags + 1, fb);
+    if (f) atomicOr(flags + (sa ? 0 : 1), f);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,10 +206,10 @@ __global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, int64_t G,
 static unsigned rowbox_blocks(int64_t nv) {
     if (nv <= 0) return 0;
     unsigned g = grid_for(nv, 2048);
-    return g > 512 ? 512 : g;
+    return g > 8192 ? 8192 : g;
 }
 
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream_t s) {
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, hipStream_t s) {
     const int64_t G = A.G;
     hipLaunchKernelGGL(k_prep_init, dim3(grid_for(G * 6 > 2 ? G * 6 : 2, 256)), dim3(256), 0, s,
                        flags, A.rowbox, B.rowbox, G);
@@ -206,12 +217,11 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, uint32_t *flags, hipStream
     XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv)};
     if (xa.nblk + xb.nblk > 0)
         hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
-    if (A.nt + B.nt > 0) {
-        unsigned g = grid_for(A.nt + B.nt, 256);
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(k_validate_tri, dim3(g), dim3(256), 0, s, A.tri, A.nt, A.v_off, A.t_off,
-                           B.tri, B.nt, B.v_off, B.t_off, G, flags);
-    }
+    TriSide ta{A.tri, A.nt, A.v_off, A.t_off, grid_for(A.nt, VT_ITEMS)};
+    TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
+    if (ta.nblk + tb.nblk > 0)
+        hipLaunchKernelGGL(k_validate_tri, dim3(ta.nblk + tb.nblk), dim3(256), 0, s, ta, tb, G, flags,
+                           P.rowid);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -224,7 +234,7 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 }
 
 // key = side << rowbits+mbits | row << mbits | the top mbits of the 30-bit
-// Morton code of the triangle centroid, quantised on cubic cells of the row
+// Morton code of the triangle's first vertex, quantised on cubic cells of the row
 // box (the largest extent / 1024 on every axis, so a flat surface spends its
 // bits on its two long axes); value = triangle index within its side.  Both
 // sides in one launch (A's triangles, then B's), keys written at the width
@@ -245,38 +255,38 @@ struct MortonSide {
 // takes 4 items and issues all their index loads, then all their vertex
 // loads, before any store.
 template <typename KT>
-__global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, int64_t G, int mbits,
-                                                 uint64_t side_key, KT *keys, int32_t *vals,
+__global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, const int32_t *rowid,
+                                                 int mbits, uint64_t side_key, KT *keys, int32_t *vals,
                                                  uint32_t *hist, int nblocks) {
     constexpr int PER = RS_ITEMS / 1024;
     __shared__ uint32_t h[256];
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t n = A.nt + B.nt;
-    int64_t vi[PER][3], g[PER];
+    int64_t vi[PER], g[PER];
     bool ok[PER], sa[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
         ok[r] = i < n;
         sa[r] = i < A.nt;
+        g[r] = ok[r] ? rowid[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
         const MortonSide &S = sa[r] ? A : B;
         const int64_t t = ok[r] ? (sa[r] ? i : i - A.nt) : 0;
-        g[r] = ok[r] ? find_row(S.t_off, G, t) : 0;
         const int64_t nvr = S.v_off[g[r] + 1] - S.v_off[g[r]];
-#pragma unroll
-        for (int k = 0; k < 3; k++) vi[r][k] = ok[r] ? S.v_off[g[r]] + corner(S.tri, t, k, nvr) : 0;
+        vi[r] = ok[r] ? S.v_off[g[r]] + corner(S.tri, t, 0, nvr) : 0;
     }
+    // the key point is the triangle's first vertex (keys only order work)
     double cen[PER][3];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         const double *X = sa[r] ? A.xyz : B.xyz;
-        for (int c = 0; c < 3; c++) cen[r][c] = 0.0;
-        if (!ok[r]) continue;
 #pragma unroll
-        for (int k = 0; k < 3; k++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) cen[r][c] += X[3 * vi[r][k] + c];
+        for (int c = 0; c < 3; c++) cen[r][c] = ok[r] ? X[3 * vi[r] + c] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < PER; r++) {
@@ -292,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, int
         const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
         uint32_t q[3];
         for (int k = 0; k < 3; k++) {
-            double f = (cen[r][k] * (1.0 / 3.0) - lo[k]) * sc;
+            double f = (cen[r][k] - lo[k]) * sc;
             int qi = (int)f;
             q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
         }
@@ -361,51 +371,6 @@ __global__ __launch_bounds__(1024) void k_scan_local(uint32_t *a, int64_t total,
         run += v[k];
     }
     if (tid == 1023) part[blockIdx.x] = wbase + inc;
-}
-
-// The whole (digit, block) histogram in one block when it has at most
-// 16 * SCAN_CHUNK entries: full prefixes in place, chunk offsets zeroed.
-// Rounds of 16384 entries are staged through LDS with coalesced loads and
-// stores; thread t scans its 16 consecutive entries (a padding word after
-// every 16 keeps those reads on distinct banks).
-__global__ __launch_bounds__(1024) void k_scan_single(uint32_t *a, int64_t total, uint32_t *part,
-                                                      int nchunk) {
-    constexpr int ROUND = 16384, PER = 16;
-    __shared__ uint32_t buf[ROUND + ROUND / PER];
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry_s;
-    const int tid = threadIdx.x;
-    auto phys = [](int j) { return j + j / PER; };
-    if (tid == 0) carry_s = 0u;
-    for (int64_t base = 0; base < total; base += ROUND) {
-        for (int k = 0; k < PER; k++) {
-            int j = k * 1024 + tid;
-            buf[phys(j)] = base + j < total ? a[base + j] : 0u;
-        }
-        __syncthreads();
-        uint32_t v[PER], sum = 0;
-        for (int k = 0; k < PER; k++) {
-            v[k] = buf[phys(tid * PER + k)];
-            sum += v[k];
-        }
-        uint32_t inc = wave_incl_scan(sum);
-        if (lane_id() == 63) wsum[tid >> 6] = inc;
-        __syncthreads();
-        uint32_t run = carry_s + inc - sum;
-        for (int w = 0; w < (tid >> 6); w++) run += wsum[w];
-        for (int k = 0; k < PER; k++) {
-            buf[phys(tid * PER + k)] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        for (int k = 0; k < PER; k++) {
-            int j = k * 1024 + tid;
-            if (base + j < total) a[base + j] = buf[phys(j)];
-        }
-        if (tid == 1023) carry_s = run;
-        __syncthreads();
-    }
-    if (tid < nchunk) part[tid] = 0u;
 }
 
 __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
@@ -519,12 +484,8 @@ static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part,
     for (int shift = 0; shift < bits; shift += 8) {
         if (shift > 0)
             hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
-        if (nchunk <= 16) {
-            hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, hist, total, part, nchunk);
-        } else {
-            hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
-        }
+        hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
         hipLaunchKernelGGL(k_scatter<KT>, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
                            keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb);
@@ -661,12 +622,12 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStr
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(1024), 0, s, ma, mb, A.G, K.mbits,
+            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid, K.mbits,
                                1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     } else {
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(1024), 0, s, ma, mb, A.G, K.mbits,
+            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid, K.mbits,
                                1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
         cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
@@ -1127,6 +1088,7 @@ struct TPShared {
     int2 be[QB];              // prefetched queue entries, their bounds and tiles
     float blb[QB];
     TileMeta bmA[QB], bmB[QB];
+    RowState brow[QB];        // the rows' state when the batch was gathered
     unsigned bq0;             // queue index of be[0]
     int bn, bi, qb;           // entries prefetched, next to take, entries per refill
     int q, live, ta, tb, g, na, nb, logged;
@@ -1147,7 +1109,8 @@ struct TPShared {
 // gathers the entries, their bounds and both tiles' metadata into LDS, one
 // lane per load.
 __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned qcount,
-                                          const TileMeta *mA, const TileMeta *mB, bool first) {
+                                          const TileMeta *mA, const TileMeta *mB,
+                                          const RowState *rows, bool first) {
     const int lane = lane_id();
     const unsigned qb = (unsigned)S.qb;
     unsigned q0 = 0;
@@ -1163,10 +1126,19 @@ __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned 
     }
     const int k = lane >> 1;
     const int tx = __shfl(ex, k), ty = __shfl(ey, k);
+    int row = 0;
     if (lane < 2 * QB && (unsigned)k < qb && q0 + k < qcount) {
-        if (lane & 1) S.bmB[k] = mB[ty];
-        else S.bmA[k] = mA[tx];
+        if (lane & 1) {
+            S.bmB[k] = mB[ty];
+        } else {
+            S.bmA[k] = mA[tx];
+            row = S.bmA[k].row;
+        }
     }
+    // the rows' state, one lane per entry (a stale upper bound is still an
+    // upper bound: it only prunes less)
+    const int rk = __shfl(row, 2 * (lane & (QB - 1)));
+    if (lane < QB && (unsigned)lane < qb && q0 + lane < qcount) S.brow[lane] = rows[rk];
     if (lane == 0) {
         S.bq0 = q0;
         S.bn = q0 < qcount ? (int)min(qb, qcount - q0) : 0;
@@ -1191,9 +1163,9 @@ __device__ __forceinline__ void tp_pop(TPShared &S, const Lists &L, RowState *ro
     const int2 e = S.be[k];
     const TileMeta &a = S.bmA[k];
     const TileMeta &b = S.bmB[k];
-    RowState *R = rows + a.row;
-    double ub = bits_to_double(load_acq(&R->ub));
-    uint32_t hit = load_acq32(&R->hit);
+    const RowState *R = &S.brow[k];
+    double ub = bits_to_double(R->ub);
+    uint32_t hit = R->hit;
     double m = row_margin(*R, ub);
     S.ta = e.x;
     S.tb = e.y;
@@ -1315,7 +1287,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     bool first = true;
     for (;;) {
         if (S.bi >= S.bn) {  // block-uniform: written by thread 0 before the last barrier
-            if (w == 0) tp_refill(S, L, qcount, mA, mB, first);
+            if (w == 0) tp_refill(S, L, qcount, mA, mB, rows, first);
             first = false;
             __syncthreads();
         }
