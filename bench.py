@@ -45,15 +45,17 @@ METRIC = "tri-pair tests/s + geometry-pairs/s, FP32+learned vs plain FP64, exact
 FLOPS_FP32_PAIR = 711   # full FP32 triangle-pair test: 9 edge/edge, 6 vertex/face, bound
 FLOPS_BOX = 12          # triangle bounding-box lower bound per boxed pair
 FLOPS_TRI_PREP = 64     # per staged triangle (edges, reciprocals, dual basis, box)
-# Algorithmic bytes of tile building per triangle: sorted index 4, triangle
-# indices 12, three FP64 vertices 72 (read); FP64 copy 72, FP32 copy 36 (write)
-BYTES_TILE_TRI = 4 + 12 + 72 + 72 + 36
+# Algorithmic bytes of tile building per triangle on the FP32 path: sorted
+# index 4, triangle indices 12, three FP64 vertices 72 (read); FP32 copy 36,
+# slot triangle id 4 (write)
+BYTES_TILE_TRI = 4 + 12 + 72 + 36 + 4
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30    # --copy-calibration: 1 GiB read + 1 GiB written
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tin512_pair.json")
+TRAFFIC_FILES = {"tin512": "traffic_tin512_pair.json", "batch4096": "traffic_batch4096.json",
+                 "scale": "traffic_scale_tin_blob.json"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_09571_amd", "csrc", "sd3_kernels.hip")
 
 
@@ -76,11 +78,11 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from committed PMC counters, or None when the
-    kernel source changed since they were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed PMC counters of this workload, or
+    None when the kernel source changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -102,7 +104,7 @@ def copy_calibration():
                       "launches": 3}))
 
 
-def roofline_for(kernel, st_list, ms, n):
+def roofline_for(kernel, st_list, ms, n, workload):
     """Roofline object of one instrumented kernel class over a step.
     st_list: stats of the step's calls; ms / n: its summed time / launches."""
     avg = ms / max(n, 1)
@@ -113,7 +115,7 @@ def roofline_for(kernel, st_list, ms, n):
         ach = per / (avg * 1e-3) / 1e9
         return {"kernel": "k_scatter (radix sort pass)", "bound": "hbm", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": measured_traffic("k_scatter"), "avg_launch_ms": avg,
+                "traffic": measured_traffic("k_scatter", workload), "avg_launch_ms": avg,
                 "algorithmic_bytes_per_launch": per,
                 "per_unit": f"{2 * (kb + 4)} B per key ({kb} B key + 4 B value, read + write)"}
     if kernel == "tiles":
@@ -121,7 +123,7 @@ def roofline_for(kernel, st_list, ms, n):
         per = tris * BYTES_TILE_TRI
         ach = per / (avg * 1e-3) / 1e9
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("k_tiles"),
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("k_tiles", workload),
                 "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per,
                 "per_unit": f"{BYTES_TILE_TRI} B per triangle"}
     raise KeyError(kernel)
@@ -290,7 +292,7 @@ def main():
     hbm_classes = [k for k in ("scatter", "tiles") if kn.get(k)]
     dom = max(kms, key=lambda k: kms[k])
     if dom in hbm_classes:
-        roof = roofline_for(dom, [sd, si], kms[dom], kn[dom])
+        roof = roofline_for(dom, [sd, si], kms[dom], kn[dom], args.workload)
     else:
         roof = pairs_roofline(sd, sd["ms_kernel"]["pairs"], max(sd["n_kernel"]["pairs"], 1))
     roof["dominant_by_time"] = dom
