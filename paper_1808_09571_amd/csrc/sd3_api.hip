@@ -470,7 +470,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
 
 // Device validation (flags in the scalar block) fused with the row boxes: the
 // first kernels of every call (host inputs were also checked on the host).
-void enqueue_validate(Call &C, hipStream_t s) { launch_validate_rowbox(C.A, C.B, C.PB, C.flags, s); }
+void enqueue_validate(Call &C, hipStream_t s) {
+    launch_validate_rowbox(C.A, C.B, C.PB, C.flags, C.rows, C.L, s);
+}
 
 // Every kernel of the call after validation, in stream order, with no host
 // synchronisation (graph capture records exactly this).
@@ -486,10 +488,10 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
     launch_prep(A, B, C.PB, sort_key(G), s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
-    launch_rows_init(C.rows, G, A.rowbox, B.rowbox, L, s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
-    if (mode == 0) launch_row_scale(C.rows, G, s);
+    // (a single queue pass sets the row scales in its work-item compaction)
+    if (mode == 0 && !Q.compact) launch_row_scale(C.rows, G, s);
     for (int64_t w0 = 0; w0 < C.n_wi; w0 += C.per_pass) {
         int64_t nw = std::min(C.per_pass, C.n_wi - w0);
         if (w0 > 0) launch_reset_queue(L, s);

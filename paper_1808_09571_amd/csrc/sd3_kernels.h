@@ -97,8 +97,11 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
 
 // Validation of both sides (flags[0] for A, flags[1] for B) fused with the
 // row bounding boxes (one read of xyz): clears the flags and boxes, checks
-// every coordinate and every triangle index, and reduces the row boxes.
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, hipStream_t s);
+// every coordinate and every triangle index, reduces the row boxes, records
+// each sort item's row, starts the row states from the boxes and clears the
+// work-list scalars and counters.
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, RowState *rows,
+                            Lists &L, hipStream_t s);
 // Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
 // `passes` 8-bit radix passes (total bits = 8 * passes at most).
 struct SortKey {
@@ -109,9 +112,7 @@ SortKey sort_key(int64_t G);
 // Morton keys of both sides, the radix sort and the tiles.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
                  KernelEvents *kev);
-// Row state from both row boxes, and cleared work-list scalars and counters.
-void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                      const unsigned long long *boxB, Lists &L, hipStream_t s);
+
 // Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
 struct GroupBox {
     double lo[3], hi[3], rep[3];

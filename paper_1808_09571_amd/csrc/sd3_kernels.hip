@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t coord_flags(double v) {
 // one binary search finds the row of a block's first triangle and each
 // thread walks forward from it.  The row of every triangle is kept for the
 // key kernel (sort item index: A's triangles, then B's).
-constexpr int VT_ITEMS = 4096;
+constexpr int VT_ITEMS = 1024;
 
 struct TriSide {
     const int32_t *tri;
@@ -71,9 +71,24 @@ struct TriSide {
     unsigned nblk;
 };
 
+__device__ void row_init(RowState *rows, int64_t g, const unsigned long long *boxA,
+                         const unsigned long long *boxB);
+
+// The same launch starts every row's state from both row boxes (computed by
+// the previous kernel) and clears the work-list scalars and counters.
 __global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int64_t G,
-                                                      uint32_t *flags, int32_t *rowid) {
+                                                      uint32_t *flags, int32_t *rowid,
+                                                      RowState *rows, const unsigned long long *boxA,
+                                                      const unsigned long long *boxB, Lists L) {
     __shared__ int64_t g0s;
+    {
+        const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+        if (i < 12) L.qcount[i] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
+                                      // items); 12-13 hold the validation flags
+        if (i < C_NCOUNTERS) L.counters[i] = 0;
+        for (int64_t g = i; g < G; g += (int64_t)gridDim.x * blockDim.x) row_init(rows, g, boxA, boxB);
+    }
+    if (blockIdx.x >= A.nblk + B.nblk) return;
     const bool sa = blockIdx.x < A.nblk;
     const TriSide &S = sa ? A : B;
     const int64_t t0 = (int64_t)(sa ? blockIdx.x : blockIdx.x - A.nblk) * VT_ITEMS;
@@ -205,11 +220,12 @@ __global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, int64_t G,
 
 static unsigned rowbox_blocks(int64_t nv) {
     if (nv <= 0) return 0;
-    unsigned g = grid_for(nv, 2048);
+    unsigned g = grid_for(nv, 1024);
     return g > 8192 ? 8192 : g;
 }
 
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, hipStream_t s) {
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, RowState *rows,
+                            Lists &L, hipStream_t s) {
     const int64_t G = A.G;
     hipLaunchKernelGGL(k_prep_init, dim3(grid_for(G * 6 > 2 ? G * 6 : 2, 256)), dim3(256), 0, s,
                        flags, A.rowbox, B.rowbox, G);
@@ -219,9 +235,9 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
         hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
     TriSide ta{A.tri, A.nt, A.v_off, A.t_off, grid_for(A.nt, VT_ITEMS)};
     TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
-    if (ta.nblk + tb.nblk > 0)
-        hipLaunchKernelGGL(k_validate_tri, dim3(ta.nblk + tb.nblk), dim3(256), 0, s, ta, tb, G, flags,
-                           P.rowid);
+    // at least one block: it also starts the row states and clears the counters
+    hipLaunchKernelGGL(k_validate_tri, dim3(ta.nblk + tb.nblk > 0 ? ta.nblk + tb.nblk : 1), dim3(256), 0,
+                       s, ta, tb, G, flags, P.rowid, rows, A.rowbox, B.rowbox, L);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -389,11 +405,13 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
 // the same digit); per-wave running digit counts live in LDS, so ranking
 // needs no block-wide barrier.  The block then places its items in LDS in
 // digit order and writes each digit's run to consecutive global addresses.
+// With at most 256 scan chunks the block scans the chunk totals itself
+// (ncraw > 0: part holds raw totals), which saves the top-level scan launch.
 template <typename KT>
 __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *vin, KT *kout,
                                                  int32_t *vout, int64_t n, int shift,
                                                  const uint32_t *hist, const uint32_t *part,
-                                                 int nblocks) {
+                                                 int nblocks, int ncraw) {
     constexpr int Q = RS_ITEMS / 4;   // items per wave
     constexpr int R = Q / 64;         // rounds per wave
     __shared__ uint32_t wc[4][256];   // per-wave digit counts, then per-wave offsets
@@ -403,7 +421,21 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
     __shared__ int32_t sval[RS_ITEMS];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
-    {
+    if (ncraw > 0) {
+        // exclusive scan of the raw chunk totals (one per thread) into loff
+        __shared__ uint32_t csum[4];
+        uint32_t v = tid < ncraw ? part[tid] : 0u;
+        uint32_t inc = wave_incl_scan(v);
+        if (lane == 63) csum[w] = inc;
+        __syncthreads();
+        uint32_t pre = inc - v;
+        for (int k = 0; k < w; k++) pre += csum[k];
+        loff[tid] = pre;
+        __syncthreads();
+        int64_t e = (int64_t)tid * nblocks + blockIdx.x;
+        gbase[tid] = hist[e] + loff[e / SCAN_CHUNK];
+        __syncthreads();
+    } else {
         int64_t e = (int64_t)tid * nblocks + blockIdx.x;
         gbase[tid] = hist[e] + part[e / SCAN_CHUNK];
     }
@@ -485,10 +517,13 @@ static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part,
         if (shift > 0)
             hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
         hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
+        const bool inline_top = nchunk <= 256;
+        if (!inline_top)
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
         hipLaunchKernelGGL(k_scatter<KT>, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb);
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb,
+                           inline_top ? nchunk : 0);
         if (kev) kev->end(KE_SCATTER, s);
         cur ^= 1;
     }
@@ -527,20 +562,34 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
         lo[k] = __builtin_inf();
         hi[k] = -__builtin_inf();
     }
+    // all loads of both slots first (one chain of memory latency); the loops
+    // are unrolled so that the arrays stay in registers
+    const bool two = tk > 64;
+    int64_t tri_id[2] = {0, 0}, vi[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+        if (r == 0 || two) tri_id[r] = J.sorted[J.t_off[g] + i * tk + min(lane + 64 * r, n - 1)];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) vi[r][k] = (r == 0 || two) ? corner(J.tri, tri_id[r], k, nvr) : 0;
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const double *p = X + 3 * vi[r][k];
+            v[r][3 * k] = (r == 0 || two) ? p[0] : 0.0;
+            v[r][3 * k + 1] = (r == 0 || two) ? p[1] : 0.0;
+            v[r][3 * k + 2] = (r == 0 || two) ? p[2] : 0.0;
+        }
+#pragma unroll
     for (int r = 0; r < 2; r++) {
         const int j = lane + 64 * r;
-        const int64_t tri_id = J.sorted[J.t_off[g] + i * tk + min(j, n - 1)];
-        for (int k = 0; k < 3; k++) {
-            const double *p = X + 3 * corner(J.tri, tri_id, k, nvr);
-            v[r][3 * k] = p[0];
-            v[r][3 * k + 1] = p[1];
-            v[r][3 * k + 2] = p[2];
-        }
         if (j < tk) {
             if (J.t64)
                 for (int c = 0; c < 9; c++) J.t64[(t * 9 + c) * tk + j] = v[r][c];
             else
-                J.ids[t * tk + j] = (int32_t)tri_id;
+                J.ids[t * tk + j] = (int32_t)tri_id[r];
             for (int k = 0; k < 3; k++) {
                 lo[k] = fmin(lo[k], fmin(v[r][k], fmin(v[r][3 + k], v[r][6 + k])));
                 hi[k] = fmax(hi[k], fmax(v[r][k], fmax(v[r][3 + k], v[r][6 + k])));
@@ -553,6 +602,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
         o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
     }
     double err = 0.0, rad = 0.0;
+#pragma unroll
     for (int r = 0; r < 2; r++) {
         const int j = lane + 64 * r;
         if (j >= tk) continue;
@@ -645,13 +695,8 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStr
 // ---------------------------------------------------------------------------
 // row state
 // ---------------------------------------------------------------------------
-__global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                            const unsigned long long *boxB, Lists L) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g < 12) L.qcount[g] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
-                                  // items); 12-13 hold the validation flags
-    if (g < C_NCOUNTERS) L.counters[g] = 0;
-    if (g >= G) return;
+__device__ void row_init(RowState *rows, int64_t g, const unsigned long long *boxA,
+                         const unsigned long long *boxB) {
     RowState r;
     r.ub = double_to_bits(__builtin_inf());
     r.d2 = double_to_bits(__builtin_inf());
@@ -672,11 +717,6 @@ __global__ void k_rows_init(RowState *rows, int64_t G, const unsigned long long 
     rows[g] = r;
 }
 
-void launch_rows_init(RowState *rows, int64_t G, const unsigned long long *boxA,
-                      const unsigned long long *boxB, Lists &L, hipStream_t s) {
-    hipLaunchKernelGGL(k_rows_init, dim3(grid_for(G > 16 ? G : 16, 256)), dim3(256), 0, s, rows, G,
-                       boxA, boxB, L);
-}
 
 // ---------------------------------------------------------------------------
 // a3: tile-pair bounds and the work queue
@@ -805,9 +845,14 @@ __global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t 
 // The work items whose group bound may still hold the row minimum (distance:
 // lower bound <= ub + m; intersects: overlapping groups), compacted so that
 // the tile-level kernels only launch useful workgroups.
+__device__ __forceinline__ void row_scale(RowState *rows, int64_t g);
+
+// With scale_rows, the same launch also sets every row's feature length scale.
 __global__ void k_wi_compact(const float *wi_lb, const int64_t *wi_off, int64_t G, int64_t n_wi,
-                             const RowState *rows, int mode, int32_t *list, unsigned int *count) {
+                             const RowState *rows, int mode, int32_t *list, unsigned int *count,
+                             RowState *scale_rows) {
     int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (scale_rows && wi < G) row_scale(scale_rows, wi);
     bool keep = false;
     if (wi < n_wi) {
         int64_t g = find_row(wi_off, G, wi);
@@ -960,7 +1005,7 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
                            what == Q_SEED ? 1 : 0);
         if (what == Q_SEED) {
             hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
-                               Q.wi_off, A.G, n_wi, rows, 0, Q.wlist, Q.wcount);
+                               Q.wi_off, A.G, n_wi, rows, 0, Q.wlist, Q.wcount, (RowState *)nullptr);
             hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
                                B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, Q.wlist, Q.wcount);
         }
@@ -970,8 +1015,10 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
     if (Q.compact) {
         // single pass over all work items: compact the survivors of the group
         // bound first (the count is read on the device)
-        hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
-                           Q.wi_off, A.G, n_wi, rows, mode, Q.wlist, Q.wcount + 1);
+        const int64_t nthreads = mode == 0 && n_wi < A.G ? A.G : n_wi;
+        hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(nthreads, 256)), dim3(256), 0, s, Q.wi_lb,
+                           Q.wi_off, A.G, n_wi, rows, mode, Q.wlist, Q.wcount + 1,
+                           mode == 0 ? rows : (RowState *)nullptr);
         hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
                            B.tile_off, Q.wi_off, A.G, (int64_t)0, rows, mode, L.queue, L.qlb,
                            L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1);
@@ -1650,12 +1697,16 @@ void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
 // ---------------------------------------------------------------------------
 // seed round: rank the queued tile pairs, evaluate each row's best first
 // ---------------------------------------------------------------------------
-__global__ void k_row_scale(RowState *rows, int64_t G) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= G) return;
+// Feature length scale of a row: its upper bound after seeding, else its extent.
+__device__ __forceinline__ void row_scale(RowState *rows, int64_t g) {
     double ub = bits_to_double(rows[g].ub);
     double ext = rows[g].margin_scale * 0x1p36;
     rows[g].scale = (ub > 0.0 && ub < __builtin_inf()) ? ub : (ext > 0.0 ? ext : 1.0);
+}
+
+__global__ void k_row_scale(RowState *rows, int64_t G) {
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < G) row_scale(rows, g);
 }
 
 void launch_row_scale(RowState *rows, int64_t G, hipStream_t s) {
