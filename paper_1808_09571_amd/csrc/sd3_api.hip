@@ -342,7 +342,11 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     S.v_off = d_offs;
     S.t_off = d_offs + (G + 1);
     S.tile_off = d_offs + 2 * (G + 1);
-    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * (G > 0 ? G : 1));
+    // replicas of the row boxes spread the reduction atomics of many blocks
+    // over one row (at most 2^20 boxes in all)
+    S.boxrep = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 20) / (G > 0 ? G : 1)));
+    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * S.boxrep *
+                                                           (G > 0 ? G : 1));
     S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * tk * S.NT);
     // FP64 tile copies only for the plain FP64 pass; the FP32 path keeps the
     // triangle id of each slot and gathers FP64 vertices for its few rescues
@@ -398,7 +402,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     setup_side(ws, 1, b, P.tileB[G], tk, fp64, ds + 3 * G1, C.B, s);
     {
         int64_t n = C.A.nt + C.B.nt;
-        int64_t nb = (n + 4095) / 4096 + 1;
+        int64_t nb = (n + RS_ITEMS - 1) / RS_ITEMS + 1;
         C.PB.keys[0] = (uint64_t *)ensure(ws.keys0, sizeof(uint64_t) * n);
         C.PB.keys[1] = (uint64_t *)ensure(ws.keys1, sizeof(uint64_t) * n);
         C.PB.vals[0] = (int32_t *)ensure(ws.vals0, sizeof(int32_t) * n);
@@ -441,6 +445,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     L.log = mode == 0 ? opts.log : nullptr;
     L.log_cap = (unsigned long long)opts.log_cap;
     L.log_count = L.counters + C_LOGGED;
+    L.xdone = sc + 11;
 
     const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
     int &gp = ctx->pairs_grid[prec][mode][tk_index(tk)];
@@ -512,7 +517,8 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
             launch_rank(A, B, C.rows, L, C.opts.order == SD3_ORDER_LEARNED ? C.opts.ranker : nullptr,
                         ctx->cus * 2, s);
             launch_seed_build(C.rows, G, L, C.seedq, C.seedlb, LS.qcount, s);
-            launch_pairs(A, B, C.rows, LS, prec, mode, C.grid_pairs, s);
+            // the seed list holds at most one entry per row
+            launch_pairs(A, B, C.rows, LS, prec, mode, (int)std::min<int64_t>(C.grid_pairs, G > 0 ? G : 1), s);
         }
         if (w0 == 0) mark(3);
         if (kev) kev->begin(KE_PAIRS, s);
@@ -523,9 +529,11 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     mark(4);
     if (prec == 0) launch_rescue(A, B, C.rows, L, mode, ctx->cus * 4, s);
     mark(5);
-    launch_exact(A, B, C.rows, L, mode, 64, s);
+    // up to 65536 rows the exact kernel's last block also writes the results
+    const int64_t fin_rows = G <= 65536 ? G : 0;
+    launch_exact(A, B, C.rows, L, mode, 64, s, fin_rows, C.dd, C.hd, C.flags);
     mark(6);
-    launch_finalize(C.rows, G, C.dd, C.hd, L, C.flags, s);
+    if (fin_rows == 0) launch_finalize(C.rows, G, C.dd, C.hd, L, C.flags, s);
 }
 
 sd3_status flags_status(sd3_ctx *ctx, const unsigned int *sc_h) {

@@ -16,7 +16,9 @@ struct SideBufs {
     const int64_t *tile_off;  // [G+1]
     int64_t G, nv, nt, NT;
     int tk;                      // triangles per tile
-    unsigned long long *rowbox;  // [G*6] ordered bits: lo xyz (min), hi xyz (max)
+    int boxrep;                  // replicas of the row boxes (spread the reduction atomics)
+    unsigned long long *rowbox;  // [boxrep][G*6] ordered bits: lo xyz (min), hi xyz (max);
+                                 // replica 0 holds the merged box after validation
     float *t32;                  // [NT*9*tk]: tile t, coordinate c, slot j at (t*9+c)*tk+j
     double *t64;                 // [NT*9*tk] exact copies (plain FP64 path), or nullptr
     int32_t *ids;                // [NT*tk] triangle of each slot (FP32 path), or nullptr
@@ -38,11 +40,16 @@ struct KernelEvents {
     }
 };
 
+// Radix-sort items per block (each block's per-digit histogram is one row of
+// the scanned (digit, block) table): RS_ITEMS for sorts of up to 2^22 keys,
+// twice that above; buffers are sized for RS_ITEMS.
+constexpr int RS_ITEMS = 2048;
+
 // Sort buffers shared by both sides (device).
 struct PrepBufs {
     uint64_t *keys[2];  // [ntA + ntB] ping-pong
     int32_t *vals[2];
-    uint32_t *hist;     // [256 * blocks]
+    uint32_t *hist;     // [256 * blocks], blocks = ceil((ntA + ntB) / RS_ITEMS)
     uint32_t *part;     // [chunks]
     int32_t *rowid;     // [ntA + ntB] row of each sort item (written by validation)
 };
@@ -82,6 +89,7 @@ struct Lists {
     float *log;                    // training log (device) or nullptr
     unsigned long long log_cap;
     unsigned long long *log_count;
+    unsigned int *xdone;           // blocks of the exact kernel that finished
 };
 
 // Validation flags.
@@ -147,8 +155,11 @@ void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
                   int mode, int grid, hipStream_t s);
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                    int grid, hipStream_t s);
+// With fin_rows > 0 the last block of the exact kernel also writes the
+// results (as launch_finalize), which saves a launch.
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
-                  int grid, hipStream_t s);
+                  int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
+                  const uint32_t *vflags);
 // Seed round: k_rank scores every queued tile pair (box lower bound, or the
 // ranker MLP when `ranker` is given) and keeps the best per row; the seeds are
 // copied to `seedq` and evaluated before the main pass.

@@ -71,22 +71,42 @@ struct TriSide {
     unsigned nblk;
 };
 
-__device__ void row_init(RowState *rows, int64_t g, const unsigned long long *boxA,
-                         const unsigned long long *boxB);
-
 // The same launch starts every row's state from both row boxes (computed by
 // the previous kernel) and clears the work-list scalars and counters.
+__device__ void row_init_vals(RowState *rows, int64_t g, const unsigned long long *bA,
+                              const unsigned long long *bB);
+
 __global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int64_t G,
                                                       uint32_t *flags, int32_t *rowid,
-                                                      RowState *rows, const unsigned long long *boxA,
-                                                      const unsigned long long *boxB, Lists L) {
+                                                      RowState *rows, unsigned long long *boxA,
+                                                      unsigned long long *boxB, int rep, Lists L) {
     __shared__ int64_t g0s;
     {
         const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
         if (i < 12) L.qcount[i] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
-                                      // items); 12-13 hold the validation flags
+                                      // items, exact blocks done); 12-13 hold the validation flags
         if (i < C_NCOUNTERS) L.counters[i] = 0;
-        for (int64_t g = i; g < G; g += (int64_t)gridDim.x * blockDim.x) row_init(rows, g, boxA, boxB);
+        // one wave per row: lanes 0-11 merge the box replicas of one component
+        // each (A's lo, hi, then B's), lane 0 starts the row state
+        const int lane = lane_id();
+        const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+        for (int64_t g = i >> 6; g < G; g += nwv) {
+            unsigned long long v = 0;
+            if (lane < 12) {
+                unsigned long long *box = lane < 6 ? boxA : boxB;
+                const int k = lane % 6;
+                v = box[g * 6 + k];
+                for (int r = 1; r < rep; r++) {
+                    unsigned long long w = box[(int64_t)r * G * 6 + g * 6 + k];
+                    v = k < 3 ? min(v, w) : max(v, w);
+                }
+                box[g * 6 + k] = v;
+            }
+            unsigned long long m[12];
+#pragma unroll
+            for (int j = 0; j < 12; j++) m[j] = __shfl(v, j);
+            if (lane == 0) row_init_vals(rows, g, m, m + 6);
+        }
     }
     if (blockIdx.x >= A.nblk + B.nblk) return;
     const bool sa = blockIdx.x < A.nblk;
@@ -114,10 +134,10 @@ __global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int6
 // ---------------------------------------------------------------------------
 // Clears the validation flags of both sides and the row boxes of both sides.
 __global__ void k_prep_init(uint32_t *flags, unsigned long long *boxA, unsigned long long *boxB,
-                            int64_t G) {
+                            int64_t nbox) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < 2) flags[i] = 0u;
-    if (i < G * 6) {
+    if (i < nbox) {
         unsigned long long v = (i % 6) < 3 ? ~0ull : 0ull;
         boxA[i] = v;
         boxB[i] = v;
@@ -162,11 +182,13 @@ struct XyzSide {
     const int64_t *v_off;
     unsigned long long *box;
     unsigned nblk;
+    int rep;  // box replicas: block b reduces into replica b % rep
 };
 
 // The same pass checks every coordinate (finite, magnitude range).
 __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t *flag) {
     __shared__ unsigned long long red[4][6];
+    unsigned long long *box = S.box + (int64_t)(blk % (unsigned)S.rep) * G * 6;
     const int64_t nv = S.nv;
     int64_t per = ((nv + S.nblk - 1) / S.nblk + 255) / 256 * 256;
     int64_t b0 = blk * per, b1 = min(nv, b0 + per);
@@ -186,7 +208,7 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
             }
         if (g0 == g1) {
             if (g0 != cur) {
-                if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
+                if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
                 cur = g0;
             }
             if (valid)
@@ -196,19 +218,19 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
                     hi[k] = max(hi[k], v);
                 }
         } else {
-            if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
+            if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
             cur = -1;
             if (valid) {
                 int64_t g = find_row(S.v_off, G, i);
                 for (int k = 0; k < 3; k++) {
                     unsigned long long v = ordered_bits(x[k]);
-                    atomicMin(&S.box[g * 6 + k], v);
-                    atomicMax(&S.box[g * 6 + 3 + k], v);
+                    atomicMin(&box[g * 6 + k], v);
+                    atomicMax(&box[g * 6 + 3 + k], v);
                 }
             }
         }
     }
-    if (cur >= 0) rowbox_flush(cur, lo, hi, red, S.box);
+    if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
     if (f) atomicOr(flag, f);
 }
 
@@ -227,17 +249,18 @@ static unsigned rowbox_blocks(int64_t nv) {
 void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, RowState *rows,
                             Lists &L, hipStream_t s) {
     const int64_t G = A.G;
-    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(G * 6 > 2 ? G * 6 : 2, 256)), dim3(256), 0, s,
-                       flags, A.rowbox, B.rowbox, G);
-    XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv)};
-    XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv)};
+    const int64_t nbox = (int64_t)A.boxrep * G * 6;
+    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(nbox > 2 ? nbox : 2, 256)), dim3(256), 0, s,
+                       flags, A.rowbox, B.rowbox, nbox);
+    XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv), A.boxrep};
+    XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv), B.boxrep};
     if (xa.nblk + xb.nblk > 0)
         hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
     TriSide ta{A.tri, A.nt, A.v_off, A.t_off, grid_for(A.nt, VT_ITEMS)};
     TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
     // at least one block: it also starts the row states and clears the counters
     hipLaunchKernelGGL(k_validate_tri, dim3(ta.nblk + tb.nblk > 0 ? ta.nblk + tb.nblk : 1), dim3(256), 0,
-                       s, ta, tb, G, flags, P.rowid, rows, A.rowbox, B.rowbox, L);
+                       s, ta, tb, G, flags, P.rowid, rows, A.rowbox, B.rowbox, A.boxrep, L);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -255,7 +278,6 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 // bits on its two long axes); value = triangle index within its side.  Both
 // sides in one launch (A's triangles, then B's), keys written at the width
 // the sort uses.
-constexpr int RS_ITEMS = 4096;  // radix sort items per block
 
 struct MortonSide {
     const double *xyz;
@@ -270,7 +292,7 @@ struct MortonSide {
 // hist[digit * nblocks + block], the layout the scan expects).  Each thread
 // takes 4 items and issues all their index loads, then all their vertex
 // loads, before any store.
-template <typename KT>
+template <typename KT, int RS_ITEMS>
 __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, const int32_t *rowid,
                                                  int mbits, uint64_t side_key, KT *keys, int32_t *vals,
                                                  uint32_t *hist, int nblocks) {
@@ -337,7 +359,7 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
 // comes from the key kernel), one exclusive scan over (digit, block), and a
 // stable scatter that ranks equal digits inside a wave with ballots.
 
-template <typename KT>
+template <typename KT, int RS_ITEMS>
 __global__ void k_hist(const KT *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -407,7 +429,7 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
 // digit order and writes each digit's run to consecutive global addresses.
 // With at most 256 scan chunks the block scans the chunk totals itself
 // (ncraw > 0: part holds raw totals), which saves the top-level scan launch.
-template <typename KT>
+template <typename KT, int RS_ITEMS>
 __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *vin, KT *kout,
                                                  int32_t *vout, int64_t n, int shift,
                                                  const uint32_t *hist, const uint32_t *part,
@@ -505,7 +527,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
 
 // Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
 // The first pass's histogram is already in `hist` (from the key kernel).
-template <typename KT>
+template <typename KT, int RS_ITEMS>
 static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
                       int bits, hipStream_t s, KernelEvents *kev) {
     int cur = 0;
@@ -515,13 +537,13 @@ static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part,
     int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
     for (int shift = 0; shift < bits; shift += 8) {
         if (shift > 0)
-            hipLaunchKernelGGL(k_hist<KT>, dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
+            hipLaunchKernelGGL((k_hist<KT, RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
         hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
         const bool inline_top = nchunk <= 256;
         if (!inline_top)
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
-        hipLaunchKernelGGL(k_scatter<KT>, dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+        hipLaunchKernelGGL((k_scatter<KT, RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
                            keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb,
                            inline_top ? nchunk : 0);
         if (kev) kev->end(KE_SCATTER, s);
@@ -659,28 +681,37 @@ SortKey sort_key(int64_t G) {
     return K;
 }
 
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
-                 KernelEvents *kev) {
+// Keys and the sort with RSI items per sort block.
+template <int RSI>
+static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
+                      KernelEvents *kev) {
     const int key_bits = K.rowbits + K.mbits;  // bits below the side bit
-    if (A.G == 0) return;
     const int64_t n = A.nt + B.nt;
     MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox};
     MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox};
-    const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
-    int cur;
+    const int nb = (int)((n + RSI - 1) / RSI);
     if (key_bits + 1 <= 32) {
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
         if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint32_t>, dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid, K.mbits,
-                               1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
-        cur = radix_sort<uint32_t>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
-    } else {
-        if (n > 0)
-            hipLaunchKernelGGL(k_morton<uint64_t>, dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid, K.mbits,
-                               1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
-        cur = radix_sort<uint64_t>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
+            hipLaunchKernelGGL((k_morton<uint32_t, RSI>), dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid,
+                               K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
+        return radix_sort<uint32_t, RSI>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
+    if (n > 0)
+        hipLaunchKernelGGL((k_morton<uint64_t, RSI>), dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid,
+                           K.mbits, 1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
+    return radix_sort<uint64_t, RSI>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
+}
+
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
+                 KernelEvents *kev) {
+    if (A.G == 0) return;
+    // smaller sort blocks shorten each block's serial ranking on small sorts;
+    // larger ones write longer contiguous runs on big sorts
+    const int64_t n = A.nt + B.nt;
+    const int cur = n <= ((int64_t)1 << 22) ? sort_items<RS_ITEMS>(A, B, P, K, s, kev)
+                                            : sort_items<2 * RS_ITEMS>(A, B, P, K, s, kev);
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
@@ -695,8 +726,9 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStr
 // ---------------------------------------------------------------------------
 // row state
 // ---------------------------------------------------------------------------
-__device__ void row_init(RowState *rows, int64_t g, const unsigned long long *boxA,
-                         const unsigned long long *boxB) {
+// Row state from the two row boxes (6 ordered-bit values each).
+__device__ void row_init_vals(RowState *rows, int64_t g, const unsigned long long *bA,
+                              const unsigned long long *bB) {
     RowState r;
     r.ub = double_to_bits(__builtin_inf());
     r.d2 = double_to_bits(__builtin_inf());
@@ -705,11 +737,11 @@ __device__ void row_init(RowState *rows, int64_t g, const unsigned long long *bo
     r.best = ~0ull;
     r.scale = 0.0;
     double ext2 = 0.0;
-    bool ok = boxA[g * 6] != ~0ull && boxB[g * 6] != ~0ull;
+    bool ok = bA[0] != ~0ull && bB[0] != ~0ull;
     if (ok) {
         for (int k = 0; k < 3; k++) {
-            double lo = fmin(from_ordered_bits(boxA[g * 6 + k]), from_ordered_bits(boxB[g * 6 + k]));
-            double hi = fmax(from_ordered_bits(boxA[g * 6 + 3 + k]), from_ordered_bits(boxB[g * 6 + 3 + k]));
+            double lo = fmin(from_ordered_bits(bA[k]), from_ordered_bits(bB[k]));
+            double hi = fmax(from_ordered_bits(bA[3 + k]), from_ordered_bits(bB[3 + k]));
             ext2 += (hi - lo) * (hi - lo);
         }
     }
@@ -1469,14 +1501,17 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
                     RowState *R = rows + S.g;
                     if (PREC == 0) {
                         float dm = fminf(fminf(S.redf[0], S.redf[1]), fminf(S.redf[2], S.redf[3]));
+                        // the row's upper bound now (this tile pair's and every
+                        // earlier result, from the atomic's return value): only
+                        // pairs that may still beat it are rescued; with no pair
+                        // tested there is nothing to rescue
+                        double ub_now = S.ub;
                         if (dm < __builtin_inff()) {
                             double U = sqrt((double)dm) * (1.0 + 4.0 * U32) + (double)S.c.eu;
-                            atomic_min_pos(&R->ub, U * (1.0 + 4.0 * U64));
+                            unsigned long long mine = double_to_bits(U * (1.0 + 4.0 * U64));
+                            unsigned long long prev = atomicMin(&R->ub, mine);
+                            ub_now = bits_to_double(prev < mine ? prev : mine);
                         }
-                        // the row's upper bound now (this tile pair's and every
-                        // earlier result): only pairs that may still beat it
-                        // are rescued
-                        double ub_now = bits_to_double(load_acq(&R->ub));
                         S.ub_now = ub_now + row_margin(*R, ub_now);
                     } else {
                         double dm = fmin(fmin(S.redd[0], S.redd[1]), fmin(S.redd[2], S.redd[3]));
@@ -1669,11 +1704,19 @@ void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &
 // ---------------------------------------------------------------------------
 // exact arithmetic for the pairs the FP64 filter left undecided
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_exact(TriSrc SA, TriSrc SB, RowState *rows, Lists L,
-                                              int mode) {
+__device__ __forceinline__ void finalize_row(const RowState *rows, int64_t g, double *dist,
+                                             uint8_t *hit) {
+    bool h = rows[g].hit != 0;
+    if (dist) dist[g] = h ? 0.0 : sqrt(bits_to_double(rows[g].d2));
+    if (hit) hit[g] = h ? 1 : 0;
+}
+
+// Exact arithmetic for the listed pairs, items first, first + step, ...
+__device__ void exact_items(const TriSrc &SA, const TriSrc &SB, RowState *rows, const Lists &L,
+                            int mode, unsigned first, unsigned step) {
     const TileMeta *mA = SA.meta;
     const unsigned n = min(*L.xcount, L.xcap);
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (unsigned i = first; i < n; i += step) {
         ExactItem e = L.exact[i];
         RowState *R = rows + mA[e.ta].row;
         if (load_acq32(&R->hit)) continue;
@@ -1689,9 +1732,41 @@ __global__ __launch_bounds__(64) void k_exact(TriSrc SA, TriSrc SB, RowState *ro
     }
 }
 
+// True in the last block of the grid to reach this point; every other
+// block's memory updates are then visible to it (fence before the counter).
+__device__ __forceinline__ bool last_block_done(unsigned int *done) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// The results of rows [0, fin_rows), unless the call failed on the device.
+__device__ __forceinline__ void finalize_rows(const RowState *rows, int64_t fin_rows, double *dist,
+                                              uint8_t *hit, const Lists &L, const uint32_t *vflags) {
+    if (call_failed(L, vflags)) return;
+    for (int64_t g = threadIdx.x; g < fin_rows; g += blockDim.x) finalize_row(rows, g, dist, hit);
+}
+
+// With fin_rows > 0 the last block to finish also writes the results.
+__global__ __launch_bounds__(64) void k_exact(TriSrc SA, TriSrc SB, RowState *rows, Lists L,
+                                              int mode, int64_t fin_rows, double *dist,
+                                              uint8_t *hit, const uint32_t *vflags) {
+    exact_items(SA, SB, rows, L, mode, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    if (fin_rows <= 0) return;
+    if (last_block_done(L.xdone)) finalize_rows(rows, fin_rows, dist, hit, L, vflags);
+}
+
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
-                  int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, tri_src(A), tri_src(B), rows, L, mode);
+                  int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
+                  const uint32_t *vflags) {
+    hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, tri_src(A), tri_src(B), rows, L, mode,
+                       fin_rows, dist, hit, vflags);
 }
 
 // ---------------------------------------------------------------------------
@@ -1719,24 +1794,27 @@ __device__ __forceinline__ uint32_t float_order_bits(float f) {
 }
 
 // One wave per queued tile pair (lane = hidden unit).  Without a ranker the
-// score is the box lower bound.  Weights sit in LDS transposed so that lanes
-// read consecutive words.
+// score is the box lower bound.
 __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta *mB, RowState *rows,
                                               Lists L, const float *W) {
-    __shared__ float w1t[MLP_IN * MLP_H], w2t[MLP_H * MLP_H], w3t[MLP_H * MLP_H];
+    // weights row-major with one padding word per row: staging writes and
+    // the lanes' row reads (lane = output unit) both fall on distinct banks
+    constexpr int P1 = MLP_IN + 1, P2 = MLP_H + 1;
+    __shared__ float w1t[MLP_H * P1], w2t[MLP_H * P2], w3t[MLP_H * P2];
     __shared__ float bias[3 * MLP_H + MLP_H + 1];
     __shared__ float hbuf[4][MLP_H];
     const unsigned n = min(*L.qcount, L.qcap);
     const int lane = lane_id(), wv = threadIdx.x >> 6;
+    if ((unsigned)blockIdx.x * 4u >= n) return;  // no entry for this block: skip the weights
     if (W) {
         for (int i = threadIdx.x; i < MLP_H * MLP_IN; i += blockDim.x) {
             int j = i / MLP_IN, k = i % MLP_IN;
-            w1t[k * MLP_H + j] = W[MLP_W1 + i];
+            w1t[j * P1 + k] = W[MLP_W1 + i];
         }
         for (int i = threadIdx.x; i < MLP_H * MLP_H; i += blockDim.x) {
             int j = i / MLP_H, k = i % MLP_H;
-            w2t[k * MLP_H + j] = W[MLP_W2 + i];
-            w3t[k * MLP_H + j] = W[MLP_W3 + i];
+            w2t[j * P2 + k] = W[MLP_W2 + i];
+            w3t[j * P2 + k] = W[MLP_W3 + i];
         }
         for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
             bias[i] = W[MLP_B1 + i];
@@ -1757,17 +1835,17 @@ __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta
             float f[MLP_IN];
             tp_features(a, mB[e.y], R->scale, L.qlb[q], f);
             float h = bias[lane];
-            for (int k = 0; k < MLP_IN; k++) h += w1t[k * MLP_H + lane] * f[k];
+            for (int k = 0; k < MLP_IN; k++) h += w1t[lane * P1 + k] * f[k];
             hbuf[wv][lane] = fmaxf(h, 0.0f);
             __builtin_amdgcn_wave_barrier();
             h = bias[MLP_H + lane];
-            for (int k = 0; k < MLP_H; k++) h += w2t[k * MLP_H + lane] * hbuf[wv][k];
+            for (int k = 0; k < MLP_H; k++) h += w2t[lane * P2 + k] * hbuf[wv][k];
             h = fmaxf(h, 0.0f);
             __builtin_amdgcn_wave_barrier();
             hbuf[wv][lane] = h;
             __builtin_amdgcn_wave_barrier();
             h = bias[2 * MLP_H + lane];
-            for (int k = 0; k < MLP_H; k++) h += w3t[k * MLP_H + lane] * hbuf[wv][k];
+            for (int k = 0; k < MLP_H; k++) h += w3t[lane * P2 + k] * hbuf[wv][k];
             h = fmaxf(h, 0.0f);
             score = wave_sum(h * bias[3 * MLP_H + lane]) + bias[4 * MLP_H];
             __builtin_amdgcn_wave_barrier();
@@ -1837,9 +1915,7 @@ __global__ void k_finalize(const RowState *rows, int64_t G, double *dist, uint8_
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= G) return;
     if (call_failed(L, vflags)) return;
-    bool h = rows[g].hit != 0;
-    if (dist) dist[g] = h ? 0.0 : sqrt(bits_to_double(rows[g].d2));
-    if (hit) hit[g] = h ? 1 : 0;
+    finalize_row(rows, g, dist, hit);
 }
 
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
