@@ -38,15 +38,14 @@ struct SideState {
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, small, grpA, grpB, wi_lb, seedq, seedlb, wlist;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, small, grpA, grpB, wi_lb, wlist;
     void release_all() {
         for (auto &sd : side) {
             DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &rowid, &small, &grpA, &grpB, &wi_lb, &seedq,
-                        &seedlb, &wlist};
+                        &vals0, &vals1, &hist, &part, &rowid, &small, &grpA, &grpB, &wi_lb, &wlist};
         for (DevBuf *b : bs) release(*b);
     }
 };
@@ -311,8 +310,6 @@ struct Call {
     int passes = 0;
     bool seed = false;
     int grid_pairs = 0;
-    int2 *seedq = nullptr;
-    float *seedlb = nullptr;
     double *dd = nullptr;  // device outputs
     uint8_t *hd = nullptr;
 };
@@ -446,6 +443,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     L.log_cap = (unsigned long long)opts.log_cap;
     L.log_count = L.counters + C_LOGGED;
     L.xdone = sc + 11;
+    L.nrows = G;
 
     const int prec = opts.precision == SD3_PREC_FP64 ? 1 : 0;
     int &gp = ctx->pairs_grid[prec][mode][tk_index(tk)];
@@ -459,10 +457,6 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     C.passes = (int)((C.n_wi + C.per_pass - 1) / C.per_pass);
     Q.compact = C.n_wi <= C.per_pass ? 1 : 0;
     C.seed = mode == 0 && opts.order != SD3_ORDER_NONE && C.n_wi > 0;
-    if (C.seed) {
-        C.seedq = (int2 *)ensure(ws.seedq, sizeof(int2) * (G + 1));
-        C.seedlb = (float *)ensure(ws.seedlb, sizeof(float) * (G + 1));
-    }
     if (a->mem == SD3_MEM_DEVICE) {
         C.dd = dist;
         C.hd = hit;
@@ -494,32 +488,29 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     launch_prep(A, B, C.PB, sort_key(G), s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     mark(2);
-    launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s);
+    launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s, 0);
     // (a single queue pass sets the row scales in its work-item compaction)
     if (mode == 0 && !Q.compact) launch_row_scale(C.rows, G, s);
+    // seed round of each pass (distance): the filter (box bound) or the
+    // ranker records each row's best-ranked queued tile pair, and a pass of
+    // the tile-pair kernel over the rows' choices evaluates them first
+    const bool learned = C.seed && C.opts.order == SD3_ORDER_LEARNED;
+    const int rank = C.seed && !learned ? 1 : 0;
+    Lists LS = L;
+    LS.qhead = C.sc + 7;
+    LS.seed_pass = 1;
     for (int64_t w0 = 0; w0 < C.n_wi; w0 += C.per_pass) {
         int64_t nw = std::min(C.per_pass, C.n_wi - w0);
-        if (w0 > 0) launch_reset_queue(L, s);
-        if (kev) kev->begin(KE_FILTER, s);
-        launch_queue(A, B, Q, nw, w0, C.rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s);
-        if (kev) kev->end(KE_FILTER, s);
-        if (C.seed) {
-            // seed round of this pass: each row's best-ranked queued tile pair
-            // is evaluated first (box bound or ranker order)
-            Lists LS = L;
-            LS.queue = C.seedq;
-            LS.qlb = C.seedlb;
-            LS.qcount = C.sc + 6;
-            LS.qhead = C.sc + 7;
-            LS.qcap = (unsigned int)(G > 0 ? G : 1);
-            LS.seed_pass = 1;
-            if (w0 > 0) launch_seed_reset(C.rows, G, LS.qcount, LS.qhead, s);
-            launch_rank(A, B, C.rows, L, C.opts.order == SD3_ORDER_LEARNED ? C.opts.ranker : nullptr,
-                        ctx->cus * 2, s);
-            launch_seed_build(C.rows, G, L, C.seedq, C.seedlb, LS.qcount, s);
-            // the seed list holds at most one entry per row
-            launch_pairs(A, B, C.rows, LS, prec, mode, (int)std::min<int64_t>(C.grid_pairs, G > 0 ? G : 1), s);
+        if (w0 > 0) {
+            launch_reset_queue(L, s);
+            if (C.seed) launch_seed_reset(C.rows, G, LS.qhead, s);
         }
+        if (kev) kev->begin(KE_FILTER, s);
+        launch_queue(A, B, Q, nw, w0, C.rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s, rank);
+        if (kev) kev->end(KE_FILTER, s);
+        if (learned) launch_rank(A, B, C.rows, L, C.opts.ranker, ctx->cus * 2, s);
+        // at most one seed per row
+        if (C.seed) launch_pairs(A, B, C.rows, LS, prec, mode, (int)std::min<int64_t>(C.grid_pairs, G), s);
         if (w0 == 0) mark(3);
         if (kev) kev->begin(KE_PAIRS, s);
         launch_pairs(A, B, C.rows, L, prec, mode, C.grid_pairs, s);

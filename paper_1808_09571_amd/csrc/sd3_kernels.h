@@ -85,7 +85,8 @@ struct Lists {
     unsigned int *xcount;
     unsigned int xcap;
     unsigned long long *counters;  // [C_NCOUNTERS]
-    int seed_pass;                 // 1 while the queue is the per-row seed list
+    int seed_pass;                 // 1: entries are the rows' seed choices (RowState::best)
+    int64_t nrows;                 // rows (entries of a seed pass)
     float *log;                    // training log (device) or nullptr
     unsigned long long log_cap;
     unsigned long long *log_count;
@@ -148,8 +149,14 @@ void launch_group_boxes(const SideBufs &A, const SideBufs &B, const QueueGeo &Q,
 // Q_GROUPS: group bounds only (intersects); Q_FILTER_DIST: keep tile pairs with
 // box lower bound <= ub + m; Q_FILTER_HIT: keep overlapping boxes.
 enum : int { Q_SEED = 0, Q_GROUPS = 1, Q_FILTER_DIST = 2, Q_FILTER_HIT = 3 };
+// rank (filter passes of sd3_distance): 1 chooses each row's seed by box bound
+// in the filter's own launch, 0 does not.
 void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
-                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s);
+                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s, int rank);
+// Learned seed choice: scores every queued tile pair with the ranker MLP
+// (weights `ranker`) and keeps each row's lowest score in the row state.
+void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
+                 const float *ranker, int grid, hipStream_t s);
 int pairs_blocks_per_cu(int precision, int mode, int tk);
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
                   int mode, int grid, hipStream_t s);
@@ -160,16 +167,11 @@ void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                   int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
                   const uint32_t *vflags);
-// Seed round: k_rank scores every queued tile pair (box lower bound, or the
-// ranker MLP when `ranker` is given) and keeps the best per row; the seeds are
-// copied to `seedq` and evaluated before the main pass.
+// Seed round: the filter (box bound) or the ranker records each row's
+// best-ranked queued tile pair in the row state; a pass of the tile-pair
+// kernel in seed mode (Lists::seed_pass) evaluates those before the main pass.
 void launch_row_scale(RowState *rows, int64_t G, hipStream_t s);
-void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
-                 const float *ranker, int grid, hipStream_t s);
-void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount, unsigned int *seedhead,
-                       hipStream_t s);
-void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
-                       unsigned int *seedcount, hipStream_t s);
+void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedhead, hipStream_t s);
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
                      const uint32_t *vflags, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);

@@ -963,10 +963,21 @@ __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileM
 
 // Keep the tile pairs that may hold the minimum (distance: box lower bound
 // <= ub + m) or a contact (intersects: closed boxes overlap).
+__device__ __forceinline__ uint32_t float_order_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+// Tile-pair box filter of one work item (thread = B tile, loop over the A
+// block's tiles) into the queue.  With RANK 1 the same launch also chooses
+// each row's seed: the kept entry with the smallest box bound, combined per
+// wave and published with one atomicMin per wave on the row's choice (ordered
+// bound bits << 32 | queue index).
+template <int RANK>
 __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMeta *mB,
                                                 const int64_t *tA, const int64_t *tB,
                                                 const int64_t *wi_off, int64_t G, int64_t wi0,
-                                                const RowState *rows, int mode, int2 *queue,
+                                                RowState *rows, int mode, int2 *queue,
                                                 float *qlb, unsigned int *qcount,
                                                 unsigned int qcap, const float *wi_lb,
                                                 const int32_t *wlist, const unsigned int *wcount) {
@@ -998,6 +1009,7 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
     // root is taken only for kept pairs
     double lim2 = lim * lim * (1.0 + 32.0 * U64);
     bool hit = R.hit != 0;
+    unsigned long long best = ~0ull;  // this wave's seed candidate
     for (int a = 0; a < w.na; a++) {
         bool keep = false;
         float lbf = 0.0f;
@@ -1017,18 +1029,44 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
         unsigned int basei = 0;
         if (lane_id() == 0) basei = atomicAdd(qcount, (unsigned int)__popcll(m));
         basei = __shfl(basei, 0);
-        if (keep) {
-            unsigned int idx = basei + (unsigned int)__popcll(m & lanes_below());
-            if (idx < qcap) {
-                queue[idx] = make_int2((int)(w.a0 + a), (int)w.b);
-                qlb[idx] = lbf;
-            }
+        const unsigned int idx = basei + (unsigned int)__popcll(m & lanes_below());
+        if (keep && idx < qcap) {
+            queue[idx] = make_int2((int)(w.a0 + a), (int)w.b);
+            qlb[idx] = lbf;
         }
+        if (RANK == 1 && keep && idx < qcap)
+            best = min(best, ((unsigned long long)float_order_bits(lbf) << 32) | idx);
+    }
+    if (RANK == 1) {
+        best = wave_min(best);
+        if (lane_id() == 0 && best != ~0ull && best < rows[w.g].best) atomicMin(&rows[w.g].best, best);
+    }
+}
+
+template <int RANK>
+static void launch_filter(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
+                          int64_t wi_begin, RowState *rows, Lists &L, int mode, hipStream_t s) {
+    const unsigned nb = (unsigned)n_wi;
+    if (Q.compact) {
+        // single pass over all work items: compact the survivors of the group
+        // bound first (the count is read on the device)
+        const int64_t nthreads = mode == 0 && n_wi < A.G ? A.G : n_wi;
+        hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(nthreads, 256)), dim3(256), 0, s, Q.wi_lb,
+                           Q.wi_off, A.G, n_wi, rows, mode, Q.wlist, Q.wcount + 1,
+                           mode == 0 ? rows : (RowState *)nullptr);
+        hipLaunchKernelGGL(k_filter<RANK>, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                           B.tile_off, Q.wi_off, A.G, (int64_t)0, rows, mode, L.queue, L.qlb,
+                           L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1);
+    } else {
+        hipLaunchKernelGGL(k_filter<RANK>, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                           B.tile_off, Q.wi_off, A.G, wi_begin, rows, mode, L.queue, L.qlb,
+                           L.qcount, L.qcap, Q.wi_lb, (const int32_t *)nullptr,
+                           (const unsigned int *)nullptr);
     }
 }
 
 void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64_t n_wi,
-                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s) {
+                  int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s, int rank) {
     if (n_wi <= 0) return;
     const unsigned nb = (unsigned)n_wi;
     if (what == Q_SEED || what == Q_GROUPS) {
@@ -1044,22 +1082,8 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
         return;
     }
     const int mode = what == Q_FILTER_DIST ? 0 : 1;
-    if (Q.compact) {
-        // single pass over all work items: compact the survivors of the group
-        // bound first (the count is read on the device)
-        const int64_t nthreads = mode == 0 && n_wi < A.G ? A.G : n_wi;
-        hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(nthreads, 256)), dim3(256), 0, s, Q.wi_lb,
-                           Q.wi_off, A.G, n_wi, rows, mode, Q.wlist, Q.wcount + 1,
-                           mode == 0 ? rows : (RowState *)nullptr);
-        hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
-                           B.tile_off, Q.wi_off, A.G, (int64_t)0, rows, mode, L.queue, L.qlb,
-                           L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1);
-    } else {
-        hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
-                           B.tile_off, Q.wi_off, A.G, wi_begin, rows, mode, L.queue, L.qlb,
-                           L.qcount, L.qcap, Q.wi_lb, (const int32_t *)nullptr,
-                           (const unsigned int *)nullptr);
-    }
+    if (rank == 1) launch_filter<1>(A, B, Q, n_wi, wi_begin, rows, L, mode, s);
+    else launch_filter<0>(A, B, Q, n_wi, wi_begin, rows, L, mode, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1188,25 +1212,40 @@ struct TPShared {
 // gathers the entries, their bounds and both tiles' metadata into LDS, one
 // lane per load.
 __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned qcount,
-                                          const TileMeta *mA, const TileMeta *mB,
-                                          const RowState *rows, bool first) {
+                                          const TileMeta *mA, const TileMeta *mB, RowState *rows,
+                                          bool first) {
     const int lane = lane_id();
     const unsigned qb = (unsigned)S.qb;
     unsigned q0 = 0;
     if (lane == 0) q0 = (first ? (unsigned)blockIdx.x : gridDim.x + atomicAdd(L.qhead, 1u)) * qb;
     q0 = __shfl(q0, 0);
-    int ex = 0, ey = 0;
+    // an entry with e.x < 0 is a row without a seed choice (seed pass)
+    int ex = -1, ey = -1;
     if ((unsigned)lane < qb && q0 + lane < qcount) {
-        const int2 e = L.queue[q0 + lane];
+        unsigned q = q0 + lane;
+        bool have = true;
+        if (L.seed_pass) {
+            // seed pass: entry g is row g's chosen queue entry
+            const unsigned long long best = rows[q].best;
+            have = best != ~0ull;
+            q = (unsigned)(best & 0xffffffffu);
+            rows[q0 + lane].seed_q = have ? (int)q : -1;
+        }
+        int2 e = make_int2(-1, -1);
+        float lb = 0.0f;
+        if (have) {
+            e = L.queue[q];
+            lb = L.qlb[q];
+        }
         ex = e.x;
         ey = e.y;
         S.be[lane] = e;
-        S.blb[lane] = L.qlb[q0 + lane];
+        S.blb[lane] = lb;
     }
     const int k = lane >> 1;
     const int tx = __shfl(ex, k), ty = __shfl(ey, k);
     int row = 0;
-    if (lane < 2 * QB && (unsigned)k < qb && q0 + k < qcount) {
+    if (lane < 2 * QB && (unsigned)k < qb && q0 + k < qcount && tx >= 0) {
         if (lane & 1) {
             S.bmB[k] = mB[ty];
         } else {
@@ -1217,7 +1256,7 @@ __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned 
     // the rows' state, one lane per entry (a stale upper bound is still an
     // upper bound: it only prunes less)
     const int rk = __shfl(row, 2 * (lane & (QB - 1)));
-    if (lane < QB && (unsigned)lane < qb && q0 + lane < qcount) S.brow[lane] = rows[rk];
+    if (lane < QB && (unsigned)lane < qb && q0 + lane < qcount && ex >= 0) S.brow[lane] = rows[rk];
     if (lane == 0) {
         S.bq0 = q0;
         S.bn = q0 < qcount ? (int)min(qb, qcount - q0) : 0;
@@ -1240,6 +1279,7 @@ __device__ __forceinline__ void tp_pop(TPShared &S, const Lists &L, RowState *ro
     const unsigned q = S.bq0 + (unsigned)k;
     S.q = (int)q;
     const int2 e = S.be[k];
+    if (e.x < 0) return;  // a row without a seed choice
     const TileMeta &a = S.bmA[k];
     const TileMeta &b = S.bmB[k];
     const RowState *R = &S.brow[k];
@@ -1352,7 +1392,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     __shared__ uint32_t glist[NGP];
     __shared__ TPShared S;
     const int tid = threadIdx.x, w = tid >> 6;
-    const unsigned qcount = min(*L.qcount, L.qcap);
+    const unsigned qcount = L.seed_pass ? (unsigned)L.nrows : min(*L.qcount, L.qcap);
     unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0;
     // entries per refill: 1 for short queues (every block starts at once), up
     // to QB for long ones (one atomic and one gather per batch)
@@ -1788,72 +1828,100 @@ void launch_row_scale(RowState *rows, int64_t G, hipStream_t s) {
     if (G > 0) hipLaunchKernelGGL(k_row_scale, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G);
 }
 
-__device__ __forceinline__ uint32_t float_order_bits(float f) {
-    uint32_t b = __float_as_uint(f);
-    return (b >> 31) ? ~b : (b | 0x80000000u);
+// Ranker weights in LDS, row-major with one padding word per row: staging
+// writes and the lanes' row reads (lane = output unit) fall on distinct banks.
+constexpr int MLP_P1 = MLP_IN + 1, MLP_P2 = MLP_H + 1;
+struct MlpLds {
+    float w1[MLP_H * MLP_P1], w2[MLP_H * MLP_P2], w3[MLP_H * MLP_P2];
+    float bias[3 * MLP_H + MLP_H + 1];  // b1 b2 b3 w4 b4
+    float h[4][MLP_H];                  // one activation row per wave
+};
+static_assert(MLP_H == 64, "one hidden unit per lane");
+static_assert((MLP_H * MLP_H) % 256 == 0, "whole hidden matrices per 256-thread block");
+
+// Weights into LDS by a 256-thread block: every global load is issued before
+// the first LDS write, so the block waits for one round trip, not one per row.
+__device__ void mlp_stage(MlpLds &M, const float *W) {
+    constexpr int N1 = (MLP_H * MLP_IN + 255) / 256, N2 = MLP_H * MLP_H / 256;
+    const int t = threadIdx.x;
+    float v1[N1], v2[N2], v3[N2], vb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < N1; r++) {
+        const int i = t + 256 * r;
+        v1[r] = i < MLP_H * MLP_IN ? W[MLP_W1 + i] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < N2; r++) {
+        v2[r] = W[MLP_W2 + t + 256 * r];
+        v3[r] = W[MLP_W3 + t + 256 * r];
+    }
+    if (t < MLP_H) {
+        vb[0] = W[MLP_B1 + t];
+        vb[1] = W[MLP_B2 + t];
+        vb[2] = W[MLP_B3 + t];
+        vb[3] = W[MLP_W4 + t];
+    }
+    const float b4 = W[MLP_B4];
+#pragma unroll
+    for (int r = 0; r < N1; r++) {
+        const int i = t + 256 * r;
+        if (i < MLP_H * MLP_IN) M.w1[(i / MLP_IN) * MLP_P1 + i % MLP_IN] = v1[r];
+    }
+#pragma unroll
+    for (int r = 0; r < N2; r++) {
+        const int i = t + 256 * r;
+        M.w2[(i / MLP_H) * MLP_P2 + i % MLP_H] = v2[r];
+        M.w3[(i / MLP_H) * MLP_P2 + i % MLP_H] = v3[r];
+    }
+    if (t < MLP_H)
+        for (int k = 0; k < 4; k++) M.bias[k * MLP_H + t] = vb[k];
+    if (t == 0) M.bias[4 * MLP_H] = b4;
 }
 
-// One wave per queued tile pair (lane = hidden unit).  Without a ranker the
-// score is the box lower bound.
+// The network's output for features f (the same in every lane); the whole
+// wave takes part, lane = hidden unit.
+__device__ float mlp_wave_score(MlpLds &M, const float *f) {
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    float h = M.bias[lane];
+    for (int k = 0; k < MLP_IN; k++) h += M.w1[lane * MLP_P1 + k] * f[k];
+    M.h[wv][lane] = fmaxf(h, 0.0f);
+    __builtin_amdgcn_wave_barrier();
+    h = M.bias[MLP_H + lane];
+#pragma unroll 16
+    for (int k = 0; k < MLP_H; k++) h += M.w2[lane * MLP_P2 + k] * M.h[wv][k];
+    h = fmaxf(h, 0.0f);
+    __builtin_amdgcn_wave_barrier();
+    M.h[wv][lane] = h;
+    __builtin_amdgcn_wave_barrier();
+    h = M.bias[2 * MLP_H + lane];
+#pragma unroll 16
+    for (int k = 0; k < MLP_H; k++) h += M.w3[lane * MLP_P2 + k] * M.h[wv][k];
+    h = fmaxf(h, 0.0f);
+    float score = wave_sum(h * M.bias[3 * MLP_H + lane]) + M.bias[4 * MLP_H];
+    __builtin_amdgcn_wave_barrier();
+    return score;
+}
+
+// Learned seed choice: one wave per queued tile pair scores it with the
+// ranker; lane 0 keeps the row's lowest (ordered score bits << 32 | queue
+// index) with atomicMin.
 __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta *mB, RowState *rows,
                                               Lists L, const float *W) {
-    // weights row-major with one padding word per row: staging writes and
-    // the lanes' row reads (lane = output unit) both fall on distinct banks
-    constexpr int P1 = MLP_IN + 1, P2 = MLP_H + 1;
-    __shared__ float w1t[MLP_H * P1], w2t[MLP_H * P2], w3t[MLP_H * P2];
-    __shared__ float bias[3 * MLP_H + MLP_H + 1];
-    __shared__ float hbuf[4][MLP_H];
+    __shared__ MlpLds M;
     const unsigned n = min(*L.qcount, L.qcap);
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
     if ((unsigned)blockIdx.x * 4u >= n) return;  // no entry for this block: skip the weights
-    if (W) {
-        for (int i = threadIdx.x; i < MLP_H * MLP_IN; i += blockDim.x) {
-            int j = i / MLP_IN, k = i % MLP_IN;
-            w1t[j * P1 + k] = W[MLP_W1 + i];
-        }
-        for (int i = threadIdx.x; i < MLP_H * MLP_H; i += blockDim.x) {
-            int j = i / MLP_H, k = i % MLP_H;
-            w2t[j * P2 + k] = W[MLP_W2 + i];
-            w3t[j * P2 + k] = W[MLP_W3 + i];
-        }
-        for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
-            bias[i] = W[MLP_B1 + i];
-            bias[MLP_H + i] = W[MLP_B2 + i];
-            bias[2 * MLP_H + i] = W[MLP_B3 + i];
-            bias[3 * MLP_H + i] = W[MLP_W4 + i];
-        }
-        if (threadIdx.x == 0) bias[4 * MLP_H] = W[MLP_B4];
-        __syncthreads();
-    }
+    mlp_stage(M, W);
+    __syncthreads();
     const unsigned nw = gridDim.x * 4;
-    for (unsigned q = blockIdx.x * 4 + wv; q < n; q += nw) {
-        int2 e = L.queue[q];
+    for (unsigned q = blockIdx.x * 4 + (threadIdx.x >> 6); q < n; q += nw) {
+        const int2 e = L.queue[q];
         const TileMeta &a = mA[e.x];
         RowState *R = rows + a.row;
-        float score;
-        if (W) {
-            float f[MLP_IN];
-            tp_features(a, mB[e.y], R->scale, L.qlb[q], f);
-            float h = bias[lane];
-            for (int k = 0; k < MLP_IN; k++) h += w1t[lane * P1 + k] * f[k];
-            hbuf[wv][lane] = fmaxf(h, 0.0f);
-            __builtin_amdgcn_wave_barrier();
-            h = bias[MLP_H + lane];
-            for (int k = 0; k < MLP_H; k++) h += w2t[lane * P2 + k] * hbuf[wv][k];
-            h = fmaxf(h, 0.0f);
-            __builtin_amdgcn_wave_barrier();
-            hbuf[wv][lane] = h;
-            __builtin_amdgcn_wave_barrier();
-            h = bias[2 * MLP_H + lane];
-            for (int k = 0; k < MLP_H; k++) h += w3t[lane * P2 + k] * hbuf[wv][k];
-            h = fmaxf(h, 0.0f);
-            score = wave_sum(h * bias[3 * MLP_H + lane]) + bias[4 * MLP_H];
-            __builtin_amdgcn_wave_barrier();
-        } else {
-            score = L.qlb[q];
-        }
-        if (lane == 0) {
-            unsigned long long key = ((unsigned long long)float_order_bits(score) << 32) | q;
+        float f[MLP_IN];
+        tp_features(a, mB[e.y], R->scale, L.qlb[q], f);
+        const float score = mlp_wave_score(M, f);
+        if (lane_id() == 0) {
+            const unsigned long long key = ((unsigned long long)float_order_bits(score) << 32) | q;
             if (key < R->best) atomicMin(&R->best, key);
         }
     }
@@ -1864,44 +1932,19 @@ void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
     hipLaunchKernelGGL(k_rank, dim3(grid), dim3(256), 0, s, A.meta, B.meta, rows, L, ranker);
 }
 
-__global__ void k_seed_build(RowState *rows, int64_t G, Lists L, int2 *seedq, float *seedlb,
-                             unsigned int *seedcount) {
+// Before each later queue pass's filter: no row has a seed choice yet, and
+// the seed pass's head is reset.
+__global__ void k_seed_reset(RowState *rows, int64_t G, unsigned int *seedhead) {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    unsigned long long b = rows[g].best;
-    if (b == ~0ull) return;
-    unsigned q = (unsigned)(b & 0xffffffffu);
-    rows[g].seed_q = (int)q;
-    unsigned i = atomicAdd(seedcount, 1u);
-    seedq[i] = L.queue[q];
-    seedlb[i] = L.qlb[q];
-}
-
-// Before each queue pass's seed round: no row has a choice yet, and the seed
-// list is empty.
-__global__ void k_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount,
-                             unsigned int *seedhead) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g == 0) {
-        *seedcount = 0;
-        *seedhead = 0;
-    }
+    if (g == 0) *seedhead = 0;
     if (g >= G) return;
     rows[g].best = ~0ull;
     rows[g].seed_q = -1;
 }
 
-void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedcount, unsigned int *seedhead,
-                       hipStream_t s) {
+void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedhead, hipStream_t s) {
     hipLaunchKernelGGL(k_seed_reset, dim3(grid_for(G > 0 ? G : 1, 256)), dim3(256), 0, s, rows, G,
-                       seedcount, seedhead);
-}
-
-void launch_seed_build(RowState *rows, int64_t G, Lists &L, int2 *seedq, float *seedlb,
-                       unsigned int *seedcount, hipStream_t s) {
-    if (G > 0)
-        hipLaunchKernelGGL(k_seed_build, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G, L, seedq,
-                           seedlb, seedcount);
+                       seedhead);
 }
 
 // ---------------------------------------------------------------------------
