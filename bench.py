@@ -119,7 +119,8 @@ def roofline_for(kernel, st_list, ms, n, workload):
                 "algorithmic_bytes_per_launch": per,
                 "per_unit": f"{2 * (kb + 4)} B per key ({kb} B key + 4 B value, read + write)"}
     if kernel == "tiles":
-        tris = st_list[0]["sort_items"] / 2.0
+        # one launch builds the tiles of both sides: every sorted item
+        tris = float(st_list[0]["sort_items"])
         per = tris * BYTES_TILE_TRI
         ach = per / (avg * 1e-3) / 1e9
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,

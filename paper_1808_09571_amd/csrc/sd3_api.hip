@@ -81,6 +81,7 @@ constexpr unsigned int QUEUE_BUDGET = 1u << 27;   // tile pairs per queue pass
 constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
 constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
 constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic
+constexpr int64_t RESOLVE_MAX_ROWS = 64;           // FP64 rescue inside the exact launch
 // device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
 // head [4] exact count [6] seed count [7] seed head [8] [9] work-item counts
 // [12] [13] validation flags of a and b; the counters follow at byte 64
@@ -340,9 +341,11 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     S.t_off = d_offs + (G + 1);
     S.tile_off = d_offs + 2 * (G + 1);
     // replicas of the row boxes spread the reduction atomics of many blocks
-    // over one row (at most 2^20 boxes in all)
-    S.boxrep = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 20) / (G > 0 ? G : 1)));
-    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * S.boxrep *
+    // over one row; both sides use the count for the larger one (set by the
+    // caller), room for the most any side can ask for is kept here
+    S.boxrep = rowbox_replicas(nv, G);
+    const int64_t rep_room = std::max<int64_t>(rowbox_replicas((int64_t)1 << 40, G), 1);
+    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * rep_room *
                                                            (G > 0 ? G : 1));
     S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * tk * S.NT);
     // FP64 tile copies only for the plain FP64 pass; the FP32 path keeps the
@@ -397,6 +400,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     const bool fp64 = opts.precision == SD3_PREC_FP64;
     setup_side(ws, 0, a, P.tileA[G], tk, fp64, ds, C.A, s);
     setup_side(ws, 1, b, P.tileB[G], tk, fp64, ds + 3 * G1, C.B, s);
+    C.A.boxrep = C.B.boxrep = std::max(C.A.boxrep, C.B.boxrep);
     {
         int64_t n = C.A.nt + C.B.nt;
         int64_t nb = (n + RS_ITEMS - 1) / RS_ITEMS + 1;
@@ -470,7 +474,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
 // Device validation (flags in the scalar block) fused with the row boxes: the
 // first kernels of every call (host inputs were also checked on the host).
 void enqueue_validate(Call &C, hipStream_t s) {
-    launch_validate_rowbox(C.A, C.B, C.PB, C.flags, C.rows, C.L, s);
+    launch_validate_rowbox(C.A, C.B, C.PB, C.flags, C.L, s);
 }
 
 // Every kernel of the call after validation, in stream order, with no host
@@ -485,7 +489,7 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int64_t G = C.P.G;
     const int mode = C.mode;
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
-    launch_prep(A, B, C.PB, sort_key(G), s, kev);
+    launch_prep(A, B, C.PB, sort_key(G), C.rows, s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s, 0);
@@ -518,10 +522,17 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     }
     if (C.n_wi == 0) mark(3);
     mark(4);
+    // up to 65536 rows the exact kernel's last block also writes the results;
+    // with few rows (a short rescue list) the FP64 rescue shares that launch
+    const int64_t fin_rows = G <= 65536 ? G : 0;
+    if (prec == 0 && G <= RESOLVE_MAX_ROWS) {
+        launch_resolve(A, B, C.rows, L, mode, 64, s, fin_rows, C.dd, C.hd, C.flags);
+        mark(5);
+        mark(6);
+        return;
+    }
     if (prec == 0) launch_rescue(A, B, C.rows, L, mode, ctx->cus * 4, s);
     mark(5);
-    // up to 65536 rows the exact kernel's last block also writes the results
-    const int64_t fin_rows = G <= 65536 ? G : 0;
     launch_exact(A, B, C.rows, L, mode, 64, s, fin_rows, C.dd, C.hd, C.flags);
     mark(6);
     if (fin_rows == 0) launch_finalize(C.rows, G, C.dd, C.hd, L, C.flags, s);

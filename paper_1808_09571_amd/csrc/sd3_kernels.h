@@ -105,12 +105,15 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
 
 
 // Validation of both sides (flags[0] for A, flags[1] for B) fused with the
-// row bounding boxes (one read of xyz): clears the flags and boxes, checks
-// every coordinate and every triangle index, reduces the row boxes, records
-// each sort item's row, starts the row states from the boxes and clears the
-// work-list scalars and counters.
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, RowState *rows,
-                            Lists &L, hipStream_t s);
+// row bounding boxes (one read of xyz): clears the flags, boxes, work-list
+// scalars and counters, checks every coordinate and every triangle index,
+// reduces the row boxes (into A.boxrep replicas) and records each sort item's
+// row.
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, Lists &L,
+                            hipStream_t s);
+// Replicas of the row boxes for rows of nv vertices on the larger side: at
+// most 16, one unless a row spans at least 32 reduction blocks.
+int rowbox_replicas(int64_t nv, int64_t G);
 // Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
 // `passes` 8-bit radix passes (total bits = 8 * passes at most).
 struct SortKey {
@@ -118,9 +121,10 @@ struct SortKey {
     int bits() const { return 1 + rowbits + mbits; }
 };
 SortKey sort_key(int64_t G);
-// Morton keys of both sides, the radix sort and the tiles.
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
-                 KernelEvents *kev);
+// Morton keys of both sides (the same launch starts the row states from the
+// merged row boxes), the radix sort and the tiles.
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
+                 hipStream_t s, KernelEvents *kev);
 
 // Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
 struct GroupBox {
@@ -167,6 +171,11 @@ void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &
 void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
                   int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
                   const uint32_t *vflags);
+// Rescue, exact arithmetic and (fin_rows > 0) the results in one launch, for
+// calls whose rescue list is short (few rows).
+void launch_resolve(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                    int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
+                    const uint32_t *vflags);
 // Seed round: the filter (box bound) or the ranker records each row's
 // best-ranked queued tile pair in the row state; a pass of the tile-pair
 // kernel in seed mode (Lists::seed_pass) evaluates those before the main pass.

@@ -8,6 +8,8 @@
 #include "sd3_pair32.h"
 #include "sd3_exact.h"
 
+static_assert(sd3::C_NCOUNTERS <= 256, "the first block clears every counter");
+
 namespace sd3 {
 
 // ---------------------------------------------------------------------------
@@ -71,47 +73,17 @@ struct TriSide {
     unsigned nblk;
 };
 
-// The same launch starts every row's state from both row boxes (computed by
-// the previous kernel) and clears the work-list scalars and counters.
+// Starts row g's state from both (merged) row boxes.
 __device__ void row_init_vals(RowState *rows, int64_t g, const unsigned long long *bA,
                               const unsigned long long *bB);
 
-__global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int64_t G,
-                                                      uint32_t *flags, int32_t *rowid,
-                                                      RowState *rows, unsigned long long *boxA,
-                                                      unsigned long long *boxB, int rep, Lists L) {
+// Triangle blocks of the validation launch (blk counts A's blocks, then B's).
+__device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, unsigned blk,
+                              uint32_t *flags, int32_t *rowid) {
     __shared__ int64_t g0s;
-    {
-        const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-        if (i < 12) L.qcount[i] = 0;  // device scalars 0-11 (queue, rescue, exact, seed, work
-                                      // items, exact blocks done); 12-13 hold the validation flags
-        if (i < C_NCOUNTERS) L.counters[i] = 0;
-        // one wave per row: lanes 0-11 merge the box replicas of one component
-        // each (A's lo, hi, then B's), lane 0 starts the row state
-        const int lane = lane_id();
-        const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
-        for (int64_t g = i >> 6; g < G; g += nwv) {
-            unsigned long long v = 0;
-            if (lane < 12) {
-                unsigned long long *box = lane < 6 ? boxA : boxB;
-                const int k = lane % 6;
-                v = box[g * 6 + k];
-                for (int r = 1; r < rep; r++) {
-                    unsigned long long w = box[(int64_t)r * G * 6 + g * 6 + k];
-                    v = k < 3 ? min(v, w) : max(v, w);
-                }
-                box[g * 6 + k] = v;
-            }
-            unsigned long long m[12];
-#pragma unroll
-            for (int j = 0; j < 12; j++) m[j] = __shfl(v, j);
-            if (lane == 0) row_init_vals(rows, g, m, m + 6);
-        }
-    }
-    if (blockIdx.x >= A.nblk + B.nblk) return;
-    const bool sa = blockIdx.x < A.nblk;
+    const bool sa = blk < A.nblk;
     const TriSide &S = sa ? A : B;
-    const int64_t t0 = (int64_t)(sa ? blockIdx.x : blockIdx.x - A.nblk) * VT_ITEMS;
+    const int64_t t0 = (int64_t)(sa ? blk : blk - A.nblk) * VT_ITEMS;
     const int64_t t1 = min(S.nt, t0 + VT_ITEMS);
     if (threadIdx.x == 0) g0s = find_row(S.t_off, G, t0);
     __syncthreads();
@@ -132,11 +104,15 @@ __global__ __launch_bounds__(256) void k_validate_tri(TriSide A, TriSide B, int6
 // ---------------------------------------------------------------------------
 // a2: row boxes, Morton keys, radix sort, tiles
 // ---------------------------------------------------------------------------
-// Clears the validation flags of both sides and the row boxes of both sides.
-__global__ void k_prep_init(uint32_t *flags, unsigned long long *boxA, unsigned long long *boxB,
-                            int64_t nbox) {
+// The first kernel of a call: clears the device scalars 0-11 (queue, rescue,
+// exact, seed, work items, exact blocks done), the validation flags of both
+// sides, the counters and the row boxes of both sides.
+__global__ void k_prep_init(unsigned int *sc, uint32_t *flags, unsigned long long *counters,
+                            unsigned long long *boxA, unsigned long long *boxB, int64_t nbox) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < 12) sc[i] = 0u;
     if (i < 2) flags[i] = 0u;
+    if (i < C_NCOUNTERS) counters[i] = 0ull;
     if (i < nbox) {
         unsigned long long v = (i % 6) < 3 ? ~0ull : 0ull;
         boxA[i] = v;
@@ -234,10 +210,14 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
     if (f) atomicOr(flag, f);
 }
 
-// Blocks [0, A.nblk) take side A, the rest side B.
-__global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, int64_t G, uint32_t *flags) {
+// Blocks [0, A.nblk) take side A's vertices, then B's vertices, then the
+// triangles of both sides.
+__global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, TriSide TA, TriSide TB,
+                                                int64_t G, uint32_t *flags, int32_t *rowid) {
+    const unsigned nvb = A.nblk + B.nblk;
     if (blockIdx.x < A.nblk) rowbox_side(A, G, blockIdx.x, flags);
-    else rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
+    else if (blockIdx.x < nvb) rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
+    else validate_tris(TA, TB, G, blockIdx.x - nvb, flags, rowid);
 }
 
 static unsigned rowbox_blocks(int64_t nv) {
@@ -246,21 +226,26 @@ static unsigned rowbox_blocks(int64_t nv) {
     return g > 8192 ? 8192 : g;
 }
 
-void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, RowState *rows,
-                            Lists &L, hipStream_t s) {
+int rowbox_replicas(int64_t nv, int64_t G) {
+    if (G <= 0) return 1;
+    const int64_t per_row = rowbox_blocks(nv) / G;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(16, per_row / 16));
+}
+
+void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, Lists &L,
+                            hipStream_t s) {
     const int64_t G = A.G;
     const int64_t nbox = (int64_t)A.boxrep * G * 6;
-    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(nbox > 2 ? nbox : 2, 256)), dim3(256), 0, s,
-                       flags, A.rowbox, B.rowbox, nbox);
+    // (one block at least: C_NCOUNTERS <= 256)
+    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(nbox > 256 ? nbox : 256, 256)), dim3(256), 0, s,
+                       L.qcount, flags, L.counters, A.rowbox, B.rowbox, nbox);
     XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv), A.boxrep};
     XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv), B.boxrep};
-    if (xa.nblk + xb.nblk > 0)
-        hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
     TriSide ta{A.tri, A.nt, A.v_off, A.t_off, grid_for(A.nt, VT_ITEMS)};
     TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
-    // at least one block: it also starts the row states and clears the counters
-    hipLaunchKernelGGL(k_validate_tri, dim3(ta.nblk + tb.nblk > 0 ? ta.nblk + tb.nblk : 1), dim3(256), 0,
-                       s, ta, tb, G, flags, P.rowid, rows, A.rowbox, B.rowbox, A.boxrep, L);
+    const unsigned nblk = xa.nblk + xb.nblk + ta.nblk + tb.nblk;
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_rowbox, dim3(nblk), dim3(256), 0, s, xa, xb, ta, tb, G, flags, P.rowid);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -292,15 +277,58 @@ struct MortonSide {
 // hist[digit * nblocks + block], the layout the scan expects).  Each thread
 // takes 4 items and issues all their index loads, then all their vertex
 // loads, before any store.
+// Row g's box component k (ordered bits) merged over the rep replicas.
+__device__ __forceinline__ unsigned long long merged_box(const unsigned long long *box, int rep,
+                                                         int64_t G, int64_t g, int k) {
+    unsigned long long v = box[g * 6 + k];
+    for (int r = 1; r < rep; r++) {
+        const unsigned long long w = box[(int64_t)r * G * 6 + g * 6 + k];
+        v = k < 3 ? min(v, w) : max(v, w);
+    }
+    return v;
+}
+
+// The same launch starts every row's state from the merged row boxes (one
+// wave per row).  With replicas, each block first merges the boxes of the
+// first two rows of its A part and of its B part into LDS (a row spread over
+// replicas spans many sort blocks, so a block rarely meets more); other rows
+// are merged per item.
 template <typename KT, int RS_ITEMS>
 __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, const int32_t *rowid,
                                                  int mbits, uint64_t side_key, KT *keys, int32_t *vals,
-                                                 uint32_t *hist, int nblocks) {
+                                                 uint32_t *hist, int nblocks, int rep, int64_t G,
+                                                 RowState *rows) {
     constexpr int PER = RS_ITEMS / 1024;
     __shared__ uint32_t h[256];
-    if (threadIdx.x < 256) h[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ unsigned long long cb[2][2][6];  // [side][row - cr[side]][component]
+    __shared__ int64_t cr[2];                   // first row of the block's part of each side
     const int64_t n = A.nt + B.nt;
+    {
+        const int lane = lane_id();
+        const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+        for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; g < G; g += nwv) {
+            unsigned long long v = 0;
+            if (lane < 12) v = merged_box(lane < 6 ? A.box : B.box, rep, G, g, lane % 6);
+            unsigned long long m[12];
+#pragma unroll
+            for (int j = 0; j < 12; j++) m[j] = __shfl(v, j);
+            if (lane == 0) row_init_vals(rows, g, m, m + 6);
+        }
+    }
+    const int64_t i0 = (int64_t)blockIdx.x * RS_ITEMS, i1 = min(n, i0 + RS_ITEMS);
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    if (rep > 1 && threadIdx.x < 2) {
+        const int64_t lo = threadIdx.x == 0 ? i0 : max(i0, A.nt);
+        const int64_t hi = threadIdx.x == 0 ? min(i1, A.nt) : i1;
+        cr[threadIdx.x] = lo < hi ? rowid[lo] : -1;
+    }
+    __syncthreads();
+    if (rep > 1 && threadIdx.x < 24) {
+        const int sd = threadIdx.x / 12, j = (threadIdx.x / 6) & 1, k = threadIdx.x % 6;
+        const int64_t g = cr[sd] + j;
+        if (cr[sd] >= 0 && g < G) cb[sd][j][k] = merged_box(sd == 0 ? A.box : B.box, rep, G, g, k);
+    }
+    __syncthreads();
     int64_t vi[PER], g[PER];
     bool ok[PER], sa[PER];
 #pragma unroll
@@ -332,10 +360,15 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
         const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
         const MortonSide &S = sa[r] ? A : B;
         const int64_t gr = g[r];
+        const int sd = sa[r] ? 0 : 1;
+        const int64_t j = rep > 1 ? gr - cr[sd] : -1;
+        const bool cached = j == 0 || j == 1;
         double lo[3], ext = 0.0;
         for (int k = 0; k < 3; k++) {
-            lo[k] = from_ordered_bits(S.box[gr * 6 + k]);
-            ext = fmax(ext, from_ordered_bits(S.box[gr * 6 + 3 + k]) - lo[k]);
+            lo[k] = from_ordered_bits(cached ? cb[sd][j][k] : merged_box(S.box, rep, G, gr, k));
+            const double hk =
+                from_ordered_bits(cached ? cb[sd][j][3 + k] : merged_box(S.box, rep, G, gr, 3 + k));
+            ext = fmax(ext, hk - lo[k]);
         }
         const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
         uint32_t q[3];
@@ -351,7 +384,8 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
         atomicAdd(&h[(uint32_t)key & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256 && (int)blockIdx.x < nblocks)
+        hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Stable LSD radix sort, 8-bit digits.  Blocks of 256 threads own 4096
@@ -683,35 +717,38 @@ SortKey sort_key(int64_t G) {
 
 // Keys and the sort with RSI items per sort block.
 template <int RSI>
-static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
+static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
+                      hipStream_t s,
                       KernelEvents *kev) {
     const int key_bits = K.rowbits + K.mbits;  // bits below the side bit
     const int64_t n = A.nt + B.nt;
     MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox};
     MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox};
     const int nb = (int)((n + RSI - 1) / RSI);
+    // at least one block: the key kernel also starts the row states
+    const int grid = nb > 0 ? nb : 1;
     if (key_bits + 1 <= 32) {
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
-        if (n > 0)
-            hipLaunchKernelGGL((k_morton<uint32_t, RSI>), dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid,
-                               K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb);
+        hipLaunchKernelGGL((k_morton<uint32_t, RSI>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
+                           K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb, A.boxrep, A.G,
+                           rows);
         return radix_sort<uint32_t, RSI>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
-    if (n > 0)
-        hipLaunchKernelGGL((k_morton<uint64_t, RSI>), dim3(nb), dim3(1024), 0, s, ma, mb, P.rowid,
-                           K.mbits, 1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb);
+    hipLaunchKernelGGL((k_morton<uint64_t, RSI>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
+                       K.mbits, 1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb, A.boxrep, A.G,
+                       rows);
     return radix_sort<uint64_t, RSI>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
 }
 
-void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, hipStream_t s,
-                 KernelEvents *kev) {
+void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
+                 hipStream_t s, KernelEvents *kev) {
     if (A.G == 0) return;
     // smaller sort blocks shorten each block's serial ranking on small sorts;
     // larger ones write longer contiguous runs on big sorts
     const int64_t n = A.nt + B.nt;
-    const int cur = n <= ((int64_t)1 << 22) ? sort_items<RS_ITEMS>(A, B, P, K, s, kev)
-                                            : sort_items<2 * RS_ITEMS>(A, B, P, K, s, kev);
+    const int cur = n <= ((int64_t)1 << 22) ? sort_items<RS_ITEMS>(A, B, P, K, rows, s, kev)
+                                            : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
@@ -1675,12 +1712,15 @@ __device__ __forceinline__ void load_tri64(const TriSrc &S, int tile, int slot, 
     }
 }
 
+// FP64 re-evaluation of rescue entries first, first + step, ... (every lane
+// of a wave calls this: the counters are summed per wave).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_rescue(TriSrc SA, TriSrc SB, RowState *rows, Lists L) {
+__device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows, const Lists &L,
+                             unsigned first, unsigned step) {
     const TileMeta *mA = SA.meta;
     const unsigned n = min(*L.rcount, L.rcap);
     unsigned long long n64 = 0, nex = 0;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (unsigned i = first; i < n; i += step) {
         Rescue e = L.rescue[i];
         int g = mA[e.ta].row;
         RowState *R = rows + g;
@@ -1731,6 +1771,11 @@ __global__ __launch_bounds__(256) void k_rescue(TriSrc SA, TriSrc SB, RowState *
         if (n64) atomicAdd(&L.counters[C_TRI64], n64);
         if (nex) atomicAdd(&L.counters[C_EXACT], nex);
     }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rescue(TriSrc SA, TriSrc SB, RowState *rows, Lists L) {
+    rescue_items<MODE>(SA, SB, rows, L, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 void launch_rescue(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
@@ -1807,6 +1852,35 @@ void launch_exact(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L
                   const uint32_t *vflags) {
     hipLaunchKernelGGL(k_exact, dim3(grid), dim3(64), 0, s, tri_src(A), tri_src(B), rows, L, mode,
                        fin_rows, dist, hit, vflags);
+}
+
+// Rescue, exact arithmetic and results in one launch: every block re-evaluates
+// its share of the rescue list in FP64; the last block to finish (when no
+// more items can be added) takes every exact item and writes the results.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_resolve(TriSrc SA, TriSrc SB, RowState *rows, Lists L,
+                                                 int64_t fin_rows, double *dist, uint8_t *hit,
+                                                 const uint32_t *vflags) {
+    rescue_items<MODE>(SA, SB, rows, L, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    if (!last_block_done(L.xdone)) return;
+    exact_items(SA, SB, rows, L, MODE, threadIdx.x, blockDim.x);
+    if (fin_rows > 0) {
+        // this block's own exact updates, then fresh row states
+        __syncthreads();
+        __threadfence();
+        finalize_rows(rows, fin_rows, dist, hit, L, vflags);
+    }
+}
+
+void launch_resolve(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int mode,
+                    int grid, hipStream_t s, int64_t fin_rows, double *dist, uint8_t *hit,
+                    const uint32_t *vflags) {
+    if (mode == 0)
+        hipLaunchKernelGGL(k_resolve<0>, dim3(grid), dim3(256), 0, s, tri_src(A), tri_src(B), rows, L,
+                           fin_rows, dist, hit, vflags);
+    else
+        hipLaunchKernelGGL(k_resolve<1>, dim3(grid), dim3(256), 0, s, tri_src(A), tri_src(B), rows, L,
+                           fin_rows, dist, hit, vflags);
 }
 
 // ---------------------------------------------------------------------------
