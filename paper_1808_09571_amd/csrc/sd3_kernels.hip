@@ -303,10 +303,12 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
     __shared__ unsigned long long cb[2][2][6];  // [side][row - cr[side]][component]
     __shared__ int64_t cr[2];                   // first row of the block's part of each side
     const int64_t n = A.nt + B.nt;
+    const int lane = lane_id();
     {
-        const int lane = lane_id();
+        // the grid's last waves (of the ragged last block) start the rows
         const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
-        for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; g < G; g += nwv) {
+        const int64_t wv = nwv - 1 - (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+        for (int64_t g = wv; g < G; g += nwv) {
             unsigned long long v = 0;
             if (lane < 12) v = merged_box(lane < 6 ? A.box : B.box, rep, G, g, lane % 6);
             unsigned long long m[12];
@@ -317,18 +319,14 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
     }
     const int64_t i0 = (int64_t)blockIdx.x * RS_ITEMS, i1 = min(n, i0 + RS_ITEMS);
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    // wave 0, lanes 0 and 1: the rows of the first items of the block's A and
+    // B parts (loaded beside the items' own loads)
+    int64_t crl = -1;
     if (rep > 1 && threadIdx.x < 2) {
         const int64_t lo = threadIdx.x == 0 ? i0 : max(i0, A.nt);
         const int64_t hi = threadIdx.x == 0 ? min(i1, A.nt) : i1;
-        cr[threadIdx.x] = lo < hi ? rowid[lo] : -1;
+        if (lo < hi) crl = rowid[lo];
     }
-    __syncthreads();
-    if (rep > 1 && threadIdx.x < 24) {
-        const int sd = threadIdx.x / 12, j = (threadIdx.x / 6) & 1, k = threadIdx.x % 6;
-        const int64_t g = cr[sd] + j;
-        if (cr[sd] >= 0 && g < G) cb[sd][j][k] = merged_box(sd == 0 ? A.box : B.box, rep, G, g, k);
-    }
-    __syncthreads();
     int64_t vi[PER], g[PER];
     bool ok[PER], sa[PER];
 #pragma unroll
@@ -354,6 +352,15 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
 #pragma unroll
         for (int c = 0; c < 3; c++) cen[r][c] = ok[r] ? X[3 * vi[r] + c] : 0.0;
     }
+    // wave 0 merges the replicas of those rows and the next ones (lanes 0-23:
+    // side, row offset, component) while the coordinates are in flight
+    if (rep > 1 && threadIdx.x < 64) {
+        const int sd = lane / 12, j = (lane / 6) & 1, k = lane % 6;
+        const int64_t c = __shfl(crl, lane < 24 ? sd : 0);
+        if (lane < 24 && c >= 0 && c + j < G) cb[sd][j][k] = merged_box(sd ? B.box : A.box, rep, G, c + j, k);
+        if (lane < 2) cr[lane] = crl;
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         if (!ok[r]) continue;
