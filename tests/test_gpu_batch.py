@@ -134,6 +134,36 @@ def test_graph_replays_match_eager_calls(ctx):
     gi.close()
 
 
+def test_graphs_replayed_concurrently_on_two_streams(ctx):
+    """Each graph has its own workspace: a distance graph and an intersects
+    graph replayed on two streams at once give the eager results, step after
+    step (replays of one graph stay in order on its stream)."""
+    import torch
+    A, B = _work()["tube_blob"]
+    ba, bb = _dev(A, B)
+    d_e, h_e = ctx.distance(ba, bb, precision="fp64")
+    hi_e = ctx.intersects(ba, bb)
+    gd = ctx.graph("distance", ba, bb)
+    gi = ctx.graph("intersects", ba, bb)
+    side = torch.cuda.Stream()
+    for step in range(4):
+        for _ in range(3):
+            gd.launch()
+            with torch.cuda.stream(side):
+                gi.launch()
+        torch.cuda.synchronize()
+        gd.result()
+        gi.result()
+        assert np.array_equal(_bits(gd.dist), _bits(d_e)), step
+        assert np.array_equal(gd.hit.cpu(), h_e.cpu()) and np.array_equal(gi.hit.cpu(), hi_e.cpu())
+        # eager work of the program between the steps
+        d2, _ = ctx.distance(ba, bb)
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(d2), _bits(d_e))
+    gd.close()
+    gi.close()
+
+
 def test_graph_replay_reports_invalid_contents(ctx):
     """A replay over contents that no longer validate leaves the outputs
     untouched and reports the error; after repair it runs again.  (Indices
