@@ -302,19 +302,19 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
     __shared__ uint32_t h[256];
     __shared__ unsigned long long cb[2][2][6];  // [side][row - cr[side]][component]
     __shared__ int64_t cr[2];                   // first row of the block's part of each side
+    __shared__ unsigned long long rb[16][12];   // per wave: the merged boxes of the row it starts
     const int64_t n = A.nt + B.nt;
     const int lane = lane_id();
     {
         // the grid's last waves (of the ragged last block) start the rows
         const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
         const int64_t wv = nwv - 1 - (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+        unsigned long long *m = rb[threadIdx.x >> 6];
         for (int64_t g = wv; g < G; g += nwv) {
-            unsigned long long v = 0;
-            if (lane < 12) v = merged_box(lane < 6 ? A.box : B.box, rep, G, g, lane % 6);
-            unsigned long long m[12];
-#pragma unroll
-            for (int j = 0; j < 12; j++) m[j] = __shfl(v, j);
+            if (lane < 12) m[lane] = merged_box(lane < 6 ? A.box : B.box, rep, G, g, lane % 6);
+            __builtin_amdgcn_wave_barrier();
             if (lane == 0) row_init_vals(rows, g, m, m + 6);
+            __builtin_amdgcn_wave_barrier();
         }
     }
     const int64_t i0 = (int64_t)blockIdx.x * RS_ITEMS, i1 = min(n, i0 + RS_ITEMS);
