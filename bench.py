@@ -12,15 +12,20 @@ distributed; these synthetic inputs stand in for it.
 A step is one pass of the whole path over the input already resident in HBM:
 sd3_distance (validation, Morton sort + tiling, tile-pair bounds and queue,
 learned seed round, FP32 triangle-pair pass with error bounds, FP64 rescue,
-exact fallback, final reduction) followed by sd3_intersects (same stages,
-any-hit), each replayed from a HIP graph with the tile size chosen by the
-autotuner.  The plain-FP64 path (box-bound seed order, its own graphs and
-tuned tiles) runs the same step for comparison; the results must match bit
-for bit.
+exact fallback, final reduction) and sd3_intersects (same stages, any-hit),
+each replayed from a HIP graph with the tile size chosen by the autotuner;
+the two queries are independent and run on two streams (the one-stream time
+is reported beside).  The plain-FP64 path (box-bound seed order, its own
+graphs and tuned tiles) runs the same step for comparison; the results must
+match bit for bit.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload tin512|batch4096|scale]
+                    [--workload tin512|batch4096|scale] [--orders]
     python bench.py --copy-calibration     # device copy of known size, for PMC scaling
+
+--orders adds, per seed order (learned, box bound, none) and precision, the
+sd3_distance graph time, the tile pairs it evaluated and whether its bits
+equal the others'.
 
 Prints one JSON line.  value = all-pairs-equivalent triangle-pair tests per
 second (sum over rows of Na * Nb pairs settled per step / step time).
@@ -67,6 +72,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     p.add_argument("--copy-calibration", action="store_true")
+    p.add_argument("--orders", action="store_true",
+                   help="also time sd3_distance per seed order and precision")
     p.add_argument("--workload", default="tin512", choices=["tin512", "batch4096", "scale"],
                    help="tin512 (default): the two-TIN pair; batch4096: the 4096-row tube/blob "
                         "batch; scale: the 4M-triangle TIN vs 1M-triangle blob")
@@ -148,6 +155,34 @@ WORKLOADS = {
     "scale": "2000x1000-cell TIN (4,000,000 triangles) vs 1,003,520-triangle blob 0.001 above "
              "it, distance + intersects",
 }
+
+
+def time_orders(ctx, ba, bb, weights, args):
+    """sd3_distance graph replays per seed order and precision: ms per call,
+    tile pairs evaluated, and whether the bits equal the first variant's."""
+    import numpy as np
+    import torch
+    out, ref = {}, None
+    for prec in ("fp32", "fp64"):
+        for order in ("learned", "bound", "none"):
+            g = ctx.graph("distance", ba, bb, precision=prec, order=order,
+                          ranker=weights if order == "learned" else None)
+            for _ in range(max(args.warmup, 1)):
+                g.launch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.launch()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            st = g.result(stats=True)
+            bits = g.dist.cpu().numpy().view(np.int64).copy()
+            ref = bits if ref is None else ref
+            out[f"{prec}.{order}"] = {"ms_per_call": round(ms, 4),
+                                      "tile_pairs_evaluated": st["tile_pairs_evaluated"],
+                                      "same_bits": bool(np.array_equal(bits, ref))}
+            g.close()
+    return out
 
 
 def make_workload(name):
@@ -346,6 +381,8 @@ def main():
     }
     gd32.close()
     gi32.close()
+    if args.orders:
+        line["orders_distance"] = time_orders(ctx, ba, bb, weights, args)
     if not args.no_cpu_baseline:
         cb, rows = cpu_baseline_rows(A, B)
         ok = all(h == bool(h32[g]) and (h or abs(d - d32[g]) <= 1e-12 * d) for g, d, h in rows)

@@ -82,6 +82,7 @@ constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
 constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
 constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic
 constexpr int64_t RESOLVE_MAX_ROWS = 64;           // FP64 rescue inside the exact launch
+constexpr int64_t COMPACT_MIN_ROWS = 64;           // compacted work lists above this
 // device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
 // head [4] exact count [6] seed count [7] seed head [8] [9] work-item counts
 // [12] [13] validation flags of a and b; the counters follow at byte 64
@@ -459,7 +460,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     C.per_pass = P.potential <= (int64_t)qcap ? std::max<int64_t>(C.n_wi, 1)
                                               : std::max<int64_t>(1, qcap / QUEUE_MIN);
     C.passes = (int)((C.n_wi + C.per_pass - 1) / C.per_pass);
-    Q.compact = C.n_wi <= C.per_pass ? 1 : 0;
+    // compacted work lists spare the later kernels' blocks a row search; with
+    // few rows that search is short and every block checks its own item
+    Q.compact = C.n_wi <= C.per_pass && G > COMPACT_MIN_ROWS ? 1 : 0;
     C.seed = mode == 0 && opts.order != SD3_ORDER_NONE && C.n_wi > 0;
     if (a->mem == SD3_MEM_DEVICE) {
         C.dd = dist;
@@ -493,8 +496,8 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s, 0);
-    // (a single queue pass sets the row scales in its work-item compaction)
-    if (mode == 0 && !Q.compact) launch_row_scale(C.rows, G, s);
+    // (the rows' feature scale is set by the work-item compaction, else by the
+    // first pass's filter)
     // seed round of each pass (distance): the filter (box bound) or the
     // ranker records each row's best-ranked queued tile pair, and a pass of
     // the tile-pair kernel over the rows' choices evaluates them first

@@ -141,7 +141,7 @@ struct QueueGeo {
     float *wi_lb;           // [n_wi]
     int32_t *wlist;         // [n_wi] compacted work items
     unsigned int *wcount;   // [2] device counts (seeding, filtering); zeroed per call
-    int compact;            // filter through the compacted list (single queue pass)
+    int compact;            // compacted work lists (single queue pass over many rows)
 };
 
 // Group boxes of both sides in one launch: A blocks of 64 tiles, B chunks of
@@ -179,7 +179,6 @@ void launch_resolve(const SideBufs &A, const SideBufs &B, RowState *rows, Lists 
 // Seed round: the filter (box bound) or the ranker records each row's
 // best-ranked queued tile pair in the row state; a pass of the tile-pair
 // kernel in seed mode (Lists::seed_pass) evaluates those before the main pass.
-void launch_row_scale(RowState *rows, int64_t G, hipStream_t s);
 void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedhead, hipStream_t s);
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
                      const uint32_t *vflags, hipStream_t s);

@@ -969,15 +969,18 @@ __device__ __forceinline__ bool wi_pruned(const float *wi_lb, int64_t wi, const 
 }
 
 // Upper bound seed: the distance between two real vertices bounds the row
-// distance from above.
+// distance from above.  Over the compacted list (wlist) or every work item.
 __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileMeta *mB,
                                                  const int64_t *tA, const int64_t *tB,
                                                  const int64_t *wi_off, int64_t G,
                                                  RowState *rows, const float *wi_lb,
                                                  const int32_t *wlist, const unsigned int *wcount) {
     __shared__ double rep[64][3];
-    if (blockIdx.x >= *wcount) return;
-    const int64_t wi = wlist[blockIdx.x];
+    int64_t wi = blockIdx.x;  // without a list: one block per work item
+    if (wlist) {
+        if (blockIdx.x >= *wcount) return;
+        wi = wlist[blockIdx.x];
+    }
     WorkItem w = decode_item(wi_off, G, wi, tA, tB);
     if (wi_pruned(wi_lb, wi, rows[w.g], 0)) return;
     if (threadIdx.x < w.na)
@@ -1024,8 +1027,12 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
                                                 RowState *rows, int mode, int2 *queue,
                                                 float *qlb, unsigned int *qcount,
                                                 unsigned int qcap, const float *wi_lb,
-                                                const int32_t *wlist, const unsigned int *wcount) {
+                                                const int32_t *wlist, const unsigned int *wcount,
+                                                RowState *scale_rows) {
     __shared__ double box[64][6];
+    // block 0 of the first uncompacted pass also sets the rows' feature scale
+    if (scale_rows && blockIdx.x == 0)
+        for (int64_t g = threadIdx.x; g < G; g += blockDim.x) row_scale(scale_rows, g);
     int64_t wi;
     if (wlist) {
         if (blockIdx.x >= *wcount) return;
@@ -1100,12 +1107,14 @@ static void launch_filter(const SideBufs &A, const SideBufs &B, const QueueGeo &
                            mode == 0 ? rows : (RowState *)nullptr);
         hipLaunchKernelGGL(k_filter<RANK>, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
                            B.tile_off, Q.wi_off, A.G, (int64_t)0, rows, mode, L.queue, L.qlb,
-                           L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1);
+                           L.qcount, L.qcap, Q.wi_lb, Q.wlist, Q.wcount + 1,
+                           (RowState *)nullptr);
     } else {
         hipLaunchKernelGGL(k_filter<RANK>, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
                            B.tile_off, Q.wi_off, A.G, wi_begin, rows, mode, L.queue, L.qlb,
                            L.qcount, L.qcap, Q.wi_lb, (const int32_t *)nullptr,
-                           (const unsigned int *)nullptr);
+                           (const unsigned int *)nullptr,
+                           mode == 0 && wi_begin == 0 ? rows : (RowState *)nullptr);
     }
 }
 
@@ -1117,11 +1126,15 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
         hipLaunchKernelGGL(k_wi_seed, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.gA, Q.gB, Q.blkA,
                            Q.chkB, A.tile_off, B.tile_off, Q.wi_off, A.G, n_wi, rows, Q.wi_lb,
                            what == Q_SEED ? 1 : 0);
-        if (what == Q_SEED) {
+        if (what == Q_SEED && Q.compact) {
             hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
                                Q.wi_off, A.G, n_wi, rows, 0, Q.wlist, Q.wcount, (RowState *)nullptr);
             hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
                                B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, Q.wlist, Q.wcount);
+        } else if (what == Q_SEED) {
+            hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                               B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, (const int32_t *)nullptr,
+                               (const unsigned int *)nullptr);
         }
         return;
     }
@@ -1900,14 +1913,6 @@ __device__ __forceinline__ void row_scale(RowState *rows, int64_t g) {
     rows[g].scale = (ub > 0.0 && ub < __builtin_inf()) ? ub : (ext > 0.0 ? ext : 1.0);
 }
 
-__global__ void k_row_scale(RowState *rows, int64_t G) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g < G) row_scale(rows, g);
-}
-
-void launch_row_scale(RowState *rows, int64_t G, hipStream_t s) {
-    if (G > 0) hipLaunchKernelGGL(k_row_scale, dim3(grid_for(G, 256)), dim3(256), 0, s, rows, G);
-}
 
 // Ranker weights in LDS, row-major with one padding word per row: staging
 // writes and the lanes' row reads (lane = output unit) fall on distinct banks.
