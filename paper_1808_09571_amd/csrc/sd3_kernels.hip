@@ -1249,6 +1249,8 @@ struct TPShared {
     float blb[QB];
     TileMeta bmA[QB], bmB[QB];
     RowState brow[QB];        // the rows' state when the batch was gathered
+    TP32 bc[QB];              // per entry: FP32 constants (FP32 pass)
+    double bT2[QB];           // per entry: squared triangle-box cull threshold
     unsigned bq0;             // queue index of be[0]
     int bn, bi, qb;           // entries prefetched, next to take, entries per refill
     int q, live, ta, tb, g, na, nb, logged;
@@ -1268,6 +1270,7 @@ struct TPShared {
 // batch is its static share, later ones come from the shared head) and
 // gathers the entries, their bounds and both tiles' metadata into LDS, one
 // lane per load.
+template <int PREC, int MODE>
 __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned qcount,
                                           const TileMeta *mA, const TileMeta *mB, RowState *rows,
                                           bool first) {
@@ -1313,7 +1316,27 @@ __device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned 
     // the rows' state, one lane per entry (a stale upper bound is still an
     // upper bound: it only prunes less)
     const int rk = __shfl(row, 2 * (lane & (QB - 1)));
-    if (lane < QB && (unsigned)lane < qb && q0 + lane < qcount && ex >= 0) S.brow[lane] = rows[rk];
+    const bool own = lane < QB && (unsigned)lane < qb && q0 + lane < qcount && ex >= 0;
+    if (own) S.brow[lane] = rows[rk];
+    // each entry's tile-pair constants and (distance) cull threshold, one lane
+    // per entry (from the row state just gathered: the pop only copies them)
+    __builtin_amdgcn_wave_barrier();
+    if (own && (PREC == 0 || MODE == 0)) {
+        const TileMeta &a = S.bmA[lane], &b = S.bmB[lane];
+        const RowState &R = S.brow[lane];
+        const double ub = bits_to_double(R.ub), m = row_margin(R, ub);
+        if (PREC == 0) {
+            const TP32 c = tp32_consts(a, b);
+            S.bc[lane] = c;
+            if (MODE == 0) {
+                const double T = (ub + m + c.eps_c) / (1.0 - 4.0 * U32);
+                S.bT2[lane] = T * T * (1.0 + 16.0 * U32);
+            }
+        } else {
+            const double T = (ub + m) * (1.0 + 8.0 * U64);
+            S.bT2[lane] = T * T;
+        }
+    }
     if (lane == 0) {
         S.bq0 = q0;
         S.bn = q0 < qcount ? (int)min(qb, qcount - q0) : 0;
@@ -1363,14 +1386,11 @@ __device__ __forceinline__ void tp_pop(TPShared &S, const Lists &L, RowState *ro
         return;
     }
     S.live = 1;
-    if (precision == 0) {
-        S.c = tp32_consts(a, b);
-        double T = (ub + m + S.c.eps_c) / (1.0 - 4.0 * U32);
-        double T2 = T * T * (1.0 + 16.0 * U32);
-        S.T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
-    } else {
-        double T = (ub + m) * (1.0 + 8.0 * U64);
-        S.T2d = T * T;
+    if (precision == 0) S.c = S.bc[k];
+    if (mode == 0) {
+        const double T2 = S.bT2[k];
+        if (precision == 0) S.T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
+        else S.T2d = T2;
     }
 }
 
@@ -1431,8 +1451,10 @@ __device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, un
     }
 }
 
+// FP32 variants whose LDS allows three blocks per CU are held to the
+// registers of three waves per SIMD.
 template <int PREC, int MODE, int TK>
-__global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *t64A,
+__global__ __launch_bounds__(256, PREC == 0 && TK <= 64 ? 3 : 1) void k_pairs(const float *t32A, const double *t64A,
                                                const TileMeta *mA, const float *t32B,
                                                const double *t64B, const TileMeta *mB,
                                                RowState *rows, Lists L) {
@@ -1463,7 +1485,7 @@ __global__ __launch_bounds__(256) void k_pairs(const float *t32A, const double *
     bool first = true;
     for (;;) {
         if (S.bi >= S.bn) {  // block-uniform: written by thread 0 before the last barrier
-            if (w == 0) tp_refill(S, L, qcount, mA, mB, rows, first);
+            if (w == 0) tp_refill<PREC, MODE>(S, L, qcount, mA, mB, rows, first);
             first = false;
             __syncthreads();
         }
