@@ -129,6 +129,34 @@ def test_single_pairs(ctx, dist):
         assert s64["exact"] > 0  # the exact-arithmetic kernel ran
 
 
+@pytest.mark.parametrize("dist", ["intgrid", "nearplane", "degenerate"])
+def test_single_pairs_few_rows(ctx, dist):
+    """At most 64 rows the FP32 rescue and the exact arithmetic share one launch
+    whose last block takes every exact item: parity there too."""
+    A, B = _pair_rows(dist, 48, 91)
+    s32, s64 = _both(ctx, A, B)
+    assert s32["exact"] > 0 and s64["exact"] > 0
+
+
+def test_big_row_then_small_rows(ctx):
+    """One 320,000-triangle TIN row, then three small rows: the row boxes get
+    replicas, and the key kernel's block at the end of each side covers four
+    rows, so rows past its first two are merged from the replicas per item."""
+    tin = synth.heightfield(400, 400, 200.0, 200.0, seed=7, amplitude=10.0)
+    x = np.asarray(tin[0]).reshape(-1, 3)
+    top = x[np.argmax(x[:, 2])]
+    A = [tin] + [synth.icosphere(1, 1.0, center=(5.0 * k, 0.0, 0.0)) for k in range(1, 4)]
+    B = [synth.icosphere(2, 1.0, center=(top[0], top[1], top[2] + 1.5))]
+    B += [synth.icosphere(1, 1.0, center=(5.0 * k + 1.0 + 0.5 * k, 0.3, 0.0)) for k in range(1, 4)]
+    d_o, h_o = _oracle_rows(A, B, mode="pruned")
+    d32, h32, _ = _run(ctx, A, B, True, "fp32")
+    d64, h64, _ = _run(ctx, A, B, True, "fp64")
+    _check(A, B, d32, h32, d_o, h_o)
+    _check(A, B, d64, h64, d_o, h_o)
+    assert np.array_equal(d32.view(np.int64), d64.view(np.int64)) and np.array_equal(h32, h64)
+    assert 0.0 < d_o[0] <= 0.5 + 1e-12 and h_o[1]  # the rows are what they are meant to be
+
+
 def test_ragged_soups(ctx):
     # sizes around the tile size and empty rows
     sizes = [(1, 1), (63, 65), (64, 64), (65, 130), (200, 7), (0, 5), (5, 0), (0, 0), (129, 1)]
