@@ -919,8 +919,10 @@ __global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t 
 }
 
 // The work items whose group bound may still hold the row minimum (distance:
-// lower bound <= ub + m; intersects: overlapping groups), compacted so that
-// the tile-level kernels only launch useful workgroups.
+// lower bound <= ub + m; intersects: overlapping groups), compacted: in the
+// tile-level kernels that follow, the useful workgroups come first and every
+// other one exits after one load instead of a row search (used with many
+// rows, where that search is long).
 __device__ __forceinline__ void row_scale(RowState *rows, int64_t g);
 
 // With scale_rows, the same launch also sets every row's feature length scale.
@@ -2010,28 +2012,49 @@ __device__ float mlp_wave_score(MlpLds &M, const float *f) {
     return score;
 }
 
-// Learned seed choice: one wave per queued tile pair scores it with the
-// ranker; lane 0 keeps the row's lowest (ordered score bits << 32 | queue
-// index) with atomicMin.
+// Learned seed choice: each wave takes batches of `per` consecutive queued
+// tile pairs (as many as keep every wave of the grid busy, at most 64); its
+// lanes gather and compute one pair's features each, then the whole wave
+// scores the batch pair by pair (lane = hidden unit), and each pair's lane
+// keeps its row's lowest (ordered score bits << 32 | queue index) with
+// atomicMin.
 __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta *mB, RowState *rows,
                                               Lists L, const float *W) {
     __shared__ MlpLds M;
+    __shared__ float fb[4][MLP_IN][64];  // per wave: features of its batch, [feature][pair]
     const unsigned n = min(*L.qcount, L.qcap);
-    if ((unsigned)blockIdx.x * 4u >= n) return;  // no entry for this block: skip the weights
+    const unsigned nw = gridDim.x * 4u;
+    const unsigned per = min(64u, max(1u, (n + nw - 1) / nw));
+    if ((unsigned)blockIdx.x * 4u * per >= n) return;  // no pair for this block: skip the weights
     mlp_stage(M, W);
     __syncthreads();
-    const unsigned nw = gridDim.x * 4;
-    for (unsigned q = blockIdx.x * 4 + (threadIdx.x >> 6); q < n; q += nw) {
-        const int2 e = L.queue[q];
-        const TileMeta &a = mA[e.x];
-        RowState *R = rows + a.row;
-        float f[MLP_IN];
-        tp_features(a, mB[e.y], R->scale, L.qlb[q], f);
-        const float score = mlp_wave_score(M, f);
-        if (lane_id() == 0) {
-            const unsigned long long key = ((unsigned long long)float_order_bits(score) << 32) | q;
-            if (key < R->best) atomicMin(&R->best, key);
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (unsigned q0 = (blockIdx.x * 4u + wv) * per; q0 < n; q0 += nw * per) {
+        const unsigned q = q0 + (unsigned)lane;
+        const bool mine = (unsigned)lane < per && q < n;
+        int row = 0;
+        if (mine) {
+            const int2 e = L.queue[q];
+            const TileMeta &a = mA[e.x];
+            row = a.row;
+            float f[MLP_IN];
+            tp_features(a, mB[e.y], rows[row].scale, L.qlb[q], f);
+            for (int k = 0; k < MLP_IN; k++) fb[wv][k][lane] = f[k];
         }
+        __builtin_amdgcn_wave_barrier();
+        const unsigned cnt = min(per, n - q0);
+        float mine_score = 0.0f;
+        for (unsigned j = 0; j < cnt; j++) {
+            float f[MLP_IN];
+            for (int k = 0; k < MLP_IN; k++) f[k] = fb[wv][k][j];
+            const float sc = mlp_wave_score(M, f);
+            if ((unsigned)lane == j) mine_score = sc;
+        }
+        if (mine) {
+            const unsigned long long key = ((unsigned long long)float_order_bits(mine_score) << 32) | q;
+            if (key < rows[row].best) atomicMin(&rows[row].best, key);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
