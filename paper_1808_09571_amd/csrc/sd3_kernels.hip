@@ -1938,13 +1938,17 @@ __device__ __forceinline__ void row_scale(RowState *rows, int64_t g) {
 }
 
 
-// Ranker weights in LDS, row-major with one padding word per row: staging
-// writes and the lanes' row reads (lane = output unit) fall on distinct banks.
-constexpr int MLP_P1 = MLP_IN + 1, MLP_P2 = MLP_H + 1;
-struct MlpLds {
-    float w1[MLP_H * MLP_P1], w2[MLP_H * MLP_P2], w3[MLP_H * MLP_P2];
+// Ranker weights in LDS, row-major.  The first layer's rows get one padding
+// word (staging writes and the lanes' row reads fall on distinct banks); the
+// hidden layers' rows get four, so that a lane (output unit) reads its row 16
+// bytes at a time with each 16-lane group on distinct banks.
+constexpr int MLP_P1 = MLP_IN + 1, MLP_P2 = MLP_H + 4;
+struct alignas(16) MlpLds {
+    alignas(16) float w1[MLP_H * MLP_P1];
+    alignas(16) float w2[MLP_H * MLP_P2];
+    alignas(16) float w3[MLP_H * MLP_P2];
+    alignas(16) float h[4][MLP_H];  // one activation row per wave
     float bias[3 * MLP_H + MLP_H + 1];  // b1 b2 b3 w4 b4
-    float h[4][MLP_H];                  // one activation row per wave
 };
 static_assert(MLP_H == 64, "one hidden unit per lane");
 static_assert((MLP_H * MLP_H) % 256 == 0, "whole hidden matrices per 256-thread block");
@@ -1988,6 +1992,22 @@ __device__ void mlp_stage(MlpLds &M, const float *W) {
     if (t == 0) M.bias[4 * MLP_H] = b4;
 }
 
+// acc + sum_k w[k] x[k] over the 64 hidden units, in order of k, with 16-byte
+// LDS reads (w: this lane's row, x: the wave's activations, a broadcast).
+__device__ __forceinline__ float mlp_row_dot(const float *w, const float *x, float acc) {
+    const float4 *w4 = reinterpret_cast<const float4 *>(w);
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
+#pragma unroll 4
+    for (int k = 0; k < MLP_H / 4; k++) {
+        const float4 a = w4[k], b = x4[k];
+        acc += a.x * b.x;
+        acc += a.y * b.y;
+        acc += a.z * b.z;
+        acc += a.w * b.w;
+    }
+    return acc;
+}
+
 // The network's output for features f (the same in every lane); the whole
 // wave takes part, lane = hidden unit.
 __device__ float mlp_wave_score(MlpLds &M, const float *f) {
@@ -1996,16 +2016,12 @@ __device__ float mlp_wave_score(MlpLds &M, const float *f) {
     for (int k = 0; k < MLP_IN; k++) h += M.w1[lane * MLP_P1 + k] * f[k];
     M.h[wv][lane] = fmaxf(h, 0.0f);
     __builtin_amdgcn_wave_barrier();
-    h = M.bias[MLP_H + lane];
-#pragma unroll 16
-    for (int k = 0; k < MLP_H; k++) h += M.w2[lane * MLP_P2 + k] * M.h[wv][k];
+    h = mlp_row_dot(M.w2 + lane * MLP_P2, M.h[wv], M.bias[MLP_H + lane]);
     h = fmaxf(h, 0.0f);
     __builtin_amdgcn_wave_barrier();
     M.h[wv][lane] = h;
     __builtin_amdgcn_wave_barrier();
-    h = M.bias[2 * MLP_H + lane];
-#pragma unroll 16
-    for (int k = 0; k < MLP_H; k++) h += M.w3[lane * MLP_P2 + k] * M.h[wv][k];
+    h = mlp_row_dot(M.w3 + lane * MLP_P2, M.h[wv], M.bias[2 * MLP_H + lane]);
     h = fmaxf(h, 0.0f);
     float score = wave_sum(h * M.bias[3 * MLP_H + lane]) + M.bias[4 * MLP_H];
     __builtin_amdgcn_wave_barrier();
