@@ -881,20 +881,6 @@ void launch_group_boxes(const SideBufs &A, const SideBufs &B, const QueueGeo &Q,
                            A.tile_off, Q.blkA, nblkA, B.meta, B.tile_off, Q.chkB, A.G, Q.gA, Q.gB);
 }
 
-// Box lower bound of work item wi's (A block, B chunk) pair (row g), rounded
-// down to FP32; the two groups' boxes through a and b.
-__device__ __forceinline__ float wi_group_lb(const GroupBox *gA, const GroupBox *gB,
-                                             const int64_t *blkA, const int64_t *chkB,
-                                             const int64_t *tB, const int64_t *wi_off, int64_t g,
-                                             int64_t wi, const GroupBox **a, const GroupBox **b) {
-    const int64_t local = wi - wi_off[g];
-    const int64_t nbc = (tB[g + 1] - tB[g] + 255) / 256;
-    *a = &gA[blkA[g] + local / nbc];
-    *b = &gB[chkB[g] + local % nbc];
-    const double g2 = box_gap2((*a)->lo, (*a)->hi, (*b)->lo, (*b)->hi);
-    return (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
-}
-
 // Per work item: box lower bound of its (A block, B chunk) pair, kept for the
 // tile-level kernels, and the distance between two real vertices (an upper
 // bound of the row distance).
@@ -911,9 +897,14 @@ __global__ void k_wi_seed(const GroupBox *gA, const GroupBox *gB, const int64_t 
     double u = __builtin_inf();
     if (valid) {
         g = find_row(wi_off, G, wi);
-        const GroupBox *a, *b;
-        wi_lb[wi] = wi_group_lb(gA, gB, blkA, chkB, tB, wi_off, g, wi, &a, &b);
-        double dx = a->rep[0] - b->rep[0], dy = a->rep[1] - b->rep[1], dz = a->rep[2] - b->rep[2];
+        int64_t local = wi - wi_off[g];
+        int64_t nB = tB[g + 1] - tB[g];
+        int64_t nbc = (nB + 255) / 256;
+        const GroupBox &a = gA[blkA[g] + local / nbc];
+        const GroupBox &b = gB[chkB[g] + local % nbc];
+        double g2 = box_gap2(a.lo, a.hi, b.lo, b.hi);
+        wi_lb[wi] = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
+        double dx = a.rep[0] - b.rep[0], dy = a.rep[1] - b.rep[1], dz = a.rep[2] - b.rep[2];
         u = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 8.0 * U64);
     }
     if (!update_ub) return;
@@ -980,20 +971,12 @@ __device__ __forceinline__ bool wi_pruned(const float *wi_lb, int64_t wi, const 
 }
 
 // Upper bound seed: the distance between two real vertices bounds the row
-// distance from above.  Over the compacted list (wlist), or with GB over every
-// work item, each block first writing its work item's group bound (the group
-// pair's vertex pair is its first tiles' and so is covered here).
-struct GroupBounds {
-    const GroupBox *gA, *gB;
-    const int64_t *blkA, *chkB;
-};
-
+// distance from above.  Over the compacted list (wlist) or every work item.
 __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileMeta *mB,
                                                  const int64_t *tA, const int64_t *tB,
                                                  const int64_t *wi_off, int64_t G,
-                                                 RowState *rows, float *wi_lb,
-                                                 const int32_t *wlist, const unsigned int *wcount,
-                                                 GroupBounds GB) {
+                                                 RowState *rows, const float *wi_lb,
+                                                 const int32_t *wlist, const unsigned int *wcount) {
     __shared__ double rep[64][3];
     int64_t wi = blockIdx.x;  // without a list: one block per work item
     if (wlist) {
@@ -1001,14 +984,7 @@ __global__ __launch_bounds__(256) void k_ub_seed(const TileMeta *mA, const TileM
         wi = wlist[blockIdx.x];
     }
     WorkItem w = decode_item(wi_off, G, wi, tA, tB);
-    if (GB.gA) {
-        if (threadIdx.x == 0) {
-            const GroupBox *a, *b;
-            wi_lb[wi] = wi_group_lb(GB.gA, GB.gB, GB.blkA, GB.chkB, tB, wi_off, w.g, wi, &a, &b);
-        }
-    } else if (wi_pruned(wi_lb, wi, rows[w.g], 0)) {
-        return;
-    }
+    if (wi_pruned(wi_lb, wi, rows[w.g], 0)) return;
     if (threadIdx.x < w.na)
         for (int k = 0; k < 3; k++) rep[threadIdx.x][k] = mA[w.a0 + threadIdx.x].rep[k];
     __syncthreads();
@@ -1148,25 +1124,19 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
                   int64_t wi_begin, RowState *rows, Lists &L, int what, hipStream_t s, int rank) {
     if (n_wi <= 0) return;
     const unsigned nb = (unsigned)n_wi;
-    if (what == Q_SEED && !Q.compact) {
-        // without compaction (few rows, or several queue passes): one launch,
-        // a block per work item, writes the group bound and seeds the upper
-        // bound
-        hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
-                           B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, (const int32_t *)nullptr,
-                           (const unsigned int *)nullptr, GroupBounds{Q.gA, Q.gB, Q.blkA, Q.chkB});
-        return;
-    }
     if (what == Q_SEED || what == Q_GROUPS) {
         hipLaunchKernelGGL(k_wi_seed, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.gA, Q.gB, Q.blkA,
                            Q.chkB, A.tile_off, B.tile_off, Q.wi_off, A.G, n_wi, rows, Q.wi_lb,
                            what == Q_SEED ? 1 : 0);
-        if (what == Q_SEED) {
+        if (what == Q_SEED && Q.compact) {
             hipLaunchKernelGGL(k_wi_compact, dim3(grid_for(n_wi, 256)), dim3(256), 0, s, Q.wi_lb,
                                Q.wi_off, A.G, n_wi, rows, 0, Q.wlist, Q.wcount, (RowState *)nullptr);
             hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
-                               B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, Q.wlist, Q.wcount,
-                               GroupBounds{nullptr, nullptr, nullptr, nullptr});
+                               B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, Q.wlist, Q.wcount);
+        } else if (what == Q_SEED) {
+            hipLaunchKernelGGL(k_ub_seed, dim3(nb), dim3(256), 0, s, A.meta, B.meta, A.tile_off,
+                               B.tile_off, Q.wi_off, A.G, rows, Q.wi_lb, (const int32_t *)nullptr,
+                               (const unsigned int *)nullptr);
         }
         return;
     }
