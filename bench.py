@@ -387,6 +387,16 @@ def main():
         cb, rows = cpu_baseline_rows(A, B)
         ok = all(h == bool(h32[g]) and (h or abs(d - d32[g]) <= 1e-12 * d) for g, d, h in rows)
         cb["matches_gpu"] = bool(ok)
+        # largest relative error of the method's distances against the oracle
+        # over the sampled rows (intersecting rows: both must be exactly 0)
+        def rel_err(d, x):
+            if d == 0.0 or d == float("inf"):
+                return 0.0 if x == d else float("inf")
+            return abs(d - x) / d
+
+        errs = [rel_err(d, float(d32[g])) for g, d, h in rows]
+        cb["max_rel_err_vs_oracle"] = max(errs) if errs else None
+        cb["rows_checked"] = len(rows)
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
