@@ -138,9 +138,12 @@ def roofline_for(kernel, st_list, ms, n, workload):
 
 
 def pairs_roofline(st, ms, n):
-    avg = ms / max(n, 1)
+    """st: the call's stats (every queue pass); ms / n: the call's summed
+    main-pass time / launches (one per queue pass)."""
+    n = max(n, 1)
+    avg = ms / n
     flops = (st["tri_pairs_fp32"] * FLOPS_FP32_PAIR + st["tri_pairs_boxed"] * FLOPS_BOX +
-             st["tile_pairs_evaluated"] * 128 * FLOPS_TRI_PREP)
+             st["tile_pairs_evaluated"] * 128 * FLOPS_TRI_PREP) / n
     ach = flops / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
     return {"kernel": "k_pairs<fp32,distance>", "bound": "alu", "achieved": ach,
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
