@@ -84,8 +84,9 @@ constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithme
 constexpr int64_t RESOLVE_MAX_ROWS = 64;           // FP64 rescue inside the exact launch
 constexpr int64_t COMPACT_MIN_ROWS = 64;           // compacted work lists above this
 // device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
-// head [4] exact count [6] seed count [7] seed head [8] [9] work-item counts
-// [12] [13] validation flags of a and b; the counters follow at byte 64
+// head [4] exact count [7] seed pass head [8] [9] work-item counts [11] exact
+// blocks done [12] [13] validation flags of a and b; the counters follow at
+// byte 64
 constexpr size_t SCALAR_BYTES = 64 + sizeof(unsigned long long) * C_NCOUNTERS;
 
 struct HipError {
