@@ -138,7 +138,8 @@ typedef struct sd3_stats {
     /* with opts.timing: device time of each phase (HIP events on the stream):
        [0] validation + upload, [1] sort + tiles, [2] bounds + queue,
        [3] triangle-pair pass, [4] FP64 rescue, [5] exact arithmetic,
-       [6] final reduction and download */
+       [6] final reduction and download (FP32 calls of at most 64 rows run the
+       rescue inside the exact-arithmetic launch: timed in [5]) */
     double ms_phase[7];
     int64_t logged;                /* training-log records produced (may exceed log_cap) */
     /* with opts.timing: device time summed over the launches of selected
@@ -230,7 +231,8 @@ sd3_status sd3_adam_step(sd3_ctx *ctx, float *p, const float *g, float *m, float
  * default stream) and returns at once.  sd3_graph_result waits for `stream`
  * and returns the status of the last replay enqueued on it (stats may be
  * NULL; timing fields are zero).  Launches of one graph must not overlap:
- * they share its work space.
+ * they share its work space.  Different graphs own different work spaces and
+ * may replay concurrently on different streams.
  */
 typedef struct sd3_graph sd3_graph;
 sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
