@@ -77,7 +77,7 @@ struct sd3_ctx {
 
 namespace {
 
-constexpr unsigned int QUEUE_BUDGET = 1u << 27;   // tile pairs per queue pass
+constexpr unsigned int QUEUE_BUDGET = 1u << 29;   // tile pairs per queue pass (12 B each)
 constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
 constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
 constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic

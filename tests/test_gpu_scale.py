@@ -45,8 +45,10 @@ def test_scale_case_tin_vs_blob(ctx):
     gi.result()
     d32, h32, hi32 = g.dist.cpu().numpy(), g.hit.cpu().numpy(), gi.hit.cpu().numpy()
     d64, h64 = ctx.distance(ba, bb, precision="fp64")
-    assert st["queue_passes"] > 1  # the candidate queue is split at this size
     assert np.array_equal(_bits(d32), _bits(d64.cpu().numpy()))
+    # the same call with the candidate queue split into several passes
+    dq, hq, sq = ctx.distance(ba, bb, order="learned", ranker=w, queue_cap=1 << 27, stats=True)
+    assert sq["queue_passes"] > 1 and np.array_equal(_bits(dq.cpu().numpy()), _bits(d32))
     print("scale case: oracle", flush=True)
     d_o, h_o, _ = oracle.mesh(A, B, mode="pruned")
     assert not h_o and not h32[0] and not hi32[0] and not h64.cpu().numpy()[0]
