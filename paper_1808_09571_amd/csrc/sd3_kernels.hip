@@ -28,6 +28,22 @@ __device__ __forceinline__ int64_t find_row(const int64_t *off, int64_t G, int64
     return lo;
 }
 
+// The same row found by a whole wave for a wave-uniform i: each round the 64
+// lanes probe 64 evenly spaced offsets of the remaining range and the count
+// of probes at or below i narrows it 64-fold (two dependent loads for 4096
+// rows instead of twelve).  Every lane of the wave must take part.
+__device__ __forceinline__ int64_t wave_find_row(const int64_t *off, int64_t G, int64_t i) {
+    int64_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) >> 6;
+        const int64_t p = lo + (int64_t)(lane_id() + 1) * step;
+        const int c = __popcll(__ballot(p < hi && off[p] <= i));
+        hi = min(hi, lo + (int64_t)(c + 1) * step);
+        lo += (int64_t)c * step;
+    }
+    return lo;
+}
+
 // Vertex index of corner k of triangle t, local to its row of nvr vertices.
 // An index outside the row reads vertex 0 instead: kernels that run before the
 // validation flags are read (graph replays) never address memory outside the
@@ -85,7 +101,10 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
     const TriSide &S = sa ? A : B;
     const int64_t t0 = (int64_t)(sa ? blk : blk - A.nblk) * VT_ITEMS;
     const int64_t t1 = min(S.nt, t0 + VT_ITEMS);
-    if (threadIdx.x == 0) g0s = find_row(S.t_off, G, t0);
+    if (threadIdx.x < 64) {
+        const int64_t g0 = wave_find_row(S.t_off, G, t0);
+        if (threadIdx.x == 0) g0s = g0;
+    }
     __syncthreads();
     int64_t g = g0s;
     uint32_t f = 0;
@@ -171,9 +190,20 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
     unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
     uint32_t f = 0;
     int64_t cur = -1;
+    // the rows of each chunk's first and last vertex, walked forward from the
+    // previous chunk's (rows are contiguous and usually span many chunks)
+    auto advance = [&](int64_t g, int64_t i) {
+        for (int k = 0; k < 4; k++) {
+            if (S.v_off[g + 1] > i) return g;
+            g++;
+        }
+        return wave_find_row(S.v_off, G, i);
+    };
+    int64_t g1 = b0 < b1 ? wave_find_row(S.v_off, G, b0) : 0;
     for (int64_t base = b0; base < b1; base += 256) {
         int64_t last = min(base + 255, b1 - 1);
-        int64_t g0 = find_row(S.v_off, G, base), g1 = find_row(S.v_off, G, last);
+        const int64_t g0 = advance(g1, base);
+        g1 = advance(g0, last);
         int64_t i = base + threadIdx.x;
         bool valid = i <= last;
         double x[3] = {0.0, 0.0, 0.0};
@@ -197,7 +227,12 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
             if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
             cur = -1;
             if (valid) {
-                int64_t g = find_row(S.v_off, G, i);
+                // the chunk's rows are g0..g1
+                int64_t g = g0;
+                if (g1 - g0 < 16)
+                    while (S.v_off[g + 1] <= i) g++;
+                else
+                    g = find_row(S.v_off, G, i);
                 for (int k = 0; k < 3; k++) {
                     unsigned long long v = ordered_bits(x[k]);
                     atomicMin(&box[g * 6 + k], v);
@@ -611,9 +646,10 @@ struct TileJob {
 // Lane l of the wave owns slots l and l + 64 (the second only for tk = 128);
 // slots past the tile's last triangle repeat it, and slots past tk are not
 // written.
+template <bool TWO>
 __device__ void tile_one(const TileJob &J, int64_t t) {
     const int lane = lane_id(), tk = J.tk;
-    const int64_t g = find_row(J.tile_off, J.G, t);
+    const int64_t g = wave_find_row(J.tile_off, J.G, t);
     const int64_t i = t - J.tile_off[g];
     const int64_t ntr = J.t_off[g + 1] - J.t_off[g];
     const int n = (int)min((int64_t)tk, ntr - i * tk);
@@ -627,7 +663,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
     }
     // all loads of both slots first (one chain of memory latency); the loops
     // are unrolled so that the arrays stay in registers
-    const bool two = tk > 64;
+    const bool two = TWO;
     int64_t tri_id[2] = {0, 0}, vi[2][3];
 #pragma unroll
     for (int r = 0; r < 2; r++)
@@ -702,10 +738,11 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
 
 // Both sides in one launch, one wave per tile: waves [0, NT_A) build A's
 // tiles, the rest B's.
+template <bool TWO>
 __global__ void k_tiles(TileJob A, TileJob B) {
     int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t < A.NT) tile_one(A, t);
-    else if (t - A.NT < B.NT) tile_one(B, t - A.NT);
+    if (t < A.NT) tile_one<TWO>(A, t);
+    else if (t - A.NT < B.NT) tile_one<TWO>(B, t - A.NT);
 }
 
 // Both sides are sorted together (the side is the top key bit), so one
@@ -762,7 +799,12 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
                    A.t64, A.ids, A.meta};
         TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, P.vals[cur] + A.nt,
                    B.t32, B.t64, B.ids, B.meta};
-        hipLaunchKernelGGL(k_tiles, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
+        // one slot per lane below 128-triangle tiles: fewer registers, more
+        // waves in flight for the gathers
+        if (A.tk > 64)
+            hipLaunchKernelGGL(k_tiles<true>, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
+        else
+            hipLaunchKernelGGL(k_tiles<false>, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
     }
     if (kev) kev->end(KE_TILES, s);
 }
