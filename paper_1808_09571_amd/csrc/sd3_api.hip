@@ -38,14 +38,15 @@ struct SideState {
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, small, grpA, grpB, wi_lb, wlist;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, vcode, small, grpA, grpB, wi_lb, wlist;
     void release_all() {
         for (auto &sd : side) {
             DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &rowid, &small, &grpA, &grpB, &wi_lb, &wlist};
+                        &vals0, &vals1, &hist, &part, &rowid, &vcode, &small, &grpA, &grpB, &wi_lb,
+                        &wlist};
         for (DevBuf *b : bs) release(*b);
     }
 };
@@ -413,6 +414,8 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.hist = (uint32_t *)ensure(ws.hist, sizeof(uint32_t) * 256 * nb);
         C.PB.part = (uint32_t *)ensure(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
         C.PB.rowid = (int32_t *)ensure(ws.rowid, sizeof(int32_t) * (n > 0 ? n : 1));
+        C.PB.vcode = n > SMALL_SORT ? (uint32_t *)ensure(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
+                                    : nullptr;
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;

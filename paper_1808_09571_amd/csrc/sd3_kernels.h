@@ -41,9 +41,11 @@ struct KernelEvents {
 };
 
 // Radix-sort items per block (each block's per-digit histogram is one row of
-// the scanned (digit, block) table): RS_ITEMS for sorts of up to 2^22 keys,
-// twice that above; buffers are sized for RS_ITEMS.
+// the scanned (digit, block) table): RS_ITEMS for sorts of up to SMALL_SORT
+// keys, twice that above; buffers are sized for RS_ITEMS.  Larger sorts also
+// take their keys from per-vertex Morton codes.
 constexpr int RS_ITEMS = 2048;
+constexpr int64_t SMALL_SORT = (int64_t)1 << 22;
 
 // Sort buffers shared by both sides (device).
 struct PrepBufs {
@@ -52,6 +54,8 @@ struct PrepBufs {
     uint32_t *hist;     // [256 * blocks], blocks = ceil((ntA + ntB) / RS_ITEMS)
     uint32_t *part;     // [chunks]
     int32_t *rowid;     // [ntA + ntB] row of each sort item (written by validation)
+    uint32_t *vcode;    // [nvA + nvB] Morton code of every vertex, or nullptr (keys
+                        // then quantise each first vertex themselves)
 };
 
 // Counters (device, unsigned long long[16]).

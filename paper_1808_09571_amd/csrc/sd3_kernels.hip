@@ -139,6 +139,26 @@ __global__ void k_prep_init(unsigned int *sc, uint32_t *flags, unsigned long lon
     }
 }
 
+// Rows of the vertex chunks of a block's contiguous range: the row of vertex
+// i walked forward from row g (off[g] <= i; g and i wave-uniform), a few
+// steps (rows usually span many chunks), else a wave search.
+__device__ __forceinline__ int64_t walk_row(const int64_t *off, int64_t G, int64_t g, int64_t i) {
+    for (int k = 0; k < 4; k++) {
+        if (off[g + 1] > i) return g;
+        g++;
+    }
+    return wave_find_row(off, G, i);
+}
+
+// Row of one lane's vertex i of a chunk whose rows are g0..g1.
+__device__ __forceinline__ int64_t lane_row(const int64_t *off, int64_t G, int64_t g0, int64_t g1,
+                                            int64_t i) {
+    if (g1 - g0 >= 16) return find_row(off, G, i);
+    int64_t g = g0;
+    while (off[g + 1] <= i) g++;
+    return g;
+}
+
 // Row bounding boxes of all vertices.  Each block owns a contiguous range of
 // vertices and keeps running per-thread min/max while its chunks stay inside
 // one row; it reduces over the block and issues one atomic per component only
@@ -192,18 +212,11 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
     int64_t cur = -1;
     // the rows of each chunk's first and last vertex, walked forward from the
     // previous chunk's (rows are contiguous and usually span many chunks)
-    auto advance = [&](int64_t g, int64_t i) {
-        for (int k = 0; k < 4; k++) {
-            if (S.v_off[g + 1] > i) return g;
-            g++;
-        }
-        return wave_find_row(S.v_off, G, i);
-    };
     int64_t g1 = b0 < b1 ? wave_find_row(S.v_off, G, b0) : 0;
     for (int64_t base = b0; base < b1; base += 256) {
         int64_t last = min(base + 255, b1 - 1);
-        const int64_t g0 = advance(g1, base);
-        g1 = advance(g0, last);
+        const int64_t g0 = walk_row(S.v_off, G, g1, base);
+        g1 = walk_row(S.v_off, G, g0, last);
         int64_t i = base + threadIdx.x;
         bool valid = i <= last;
         double x[3] = {0.0, 0.0, 0.0};
@@ -227,12 +240,7 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
             if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
             cur = -1;
             if (valid) {
-                // the chunk's rows are g0..g1
-                int64_t g = g0;
-                if (g1 - g0 < 16)
-                    while (S.v_off[g + 1] <= i) g++;
-                else
-                    g = find_row(S.v_off, G, i);
+                const int64_t g = lane_row(S.v_off, G, g0, g1, i);
                 for (int k = 0; k < 3; k++) {
                     unsigned long long v = ordered_bits(x[k]);
                     atomicMin(&box[g * 6 + k], v);
@@ -299,19 +307,6 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 // sides in one launch (A's triangles, then B's), keys written at the width
 // the sort uses.
 
-struct MortonSide {
-    const double *xyz;
-    const int32_t *tri;
-    int64_t nt;
-    const int64_t *v_off, *t_off;
-    const unsigned long long *box;
-};
-
-// One block of 1024 threads per radix-sort block of RS_ITEMS keys, so that
-// the histogram of the sort's first digit is counted here (written as
-// hist[digit * nblocks + block], the layout the scan expects).  Each thread
-// takes 4 items and issues all their index loads, then all their vertex
-// loads, before any store.
 // Row g's box component k (ordered bits) merged over the rep replicas.
 __device__ __forceinline__ unsigned long long merged_box(const unsigned long long *box, int rep,
                                                          int64_t G, int64_t g, int k) {
@@ -323,12 +318,104 @@ __device__ __forceinline__ unsigned long long merged_box(const unsigned long lon
     return v;
 }
 
+// Cells of a row: the origin (box minimum) and the scale mapping the largest
+// extent onto 1024 cells, from the six ordered-bit box components.
+__device__ __forceinline__ double row_cells(const unsigned long long *b, double lo[3]) {
+    double ext = 0.0;
+    for (int k = 0; k < 3; k++) {
+        lo[k] = from_ordered_bits(b[k]);
+        ext = fmax(ext, from_ordered_bits(b[3 + k]) - lo[k]);
+    }
+    return ext > 0.0 ? 1024.0 / ext : 0.0;
+}
+
+// 30-bit Morton code of point p on those cells.
+__device__ __forceinline__ uint32_t morton_code(const double *p, const double *lo, double sc) {
+    uint32_t q[3];
+    for (int k = 0; k < 3; k++) {
+        const double f = (p[k] - lo[k]) * sc;
+        const int qi = (int)f;
+        q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
+    }
+    return spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
+}
+
+struct MortonSide {
+    const double *xyz;
+    const int32_t *tri;
+    int64_t nt;
+    const int64_t *v_off, *t_off;
+    const unsigned long long *box;
+    const uint32_t *vcode;  // per-vertex codes (VC keys)
+};
+
+// Per-vertex Morton codes for large sorts: the key kernel then gathers a
+// 4-byte code per triangle instead of a 24-byte vertex (a sixth of the lines
+// when a row's vertex order is far from its triangle order) and no row box.
+// Blocks own contiguous vertex ranges as in the row-box pass; a wave merges a
+// row's box once while its chunks stay inside that row.
+struct VcodeSide {
+    const double *xyz;
+    int64_t nv;
+    const int64_t *v_off;
+    const unsigned long long *box;
+    uint32_t *code;
+    unsigned nblk;
+};
+
+__device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk) {
+    const int lane = lane_id();
+    const int64_t nv = S.nv;
+    const int64_t per = ((nv + S.nblk - 1) / S.nblk + 255) / 256 * 256;
+    const int64_t b0 = blk * per, b1 = min(nv, b0 + per);
+    int64_t cg = -1;  // row whose cells are held (wave-uniform)
+    double clo[3] = {0.0, 0.0, 0.0}, csc = 0.0;
+    int64_t g1 = b0 < b1 ? wave_find_row(S.v_off, G, b0) : 0;
+    for (int64_t base = b0; base < b1; base += 256) {
+        const int64_t last = min(base + 255, b1 - 1);
+        const int64_t g0 = walk_row(S.v_off, G, g1, base);
+        g1 = walk_row(S.v_off, G, g0, last);
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i <= last;
+        double p[3] = {0.0, 0.0, 0.0};
+        if (valid)
+            for (int k = 0; k < 3; k++) p[k] = S.xyz[3 * i + k];
+        if (g0 == g1) {
+            if (g0 != cg) {
+                const unsigned long long m = lane < 6 ? merged_box(S.box, rep, G, g0, lane) : 0ull;
+                unsigned long long b[6];
+                for (int k = 0; k < 6; k++) b[k] = __shfl(m, k);
+                csc = row_cells(b, clo);
+                cg = g0;
+            }
+            if (valid) S.code[i] = morton_code(p, clo, csc);
+        } else if (valid) {
+            const int64_t g = lane_row(S.v_off, G, g0, g1, i);
+            unsigned long long b[6];
+            for (int k = 0; k < 6; k++) b[k] = merged_box(S.box, rep, G, g, k);
+            double lo[3];
+            const double sc = row_cells(b, lo);
+            S.code[i] = morton_code(p, lo, sc);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_vcode(VcodeSide A, VcodeSide B, int64_t G, int rep) {
+    if (blockIdx.x < A.nblk) vcode_side(A, G, rep, blockIdx.x);
+    else vcode_side(B, G, rep, blockIdx.x - A.nblk);
+}
+
+// One block of 1024 threads per radix-sort block of RS_ITEMS keys, so that
+// the histogram of the sort's first digit is counted here (written as
+// hist[digit * nblocks + block], the layout the scan expects).  Each thread
+// takes RS_ITEMS / 1024 items and issues all their index loads, then all
+// their vertex (VC: code) loads, before any store.
 // The same launch starts every row's state from the merged row boxes (one
-// wave per row).  With replicas, each block first merges the boxes of the
-// first two rows of its A part and of its B part into LDS (a row spread over
-// replicas spans many sort blocks, so a block rarely meets more); other rows
-// are merged per item.
-template <typename KT, int RS_ITEMS>
+// wave per row).  Without per-vertex codes and with replicas, each block
+// first merges the boxes of the first two rows of its A part and of its B
+// part into LDS (a row spread over replicas spans many sort blocks, so a
+// block rarely meets more); other rows are merged per item.
+template <typename KT, int RS_ITEMS, bool VC>
 __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, const int32_t *rowid,
                                                  int mbits, uint64_t side_key, KT *keys, int32_t *vals,
                                                  uint32_t *hist, int nblocks, int rep, int64_t G,
@@ -357,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
     // wave 0, lanes 0 and 1: the rows of the first items of the block's A and
     // B parts (loaded beside the items' own loads)
     int64_t crl = -1;
-    if (rep > 1 && threadIdx.x < 2) {
+    if (!VC && rep > 1 && threadIdx.x < 2) {
         const int64_t lo = threadIdx.x == 0 ? i0 : max(i0, A.nt);
         const int64_t hi = threadIdx.x == 0 ? min(i1, A.nt) : i1;
         if (lo < hi) crl = rowid[lo];
@@ -380,16 +467,21 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
         vi[r] = ok[r] ? S.v_off[g[r]] + corner(S.tri, t, 0, nvr) : 0;
     }
     // the key point is the triangle's first vertex (keys only order work)
-    double cen[PER][3];
+    double cen[VC ? 1 : PER][3];
+    uint32_t code[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
-        const double *X = sa[r] ? A.xyz : B.xyz;
+        if (VC) {
+            code[r] = ok[r] ? (sa[r] ? A.vcode : B.vcode)[vi[r]] : 0u;
+        } else {
+            const double *X = sa[r] ? A.xyz : B.xyz;
 #pragma unroll
-        for (int c = 0; c < 3; c++) cen[r][c] = ok[r] ? X[3 * vi[r] + c] : 0.0;
+            for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? X[3 * vi[r] + c] : 0.0;
+        }
     }
     // wave 0 merges the replicas of those rows and the next ones (lanes 0-23:
     // side, row offset, component) while the coordinates are in flight
-    if (rep > 1 && threadIdx.x < 64) {
+    if (!VC && rep > 1 && threadIdx.x < 64) {
         const int sd = lane / 12, j = (lane / 6) & 1, k = lane % 6;
         const int64_t c = __shfl(crl, lane < 24 ? sd : 0);
         if (lane < 24 && c >= 0 && c + j < G) cb[sd][j][k] = merged_box(sd ? B.box : A.box, rep, G, c + j, k);
@@ -400,27 +492,20 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
     for (int r = 0; r < PER; r++) {
         if (!ok[r]) continue;
         const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
-        const MortonSide &S = sa[r] ? A : B;
         const int64_t gr = g[r];
-        const int sd = sa[r] ? 0 : 1;
-        const int64_t j = rep > 1 ? gr - cr[sd] : -1;
-        const bool cached = j == 0 || j == 1;
-        double lo[3], ext = 0.0;
-        for (int k = 0; k < 3; k++) {
-            lo[k] = from_ordered_bits(cached ? cb[sd][j][k] : merged_box(S.box, rep, G, gr, k));
-            const double hk =
-                from_ordered_bits(cached ? cb[sd][j][3 + k] : merged_box(S.box, rep, G, gr, 3 + k));
-            ext = fmax(ext, hk - lo[k]);
+        if (!VC) {
+            const MortonSide &S = sa[r] ? A : B;
+            const int sd = sa[r] ? 0 : 1;
+            const int64_t j = rep > 1 ? gr - cr[sd] : -1;
+            const bool cached = j == 0 || j == 1;
+            unsigned long long b[6];
+            for (int k = 0; k < 6; k++) b[k] = cached ? cb[sd][j][k] : merged_box(S.box, rep, G, gr, k);
+            double lo[3];
+            const double sc = row_cells(b, lo);
+            code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
         }
-        const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
-        uint32_t q[3];
-        for (int k = 0; k < 3; k++) {
-            double f = (cen[r][k] - lo[k]) * sc;
-            int qi = (int)f;
-            q[k] = (uint32_t)(qi < 0 ? 0 : (qi > 1023 ? 1023 : qi));
-        }
-        uint32_t code = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-        const KT key = (KT)((sa[r] ? 0ull : side_key) | ((uint64_t)gr << mbits) | (code >> (30 - mbits)));
+        const KT key =
+            (KT)((sa[r] ? 0ull : side_key) | ((uint64_t)gr << mbits) | (code[r] >> (30 - mbits)));
         keys[i] = key;
         vals[i] = (int32_t)(sa[r] ? i : i - A.nt);
         atomicAdd(&h[(uint32_t)key & 255u], 1u);
@@ -766,20 +851,28 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
                       KernelEvents *kev) {
     const int key_bits = K.rowbits + K.mbits;  // bits below the side bit
     const int64_t n = A.nt + B.nt;
-    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox};
-    MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox};
+    // large sorts take their keys from per-vertex codes (P.vcode is then set)
+    constexpr bool VC = RSI > RS_ITEMS;
+    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode};
+    MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox, VC ? P.vcode + A.nv : nullptr};
+    if (VC) {
+        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv)};
+        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv)};
+        if (ca.nblk + cb.nblk > 0)
+            hipLaunchKernelGGL(k_vcode, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
+    }
     const int nb = (int)((n + RSI - 1) / RSI);
     // at least one block: the key kernel also starts the row states
     const int grid = nb > 0 ? nb : 1;
     if (key_bits + 1 <= 32) {
         // both ping-pong buffers of 32-bit keys live in keys[1]
         uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
-        hipLaunchKernelGGL((k_morton<uint32_t, RSI>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
-                           K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb, A.boxrep, A.G,
-                           rows);
+        hipLaunchKernelGGL((k_morton<uint32_t, RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb,
+                           P.rowid, K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb,
+                           A.boxrep, A.G, rows);
         return radix_sort<uint32_t, RSI>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
     }
-    hipLaunchKernelGGL((k_morton<uint64_t, RSI>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
+    hipLaunchKernelGGL((k_morton<uint64_t, RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
                        K.mbits, 1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb, A.boxrep, A.G,
                        rows);
     return radix_sort<uint64_t, RSI>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
@@ -791,8 +884,9 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
     // smaller sort blocks shorten each block's serial ranking on small sorts;
     // larger ones write longer contiguous runs on big sorts
     const int64_t n = A.nt + B.nt;
-    const int cur = n <= ((int64_t)1 << 22) ? sort_items<RS_ITEMS>(A, B, P, K, rows, s, kev)
-                                            : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
+    // (the large-sort variant needs the per-vertex code buffer)
+    const int cur = n <= SMALL_SORT || !P.vcode ? sort_items<RS_ITEMS>(A, B, P, K, rows, s, kev)
+                                                : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
