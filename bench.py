@@ -58,6 +58,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30    # --copy-calibration: 1 GiB read + 1 GiB written
+TUNE_REPS = 8           # autotuner rounds (each times every tile size once)
 
 TRAFFIC_FILES = {"tin512": "traffic_tin512_pair.json", "batch4096": "traffic_batch4096.json",
                  "scale": "traffic_scale_tin_blob.json"}
@@ -137,7 +138,7 @@ def roofline_for(kernel, st_list, ms, n, workload):
     raise KeyError(kernel)
 
 
-def pairs_roofline(st, ms, n):
+def pairs_roofline(st, ms, n, workload):
     """st: the call's stats (every queue pass); ms / n: the call's summed
     main-pass time / launches (one per queue pass)."""
     n = max(n, 1)
@@ -147,6 +148,7 @@ def pairs_roofline(st, ms, n):
     ach = flops / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
     return {"kernel": "k_pairs<fp32,distance>", "bound": "alu", "achieved": ach,
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic(f"k_pairs<fp32,distance,{st['tile']}> main pass", workload),
             "avg_launch_ms": avg, "flops_per_launch": flops,
             "per_unit": f"{FLOPS_FP32_PAIR} flops per FP32 pair test, {FLOPS_BOX} per box test"}
 
@@ -253,10 +255,10 @@ def main():
 
     # tile sizes picked by the autotuner on this workload (the choice is kept
     # in the context for tile=0 calls and graphs)
-    tune = {"distance": ctx.autotune("distance", ba, bb, order="learned", ranker=weights, reps=2),
-            "intersects": ctx.autotune("intersects", ba, bb, reps=2)}
-    tune64 = {"distance": ctx.autotune("distance", ba, bb, precision="fp64", reps=2),
-              "intersects": ctx.autotune("intersects", ba, bb, precision="fp64", reps=2)}
+    tune = {"distance": ctx.autotune("distance", ba, bb, order="learned", ranker=weights, reps=TUNE_REPS),
+            "intersects": ctx.autotune("intersects", ba, bb, reps=TUNE_REPS)}
+    tune64 = {"distance": ctx.autotune("distance", ba, bb, precision="fp64", reps=TUNE_REPS),
+              "intersects": ctx.autotune("intersects", ba, bb, precision="fp64", reps=TUNE_REPS)}
 
     def graphs(prec, order):
         w = weights if order == "learned" else None
@@ -347,10 +349,10 @@ def main():
     if dom in hbm_classes:
         roof = roofline_for(dom, [sd, si], kms[dom], kn[dom], args.workload)
     else:
-        roof = pairs_roofline(sd, sd["ms_kernel"]["pairs"], max(sd["n_kernel"]["pairs"], 1))
+        roof = pairs_roofline(sd, sd["ms_kernel"]["pairs"], max(sd["n_kernel"]["pairs"], 1), args.workload)
     roof["dominant_by_time"] = dom
     roof["kernel_ms_per_step"] = {k: round(v, 4) for k, v in kms.items()}
-    secondary = pairs_roofline(sd, sd["ms_kernel"]["pairs"], sd["n_kernel"]["pairs"])
+    secondary = pairs_roofline(sd, sd["ms_kernel"]["pairs"], sd["n_kernel"]["pairs"], args.workload)
 
     tri_exec = (sd32["tri_pairs_fp32"] + sd32["tri_pairs_fp64"] + si32["tri_pairs_fp32"] +
                 si32["tri_pairs_fp64"])

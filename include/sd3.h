@@ -242,9 +242,10 @@ sd3_status sd3_graph_result(sd3_graph *graph, sd3_stats *stats, void *stream);
 sd3_status sd3_graph_destroy(sd3_graph *graph);
 
 /*
- * Tile-size autotuner.  Runs the call `kind` on the given batches once per
- * candidate tile size (32, 64, 128 triangles) for 1 + reps repetitions, keeps
- * the median wall time of the last reps, and records the fastest size in ctx
+ * Tile-size autotuner.  Runs the call `kind` on the given batches with each
+ * candidate tile size (32, 64, 128 triangles): one untimed round, then reps
+ * rounds that time the sizes in turn; keeps each size's median wall time of
+ * those rounds, and records the fastest size in ctx
  * for this kind of workload (operator, precision, order, and the binary
  * magnitudes of the row count and of the mean triangles per row): later calls
  * with opts->tile == SD3_TILE_AUTO on a workload of the same kind use it.

@@ -926,28 +926,31 @@ sd3_status sd3_autotune(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd
     }
     const int cand[3] = {32, 64, 128};
     sd3_tune_report rep{};
-    double best_ms = 0.0;
-    for (int c = 0; c < 3; c++) {
-        opts.tile = cand[c];
-        std::vector<double> ms;
-        for (int r = 0; r <= reps && st == SD3_OK; r++) {
+    // one untimed call per size, then `reps` rounds that time the sizes in
+    // turn (drift of the clock or of the device affects every size alike)
+    std::vector<double> ms[3];
+    for (int r = 0; r <= reps && st == SD3_OK; r++) {
+        for (int c = 0; c < 3 && st == SD3_OK; c++) {
+            opts.tile = cand[c];
             auto t0 = std::chrono::steady_clock::now();
             st = run(ctx, a, b, mode == 0 ? dist : nullptr, hit, &opts, nullptr, stream, mode);
             auto t1 = std::chrono::steady_clock::now();
-            if (r > 0) ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+            if (r > 0) ms[c].push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
         }
-        if (st != SD3_OK) break;
-        std::sort(ms.begin(), ms.end());
+    }
+    if (dev_out.p) release(dev_out);
+    if (st != SD3_OK) return st;
+    double best_ms = 0.0;
+    for (int c = 0; c < 3; c++) {
+        std::sort(ms[c].begin(), ms[c].end());
         rep.tile[c] = cand[c];
-        rep.ms[c] = ms[ms.size() / 2];
+        rep.ms[c] = ms[c][ms[c].size() / 2];
         rep.n = c + 1;
         if (c == 0 || rep.ms[c] < best_ms) {
             best_ms = rep.ms[c];
             rep.best = cand[c];
         }
     }
-    if (dev_out.p) release(dev_out);
-    if (st != SD3_OK) return st;
     opts.tile = SD3_TILE_AUTO;
     ctx->tuned[workload_key(opts, mode, a, b)] = rep.best;
     if (report) *report = rep;
