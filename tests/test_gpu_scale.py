@@ -7,7 +7,11 @@ the benchmark times (HIP graphs, autotuned tiles, learned seed round):
 * the 4096-row drill-hole / ore-body batch (about 1.8e8 triangles): sampled
   rows against the oracle one by one, and properties on every row (FP32 +
   rescue bit-identical to plain FP64, distance 0 exactly on intersecting
-  rows, a plausible hit fraction).
+  rows, a plausible hit fraction);
+* a 512-row batch of the same distribution in every precision, seed order and
+  tile size: each schedules the persistent queue differently (which tile
+  pairs are seeded, pruned, or run side by side) and all must give the same
+  bits, with the smallest rows against the oracle.
 """
 import numpy as np
 import pytest
@@ -103,3 +107,34 @@ def test_batch_4096_rows(ctx):
             assert abs(d32[r] - d_o) <= 1e-12 * d_o, (r, d32[r], d_o)
     g.close()
     gi.close()
+
+
+def test_batch_rows_every_variant_agrees(ctx):
+    print("batch512: generating", flush=True)
+    A, B = synth.config_tube_blob_batch(rows=512, seed=5)
+    ba = sd3.Batch.from_packed(synth.pack(A), "cuda:0")
+    bb = sd3.Batch.from_packed(synth.pack(B), "cuda:0")
+    w = ranker.load(device="cuda:0")
+    ref, ref_name = None, None
+    for prec in ("fp32", "fp64"):
+        for order in ("learned", "bound", "none"):
+            for tile in sd3.TILES:
+                print(f"batch512: {prec} {order} {tile}", flush=True)
+                d, h = ctx.distance(ba, bb, precision=prec, order=order, tile=tile,
+                                    ranker=w if order == "learned" else None)
+                hi = ctx.intersects(ba, bb, precision=prec, tile=tile)
+                got = (_bits(d.cpu().numpy()).copy(), h.cpu().numpy().astype(bool))
+                assert np.array_equal(got[1], hi.cpu().numpy().astype(bool)), (prec, order, tile)
+                if ref is None:
+                    ref, ref_name = got, (prec, order, tile)
+                bad = np.nonzero(got[0] != ref[0])[0]
+                assert bad.size == 0 and np.array_equal(got[1], ref[1]), \
+                    ((prec, order, tile), ref_name, bad[:8].tolist())
+    d = ref[0].view(np.float64)
+    assert np.all((d == 0.0) == ref[1])
+    sizes = np.array([len(a[1]) * len(b[1]) for a, b in zip(A, B)])
+    for r in np.argsort(sizes)[:3].tolist():
+        d_o, h_o, _ = oracle.mesh(A[r], B[r], mode="pruned")
+        assert bool(h_o) == bool(ref[1][r]), r
+        if not h_o:
+            assert abs(d[r] - d_o) <= 1e-12 * d_o, (r, d[r], d_o)
