@@ -106,15 +106,25 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
         if (threadIdx.x == 0) g0s = g0;
     }
     __syncthreads();
+    // every index load first, at clamped positions (one memory latency)
+    constexpr int PER = VT_ITEMS / 256;
+    int32_t tv[PER][3];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int64_t t = min(t0 + threadIdx.x + 256 * r, t1 - 1);
+#pragma unroll
+        for (int k = 0; k < 3; k++) tv[r][k] = S.tri[3 * t + k];
+    }
     int64_t g = g0s;
     uint32_t f = 0;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int64_t t = t0 + threadIdx.x + 256 * r;
+        if (t >= t1) break;
         while (S.t_off[g + 1] <= t) g++;
         const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
-        for (int k = 0; k < 3; k++) {
-            int32_t v = S.tri[3 * t + k];
-            if (v < 0 || v >= nvr) f = V_INDEX;
-        }
+        for (int k = 0; k < 3; k++)
+            if (tv[r][k] < 0 || tv[r][k] >= nvr) f = V_INDEX;
         rowid[(sa ? 0 : A.nt) + t] = (int32_t)g;
     }
     if (f) atomicOr(flags + (sa ? 0 : 1), f);
@@ -149,6 +159,25 @@ __device__ __forceinline__ int64_t walk_row(const int64_t *off, int64_t G, int64
     }
     return wave_find_row(off, G, i);
 }
+
+// The row of consecutive chunks' vertices, walked forward (wave-uniform):
+// the current row and the offset where it ends, so that a chunk inside one
+// row needs no load.
+struct RowCursor {
+    int64_t g, end;
+    __device__ void start(const int64_t *off, int64_t G, int64_t i) {
+        g = wave_find_row(off, G, i);
+        end = off[g + 1];
+    }
+    // row of vertex i (at or after the current row's start)
+    __device__ int64_t at(const int64_t *off, int64_t G, int64_t i) {
+        if (i >= end) {
+            g = walk_row(off, G, g, i);
+            end = off[g + 1];
+        }
+        return g;
+    }
+};
 
 // Row of one lane's vertex i of a chunk whose rows are g0..g1.
 __device__ __forceinline__ int64_t lane_row(const int64_t *off, int64_t G, int64_t g0, int64_t g1,
@@ -210,21 +239,27 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
     unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
     uint32_t f = 0;
     int64_t cur = -1;
-    // the rows of each chunk's first and last vertex, walked forward from the
-    // previous chunk's (rows are contiguous and usually span many chunks)
-    int64_t g1 = b0 < b1 ? wave_find_row(S.v_off, G, b0) : 0;
+    // the rows of each chunk's first and last vertex, walked forward (rows
+    // are contiguous and usually span many chunks); each chunk's coordinates
+    // are loaded while the previous chunk is reduced
+    RowCursor rc{0, 0};
+    double xn[3] = {0.0, 0.0, 0.0};
+    if (b0 < b1) {
+        rc.start(S.v_off, G, b0);
+        if (b0 + threadIdx.x < b1)
+            for (int k = 0; k < 3; k++) xn[k] = S.xyz[3 * (b0 + threadIdx.x) + k];
+    }
     for (int64_t base = b0; base < b1; base += 256) {
         int64_t last = min(base + 255, b1 - 1);
-        const int64_t g0 = walk_row(S.v_off, G, g1, base);
-        g1 = walk_row(S.v_off, G, g0, last);
+        const int64_t g0 = rc.at(S.v_off, G, base);
+        const int64_t g1 = rc.at(S.v_off, G, last);
         int64_t i = base + threadIdx.x;
         bool valid = i <= last;
-        double x[3] = {0.0, 0.0, 0.0};
+        const double x[3] = {xn[0], xn[1], xn[2]};
+        if (i + 256 < b1)
+            for (int k = 0; k < 3; k++) xn[k] = S.xyz[3 * (i + 256) + k];
         if (valid)
-            for (int k = 0; k < 3; k++) {
-                x[k] = S.xyz[3 * i + k];
-                f |= coord_flags(x[k]);
-            }
+            for (int k = 0; k < 3; k++) f |= coord_flags(x[k]);
         if (g0 == g1) {
             if (g0 != cur) {
                 if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
@@ -370,16 +405,22 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
     const int64_t b0 = blk * per, b1 = min(nv, b0 + per);
     int64_t cg = -1;  // row whose cells are held (wave-uniform)
     double clo[3] = {0.0, 0.0, 0.0}, csc = 0.0;
-    int64_t g1 = b0 < b1 ? wave_find_row(S.v_off, G, b0) : 0;
+    RowCursor rc{0, 0};
+    double pn[3] = {0.0, 0.0, 0.0};  // the next chunk's coordinates, in flight
+    if (b0 < b1) {
+        rc.start(S.v_off, G, b0);
+        if (b0 + threadIdx.x < b1)
+            for (int k = 0; k < 3; k++) pn[k] = S.xyz[3 * (b0 + threadIdx.x) + k];
+    }
     for (int64_t base = b0; base < b1; base += 256) {
         const int64_t last = min(base + 255, b1 - 1);
-        const int64_t g0 = walk_row(S.v_off, G, g1, base);
-        g1 = walk_row(S.v_off, G, g0, last);
+        const int64_t g0 = rc.at(S.v_off, G, base);
+        const int64_t g1 = rc.at(S.v_off, G, last);
         const int64_t i = base + threadIdx.x;
         const bool valid = i <= last;
-        double p[3] = {0.0, 0.0, 0.0};
-        if (valid)
-            for (int k = 0; k < 3; k++) p[k] = S.xyz[3 * i + k];
+        const double p[3] = {pn[0], pn[1], pn[2]};
+        if (i + 256 < b1)
+            for (int k = 0; k < 3; k++) pn[k] = S.xyz[3 * (i + 256) + k];
         if (g0 == g1) {
             if (g0 != cg) {
                 const unsigned long long m = lane < 6 ? merged_box(S.box, rep, G, g0, lane) : 0ull;
@@ -522,14 +563,19 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
 
 template <typename KT, int RS_ITEMS>
 __global__ void k_hist(const KT *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+    constexpr int PER = RS_ITEMS / 256;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
+    const int64_t base = (int64_t)blockIdx.x * RS_ITEMS;
+    // every load first, at clamped indices (n >= 2 here), so that the thread
+    // waits for one memory latency rather than one per item
+    KT k[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) k[r] = keys[min(base + r * 256 + threadIdx.x, n - 1)];
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_ITEMS;
-    for (int r = 0; r < RS_ITEMS / 256; r++) {
-        int64_t i = base + r * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
-    }
+#pragma unroll
+    for (int r = 0; r < PER; r++)
+        if (base + r * 256 + threadIdx.x < n) atomicAdd(&h[(k[r] >> shift) & 255], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
