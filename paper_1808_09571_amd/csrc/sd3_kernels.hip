@@ -1948,16 +1948,18 @@ __device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows,
     unsigned long long n64 = 0, nex = 0;
     for (unsigned i = first; i < n; i += step) {
         Rescue e = L.rescue[i];
+        int a = e.slots & 0xffff, b = e.slots >> 16;
+        // the vertices depend on the entry alone: their loads go out beside
+        // the row state's, not after its checks
+        double ta[F_NTRI64], tb[F_NTRI64];
+        load_tri64(SA, e.ta, a, ta);
+        load_tri64(SB, e.tb, b, tb);
         int g = mA[e.ta].row;
         RowState *R = rows + g;
         if (load_acq32(&R->hit)) continue;
-        int a = e.slots & 0xffff, b = e.slots >> 16;
         if (MODE == 0) {
             double ub = bits_to_double(load_acq(&R->ub));
             if ((double)e.lb > ub + row_margin(*R, ub)) continue;
-            double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(SA, e.ta, a, ta);
-            load_tri64(SB, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             Pair64 r = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1});
@@ -1975,9 +1977,6 @@ __device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows,
                 }
             }
         } else {
-            double ta[F_NTRI64], tb[F_NTRI64];
-            load_tri64(SA, e.ta, a, ta);
-            load_tri64(SB, e.tb, b, tb);
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
             int f = pair64(TriRef<double>{ta, 1}, TriRef<double>{tb, 1}).status;
@@ -2029,11 +2028,11 @@ __device__ void exact_items(const TriSrc &SA, const TriSrc &SB, RowState *rows, 
     const unsigned n = min(*L.xcount, L.xcap);
     for (unsigned i = first; i < n; i += step) {
         ExactItem e = L.exact[i];
-        RowState *R = rows + mA[e.ta].row;
-        if (load_acq32(&R->hit)) continue;
         double va[9], vb[9];
         load_tri64(SA, e.ta, e.slots & 0xffff, va);
         load_tri64(SB, e.tb, e.slots >> 16, vb);
+        RowState *R = rows + mA[e.ta].row;
+        if (load_acq32(&R->hit)) continue;
         if (ex::tri_tri_exact(va, vb)) {
             atomicOr(&R->hit, 1u);
             atomic_min_pos(&R->d2, 0.0);
