@@ -1818,12 +1818,9 @@ __global__ __launch_bounds__(256, PREC == 0 && TK <= 64 ? 3 : 1) void k_pairs(co
                         S.ub_now = ub_now + row_margin(*R, ub_now);
                     } else {
                         double dm = fmin(fmin(S.redd[0], S.redd[1]), fmin(S.redd[2], S.redd[3]));
-                        // (values at or above the row's state when the entry
-                        // was gathered cannot lower it: no atomic for them)
                         if (dm < __builtin_inf()) {
-                            const RowState &seen = S.brow[S.bi - 1];
-                            if (dm < bits_to_double(seen.d2)) atomic_min_pos(&R->d2, dm);
-                            if (sqrt(dm) < bits_to_double(seen.ub)) atomic_min_pos(&R->ub, sqrt(dm));
+                            atomic_min_pos(&R->d2, dm);
+                            atomic_min_pos(&R->ub, sqrt(dm));
                         }
                     }
                     if (L.log) {
@@ -1962,9 +1959,6 @@ __device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows,
         if (load_acq32(&R->hit)) continue;
         if (MODE == 0) {
             double ub = bits_to_double(load_acq(&R->ub));
-            // the row minimum as read now: a result at or above it cannot
-            // lower it (it only decreases), so no atomic is sent for it
-            const double d2_seen = bits_to_double(load_acq(&R->d2));
             if ((double)e.lb > ub + row_margin(*R, ub)) continue;
             tri_prep64(TriRef<double>{ta, 1});
             tri_prep64(TriRef<double>{tb, 1});
@@ -1974,7 +1968,7 @@ __device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows,
                 atomicOr(&R->hit, 1u);
                 atomic_min_pos(&R->d2, 0.0);
             } else {
-                if (r.d2 < d2_seen) atomic_min_pos(&R->d2, r.d2);
+                atomic_min_pos(&R->d2, r.d2);
                 if (r.status == 2) {
                     ExactItem it{e.ta, e.tb, e.slots, 0, r.d2};
                     unsigned j = atomicAdd(L.xcount, 1u);
