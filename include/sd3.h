@@ -110,9 +110,12 @@ typedef struct sd3_opts {
     float *log;          /* device or NULL: one record per tile pair dequeued by
                             sd3_distance, SD3_LOG_STRIDE floats each */
     int64_t log_cap;     /* records `log` can hold; extra records are dropped */
-    int64_t queue_cap;   /* tile pairs the candidate queue holds per pass (0: 2^27);
+    int64_t queue_cap;   /* tile pairs the candidate queue holds per pass (0: 2^29);
                             larger workloads are processed in several passes */
-    int64_t reserved[3];
+    int64_t rescue_cap;  /* 0, or a smaller bound of the FP32 rescue list (2^24) */
+    int64_t exact_cap;   /* 0, or the starting bound of the exact-arithmetic list
+                            (2^22) */
+    int64_t reserved[1];
 } sd3_opts;
 
 #define SD3_TILE_AUTO 0
@@ -152,6 +155,14 @@ typedef struct sd3_stats {
     int32_t sort_passes;
     int32_t tile;                  /* triangles per tile used by the call */
     int32_t queue_passes;          /* candidate-queue passes */
+    int64_t queue_skew;            /* consistency check of the tile-pair pass:
+                                      evaluated tile pairs whose two tiles name
+                                      different rows (0 in a correct run) */
+    int32_t fallback;              /* work-list overflows the call recovered
+                                      from by computing again: a full rescue
+                                      list by the plain FP64 pass (same bits),
+                                      a full exact list with a 4x longer one */
+    int32_t reserved32;
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;
@@ -175,6 +186,9 @@ sd3_status sd3_destroy(sd3_ctx *ctx);
  * dist/hit are device pointers when a->mem == SD3_MEM_DEVICE, host pointers
  * otherwise.  opts and stats may be NULL.  stream is a hipStream_t (NULL: the
  * default stream); the call synchronises it before returning.
+ * A work list that overflows does not fail the call: the FP32 rescue list is
+ * replaced by the plain FP64 pass (identical results), the exact list is
+ * enlarged (up to 2^26 entries); stats->fallback counts such re-runs.
  * On any error the outputs are left untouched.
  */
 sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
@@ -187,6 +201,49 @@ sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, do
  */
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
                           const sd3_opts *opts, sd3_stats *stats, void *stream);
+
+/*
+ * 3D volume of each row (Sec. 3.2.1): the divergence theorem with the field
+ * p / 3 (Eq. 1) gives V = 1/6 sum over triangles (u, v, w) of
+ * u . ((v - u) x (w - u)) (Eq. 2).  Positive for closed meshes whose triangles
+ * are counter-clockwise seen from outside; for other meshes it is that flux
+ * sum as written (relative to the origin).  vol: [count] doubles (device
+ * memory when g->mem == SD3_MEM_DEVICE, else host).  Computed in
+ * double-double (about 100 bits before the final rounding): within 1e-12
+ * relative of the exact value unless the faces' terms cancel by more than
+ * about 2^50.  An empty row gives 0.  Errors: as sd3_validate for the batch;
+ * outputs untouched on error.
+ */
+sd3_status sd3_volume(sd3_ctx *ctx, const sd3_geoms *g, double *vol, sd3_stats *stats, void *stream);
+
+/*
+ * Segments (or points) against one triangle mesh: the workload the paper
+ * measures (Sec. 4: drill-hole line segments against an ore-body mesh), with
+ * the operators of Sec. 3.2.2 (distance: segment/segment, segment/surface and
+ * point/surface distances, then the minimum) and Sec. 3.2.3 (intersection:
+ * Eq. 4 with closed constraints), plus the distance-threshold filter of
+ * Sec. 4 ("filtering drill holes based on their distance").
+ *   op    : SD3_SEG_DISTANCE (dist[i] = distance of segment i to the mesh,
+ *           flag[i] = intersects, flag may be NULL), SD3_SEG_INTERSECTS
+ *           (flag[i] = intersects) or SD3_SEG_WITHIN (flag[i] = 1 iff the
+ *           distance sd3 returns for segment i is <= r; r finite, >= 0)
+ *   seg   : [n][2][3] doubles, endpoints P0 P1 of each segment; P0 == P1 is a
+ *           point.  A segment is the closed set {P0 + t (P1 - P0), t in [0, 1]}
+ *   mesh  : a batch of exactly one row (at most 2^25 - 1 triangles)
+ *   seg_mem : SD3_MEM_HOST or SD3_MEM_DEVICE; must equal mesh->mem; the
+ *           outputs are in the same kind of memory
+ * Results equal those of sd3_distance / sd3_intersects on the segment as the
+ * degenerate triangle (P0, P1, P1): FP64 distances, exact flags; an empty mesh
+ * gives +inf and 0.  Errors as for sd3_distance (validation of the segment
+ * coordinates and of the mesh); outputs untouched on error.  stats: box tests
+ * in tri_pairs_boxed, FP64 pair tests in tri_pairs_fp64, exact tests in exact.
+ */
+#define SD3_SEG_DISTANCE 0
+#define SD3_SEG_INTERSECTS 1
+#define SD3_SEG_WITHIN 2
+sd3_status sd3_segments(sd3_ctx *ctx, int32_t op, const double *seg, int64_t n, int32_t seg_mem,
+                        const sd3_geoms *mesh, double r, double *dist, uint8_t *flag,
+                        sd3_stats *stats, void *stream);
 
 /*
  * Training of the tile-pair ranker (SD3_ORDER_LEARNED) by the library's own
@@ -208,6 +265,18 @@ sd3_status sd3_mlp_loss_grad(sd3_ctx *ctx, const float *params, const float *x, 
                              int64_t n, float *loss, float *grad, void *stream);
 sd3_status sd3_adam_step(sd3_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t count,
                          int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * The scorer of the learned seed round (SD3_ORDER_LEARNED) applied to given
+ * feature rows: y[i] = MLP(x[i]) for x [n][SD3_MLP_NIN], computed by the same
+ * device function and LDS weight layout that ranks queued tile pairs inside
+ * sd3_distance (one wave per row, lane = hidden unit).  sd3_mlp_forward is the
+ * training path's batched forward pass; both evaluate the same network.
+ * Device arrays, asynchronous on `stream`.  Errors: SD3_E_INVALID_ARG for NULL
+ * pointers or n < 0.
+ */
+sd3_status sd3_mlp_score(sd3_ctx *ctx, const float *params, const float *x, int64_t n, float *y,
+                         void *stream);
 
 /*
  * Batched replay through a HIP graph.  sd3_graph_create plans one call of

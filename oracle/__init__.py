@@ -66,6 +66,12 @@ def load(path: str | None = None):
     lib.sd3o_mesh.argtypes = [_D, _I32, ctypes.c_int64, _D, _I32, ctypes.c_int64, ctypes.c_int,
                               ctypes.c_int, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
     lib.sd3o_mesh.restype = ctypes.c_int64
+    lib.sd3o_volume6_exact.argtypes = [_D, ctypes.c_int64, _I32, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]
+    lib.sd3o_volume6_exact.restype = ctypes.c_int
+    lib.sd3o_winding.argtypes = [_D, _I32, ctypes.c_int64, _D]
+    lib.sd3o_winding.restype = ctypes.c_double
     if path is None:
         _lib = lib
     return lib
@@ -181,3 +187,54 @@ def batch(packed_a, packed_b, mode="all", want="distance", threads=None, rows=No
         dist[k] = np.nan if d is None else d
         hit[k] = h
     return dist, hit
+
+
+def volume_exact(mesh, threads=None, lib=None):
+    """Volume of a mesh by the divergence theorem (Sec. 3.2.1, Eq. 2:
+    1/6 of the sum over faces of u . ((v - u) x (w - u))), evaluated exactly:
+    returned as a fractions.Fraction."""
+    from fractions import Fraction
+    lib = lib or load()
+    x = np.ascontiguousarray(mesh[0], dtype=np.float64).reshape(-1)
+    t = np.ascontiguousarray(mesh[1], dtype=np.int32).reshape(-1)
+    if not check_range(x):
+        raise ValueError("coordinates outside the supported range")
+    limbs = (ctypes.c_uint32 * 72)()
+    neg, e0 = ctypes.c_int(0), ctypes.c_int(0)
+    n = lib.sd3o_volume6_exact(x.ctypes.data_as(_D), x.size // 3, t.ctypes.data_as(_I32), t.size // 3,
+                               int(threads or default_threads()), limbs, ctypes.byref(neg),
+                               ctypes.byref(e0))
+    if n < 0:
+        raise ValueError("triangle index out of range")
+    mag = sum(int(limbs[i]) << (32 * i) for i in range(n))
+    v6 = Fraction(-mag if neg.value else mag) * Fraction(2) ** (3 * e0.value)
+    return v6 / 6
+
+
+def volume(mesh, threads=None, lib=None):
+    """The exact volume rounded to the nearest double."""
+    return float(volume_exact(mesh, threads, lib))
+
+
+def winding(mesh, p, lib=None):
+    """Generalised winding number of a closed mesh around point p (FP64)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(mesh[0], dtype=np.float64).reshape(-1)
+    t = np.ascontiguousarray(mesh[1], dtype=np.int32).reshape(-1)
+    q = np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+    return float(lib.sd3o_winding(x.ctypes.data_as(_D), t.ctypes.data_as(_I32), t.size // 3,
+                                  q.ctypes.data_as(_D)))
+
+
+def mesh_solid(A, B, mode="pruned", threads=None, lib=None):
+    """Distance and intersects under solid semantics: each row is the closed
+    region a closed, outward-oriented (connected) mesh bounds.  The solids meet
+    iff the surfaces meet or a vertex of one lies inside the other (winding
+    number above 1/2); the distance is then 0, else the surface distance.
+    Returns (dist, hit)."""
+    d, h, _ = mesh(A, B, mode=mode, threads=threads, lib=lib)
+    if h:
+        return 0.0, True
+    inside = ((len(A[1]) and len(B[1]) and winding(B, np.asarray(A[0])[int(np.asarray(A[1])[0][0])], lib) > 0.5)
+              or (len(A[1]) and len(B[1]) and winding(A, np.asarray(B[0])[int(np.asarray(B[1])[0][0])], lib) > 0.5))
+    return (0.0, True) if inside else (d, False)

@@ -712,3 +712,99 @@ int64_t sd3o_mesh(const double *xa, const int32_t *ta, int64_t na, const double 
     *hit = h;
     return tests;
 }
+
+/* ------------------------------------------------------------------------- */
+/* 3D volume (Sec. 3.2.1): the divergence theorem with F = p/3 turns the      */
+/* volume integral into a sum over the faces (Eq. 1); on a triangle u v w the */
+/* flux of F through the face is u . n / 6 with n = (v - u) x (w - u) (Eq. 2, */
+/* counter-clockwise seen from outside), so V = 1/6 sum_i u_i . n_i.          */
+/* Evaluated exactly: every coordinate is an integer times 2^e0 (e0 the       */
+/* smallest unit in the last place over the mesh), each term is an exact      */
+/* integer in units of 2^(3 e0), and the sum is exact.                        */
+/* ------------------------------------------------------------------------- */
+static void vol_term(const double *xyz, const int32_t *tri, int64_t t, int e0, bn *out) {
+    bn U[3], V[3], W[3], a[3], b[3], n[3], p, q;
+    for (int k = 0; k < 3; k++) {
+        bn_from_double(&U[k], xyz[3 * (int64_t)tri[3 * t] + k], e0);
+        bn_from_double(&V[k], xyz[3 * (int64_t)tri[3 * t + 1] + k], e0);
+        bn_from_double(&W[k], xyz[3 * (int64_t)tri[3 * t + 2] + k], e0);
+    }
+    for (int k = 0; k < 3; k++) {
+        bn_sub(&a[k], &V[k], &U[k]);
+        bn_sub(&b[k], &W[k], &U[k]);
+    }
+    for (int k = 0; k < 3; k++) {  /* n = a x b */
+        int j = (k + 1) % 3, l = (k + 2) % 3;
+        bn_mul(&p, &a[j], &b[l]);
+        bn_mul(&q, &a[l], &b[j]);
+        bn_sub(&n[k], &p, &q);
+    }
+    memset(out, 0, sizeof *out);
+    for (int k = 0; k < 3; k++) {  /* u . n */
+        bn_mul(&p, &U[k], &n[k]);
+        bn_add(out, out, &p);
+    }
+}
+
+/*
+ * 6 V of one mesh exactly: |6 V| = sum_i limbs[i] 2^(32 i) * 2^(3 e0), with
+ * the sign in *neg.  Returns the number of limbs (0 for V = 0) or -1 when an
+ * index is out of range.
+ */
+int sd3o_volume6_exact(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, int threads,
+                       uint32_t *limbs, int *neg, int *e0_out) {
+    for (int64_t i = 0; i < 3 * nt; i++)
+        if (tri[i] < 0 || tri[i] >= nv) return -1;
+    int e0 = 1 << 20;
+    for (int64_t i = 0; i < 3 * nv; i++)
+        if (xyz[i] != 0.0) {
+            int e = ulp_exp(xyz[i]);
+            if (e < e0) e0 = e;
+        }
+    if (e0 == (1 << 20)) e0 = 0;
+    bn total;
+    memset(&total, 0, sizeof total);
+    if (threads < 1) threads = 1;
+#pragma omp parallel num_threads(threads)
+    {
+        bn part, term;
+        memset(&part, 0, sizeof part);
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < nt; t++) {
+            vol_term(xyz, tri, t, e0, &term);
+            bn_add(&part, &part, &term);
+        }
+#pragma omp critical
+        bn_add(&total, &total, &part);
+    }
+    for (int i = 0; i < total.n; i++) limbs[i] = total.d[i];
+    *neg = total.neg;
+    *e0_out = e0;
+    return total.n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Point in solid: the generalised winding number of a closed, consistently   */
+/* oriented mesh around p, the sum of the signed solid angles its triangles   */
+/* subtend at p over 4 pi (Van Oosterom and Strackee's formula for the solid  */
+/* angle of a triangle).  1 inside, 0 outside, in FP64; meaningful for points */
+/* not within rounding distance of the surface.                              */
+/* ------------------------------------------------------------------------- */
+double sd3o_winding(const double *xyz, const int32_t *tri, int64_t nt, const double *p) {
+    double total = 0.0;
+    for (int64_t t = 0; t < nt; t++) {
+        double a[3], b[3], c[3];
+        for (int k = 0; k < 3; k++) {
+            a[k] = xyz[3 * (int64_t)tri[3 * t] + k] - p[k];
+            b[k] = xyz[3 * (int64_t)tri[3 * t + 1] + k] - p[k];
+            c[k] = xyz[3 * (int64_t)tri[3 * t + 2] + k] - p[k];
+        }
+        double la = sqrt(dot3(a, a)), lb = sqrt(dot3(b, b)), lc = sqrt(dot3(c, c));
+        double bc[3];
+        cross3(b, c, bc);
+        double num = dot3(a, bc);
+        double den = la * lb * lc + dot3(a, b) * lc + dot3(a, c) * lb + dot3(b, c) * la;
+        total += 2.0 * atan2(num, den);
+    }
+    return total / (4.0 * 3.14159265358979323846);
+}

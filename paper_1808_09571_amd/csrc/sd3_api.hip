@@ -33,12 +33,54 @@ struct SideState {
     DevBuf xyz, tri, rowbox, t32, t64, ids, meta;
 };
 
+constexpr unsigned int QUEUE_BUDGET = 1u << 29;   // tile pairs per queue pass (12 B each)
+constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
+constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
+constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic
+constexpr unsigned int EXACT_CAP_MAX = 1u << 26;  // largest exact list an eager call grows to
+// Calls without allocation (sd3_distance_noalloc): every buffer is carved
+// from one static device array; smaller work lists, longer queues run in
+// more passes.
+constexpr unsigned int NOALLOC_QUEUE = 1u << 21;
+constexpr unsigned int NOALLOC_RESCUE = 1u << 20;
+constexpr unsigned int NOALLOC_EXACT = 1u << 18;
+
+// The buffers of a call outgrew the static scratch (bytes needed so far).
+struct ScratchFull {
+    size_t need;
+};
+
+void *ensure(DevBuf &b, size_t bytes);
+
 // Device work space of one call: a context owns one, and every graph owns its
 // own, so that replays never share buffers with eager calls.
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
     DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, vcode, small, grpA, grpB, wi_lb, wlist;
+    DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
+    DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
+    // work-list capacities (a call's options may lower them)
+    int64_t queue_budget = QUEUE_BUDGET;
+    unsigned int rescue_cap = RESCUE_CAP, exact_cap = EXACT_CAP;
+    // static scratch mode: buffers are carved from [arena, arena + arena_cap)
+    // in call order and never freed; the DevBufs stay empty
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    bool arena_full = false;
+    void *buf(DevBuf &b, size_t bytes) {
+        if (!arena) return ensure(b, bytes);
+        if (bytes == 0) bytes = 256;
+        const size_t off = (arena_used + 255) & ~(size_t)255;
+        arena_used = off + bytes;
+        if (arena_used > arena_cap) {
+            // keep counting (the error reports the whole need); nothing is
+            // launched or copied before the plan checks arena_full
+            arena_full = true;
+            return arena;
+        }
+        return arena + off;
+    }
     void release_all() {
         for (auto &sd : side) {
             DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
@@ -46,7 +88,7 @@ struct Workspace {
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
                         &vals0, &vals1, &hist, &part, &rowid, &vcode, &small, &grpA, &grpB, &wi_lb,
-                        &wlist};
+                        &wlist, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part};
         for (DevBuf *b : bs) release(*b);
     }
 };
@@ -71,6 +113,7 @@ struct sd3_ctx {
     void *pin = nullptr;  // pinned host staging: offsets up, counters down
     size_t pin_cap = 0;
     int pairs_grid[2][2][3] = {};         // [precision][mode][tile size 32/64/128]
+    int seg_grid[3] = {};                 // segment kernels, per operator
     std::map<uint64_t, int> tuned;        // workload key -> tile size (sd3_autotune)
     hipEvent_t ev[8] = {};
     KernelEvents *kev = nullptr;  // created on the first timed call
@@ -78,10 +121,6 @@ struct sd3_ctx {
 
 namespace {
 
-constexpr unsigned int QUEUE_BUDGET = 1u << 29;   // tile pairs per queue pass (12 B each)
-constexpr unsigned int QUEUE_MIN = 64u * 256u;    // one work item's tile pairs
-constexpr unsigned int RESCUE_CAP = 1u << 24;     // FP32 pairs sent to FP64
-constexpr unsigned int EXACT_CAP = 1u << 22;      // pairs sent to exact arithmetic
 constexpr int64_t RESOLVE_MAX_ROWS = 64;           // FP64 rescue inside the exact launch
 constexpr int64_t COMPACT_MIN_ROWS = 64;           // compacted work lists above this
 // device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
@@ -269,6 +308,8 @@ sd3_status check_call(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, cons
     if (opts.tile != SD3_TILE_AUTO && !tile_size_ok(opts.tile))
         return fail(ctx, SD3_E_INVALID_ARG, "tile must be 0, 32, 64 or 128");
     if (opts.queue_cap < 0) return fail(ctx, SD3_E_INVALID_ARG, "queue_cap < 0");
+    if (opts.rescue_cap < 0 || opts.exact_cap < 0 || opts.rescue_cap > INT32_MAX || opts.exact_cap > INT32_MAX)
+        return fail(ctx, SD3_E_INVALID_ARG, "rescue_cap / exact_cap outside [0, 2^31)");
     if (opts.log && (opts.log_cap < 0 || a->mem != SD3_MEM_DEVICE))
         return fail(ctx, SD3_E_INVALID_ARG, "log needs a device buffer and log_cap >= 0");
     if (a->mem == SD3_MEM_HOST) {
@@ -330,8 +371,8 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     S.NT = NT;
     S.tk = tk;
     if (g->mem == SD3_MEM_HOST) {
-        double *x = (double *)ensure(st.xyz, sizeof(double) * 3 * nv);
-        int32_t *t = (int32_t *)ensure(st.tri, sizeof(int32_t) * 3 * nt);
+        double *x = (double *)ws.buf(st.xyz, sizeof(double) * 3 * nv);
+        int32_t *t = (int32_t *)ws.buf(st.tri, sizeof(int32_t) * 3 * nt);
         if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
         if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
         S.xyz = x;
@@ -348,14 +389,14 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     // caller), room for the most any side can ask for is kept here
     S.boxrep = rowbox_replicas(nv, G);
     const int64_t rep_room = std::max<int64_t>(rowbox_replicas((int64_t)1 << 40, G), 1);
-    S.rowbox = (unsigned long long *)ensure(st.rowbox, sizeof(unsigned long long) * 6 * rep_room *
+    S.rowbox = (unsigned long long *)ws.buf(st.rowbox, sizeof(unsigned long long) * 6 * rep_room *
                                                            (G > 0 ? G : 1));
-    S.t32 = (float *)ensure(st.t32, sizeof(float) * 9 * tk * S.NT);
+    S.t32 = (float *)ws.buf(st.t32, sizeof(float) * 9 * tk * S.NT);
     // FP64 tile copies only for the plain FP64 pass; the FP32 path keeps the
     // triangle id of each slot and gathers FP64 vertices for its few rescues
-    S.t64 = fp64 ? (double *)ensure(st.t64, sizeof(double) * 9 * tk * S.NT) : nullptr;
-    S.ids = fp64 ? nullptr : (int32_t *)ensure(st.ids, sizeof(int32_t) * tk * S.NT);
-    S.meta = (TileMeta *)ensure(st.meta, sizeof(TileMeta) * S.NT);
+    S.t64 = fp64 ? (double *)ws.buf(st.t64, sizeof(double) * 9 * tk * S.NT) : nullptr;
+    S.ids = fp64 ? nullptr : (int32_t *)ws.buf(st.ids, sizeof(int32_t) * tk * S.NT);
+    S.meta = (TileMeta *)ws.buf(st.meta, sizeof(TileMeta) * S.NT);
 }
 
 // Plans a call: tiles and work items per row, buffer sizes in `ws`, offsets
@@ -369,6 +410,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     Plan &P = C.P;
     P.G = G;
     P.tk = tk;
+    P.potential = 0;
     P.tileA.assign(G + 1, 0);
     P.tileB.assign(G + 1, 0);
     P.wi.assign(G + 1, 0);
@@ -398,8 +440,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     memcpy(hs + 6 * G1, P.wi.data(), sizeof(int64_t) * G1);
     memcpy(hs + 7 * G1, P.blkA.data(), sizeof(int64_t) * G1);
     memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
-    int64_t *ds = (int64_t *)ensure(ws.small, sizeof(int64_t) * 9 * G1);
-    check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
+    int64_t *ds = (int64_t *)ws.buf(ws.small, sizeof(int64_t) * 9 * G1);
     const bool fp64 = opts.precision == SD3_PREC_FP64;
     setup_side(ws, 0, a, P.tileA[G], tk, fp64, ds, C.A, s);
     setup_side(ws, 1, b, P.tileB[G], tk, fp64, ds + 3 * G1, C.B, s);
@@ -407,37 +448,42 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     {
         int64_t n = C.A.nt + C.B.nt;
         int64_t nb = (n + RS_ITEMS - 1) / RS_ITEMS + 1;
-        C.PB.keys[0] = (uint64_t *)ensure(ws.keys0, sizeof(uint64_t) * n);
-        C.PB.keys[1] = (uint64_t *)ensure(ws.keys1, sizeof(uint64_t) * n);
-        C.PB.vals[0] = (int32_t *)ensure(ws.vals0, sizeof(int32_t) * n);
-        C.PB.vals[1] = (int32_t *)ensure(ws.vals1, sizeof(int32_t) * n);
-        C.PB.hist = (uint32_t *)ensure(ws.hist, sizeof(uint32_t) * 256 * nb);
-        C.PB.part = (uint32_t *)ensure(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
-        C.PB.rowid = (int32_t *)ensure(ws.rowid, sizeof(int32_t) * (n > 0 ? n : 1));
-        C.PB.vcode = n > SMALL_SORT ? (uint32_t *)ensure(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
+        C.PB.keys[0] = (uint64_t *)ws.buf(ws.keys0, sizeof(uint64_t) * n);
+        C.PB.keys[1] = (uint64_t *)ws.buf(ws.keys1, sizeof(uint64_t) * n);
+        C.PB.vals[0] = (int32_t *)ws.buf(ws.vals0, sizeof(int32_t) * n);
+        C.PB.vals[1] = (int32_t *)ws.buf(ws.vals1, sizeof(int32_t) * n);
+        C.PB.hist = (uint32_t *)ws.buf(ws.hist, sizeof(uint32_t) * 256 * nb);
+        C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
+        C.PB.rowid = (int32_t *)ws.buf(ws.rowid, sizeof(int32_t) * (n > 0 ? n : 1));
+        C.PB.vcode = n > SMALL_SORT ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
                                     : nullptr;
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;
     Q.blkA = ds + 7 * G1;
     Q.chkB = ds + 8 * G1;
-    Q.gA = (GroupBox *)ensure(ws.grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
-    Q.gB = (GroupBox *)ensure(ws.grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
-    Q.wi_lb = (float *)ensure(ws.wi_lb, sizeof(float) * (P.wi[G] + 1));
-    Q.wlist = (int32_t *)ensure(ws.wlist, sizeof(int32_t) * (P.wi[G] + 1));
-    C.rows = (RowState *)ensure(ws.rows, sizeof(RowState) * (G > 0 ? G : 1));
+    Q.gA = (GroupBox *)ws.buf(ws.grpA, sizeof(GroupBox) * (P.blkA[G] + 1));
+    Q.gB = (GroupBox *)ws.buf(ws.grpB, sizeof(GroupBox) * (P.chkB[G] + 1));
+    Q.wi_lb = (float *)ws.buf(ws.wi_lb, sizeof(float) * (P.wi[G] + 1));
+    Q.wlist = (int32_t *)ws.buf(ws.wlist, sizeof(int32_t) * (P.wi[G] + 1));
+    C.rows = (RowState *)ws.buf(ws.rows, sizeof(RowState) * (G > 0 ? G : 1));
 
     Lists &L = C.L;
-    const int64_t budget = opts.queue_cap > 0 ? std::max<int64_t>(opts.queue_cap, QUEUE_MIN) : QUEUE_BUDGET;
+    const int64_t budget = opts.queue_cap > 0 ? std::min<int64_t>(std::max<int64_t>(opts.queue_cap, QUEUE_MIN),
+                                                                  ws.queue_budget)
+                                              : ws.queue_budget;
     unsigned int qcap = (unsigned int)std::min<int64_t>(std::max<int64_t>(P.potential, 1), budget);
-    L.queue = (int2 *)ensure(ws.queue, sizeof(int2) * qcap);
-    L.qlb = (float *)ensure(ws.qlb, sizeof(float) * qcap);
+    L.queue = (int2 *)ws.buf(ws.queue, sizeof(int2) * qcap);
+    L.qlb = (float *)ws.buf(ws.qlb, sizeof(float) * qcap);
     L.qcap = qcap;
-    L.rescue = (Rescue *)ensure(ws.rescue, sizeof(Rescue) * RESCUE_CAP);
-    L.rcap = RESCUE_CAP;
-    L.exact = (ExactItem *)ensure(ws.exact, sizeof(ExactItem) * EXACT_CAP);
-    L.xcap = EXACT_CAP;
-    unsigned int *sc = (unsigned int *)ensure(ws.scalars, SCALAR_BYTES);
+    // work-list capacities: the workspace's, or smaller ones from the options
+    // (an exact list that overflowed is enlarged through them on a re-run)
+    const int64_t xmax = ws.arena ? (int64_t)NOALLOC_EXACT : (int64_t)EXACT_CAP_MAX;
+    L.rcap = opts.rescue_cap > 0 ? (unsigned int)std::min<int64_t>(opts.rescue_cap, ws.rescue_cap) : ws.rescue_cap;
+    L.xcap = (unsigned int)std::min<int64_t>(opts.exact_cap > 0 ? opts.exact_cap : ws.exact_cap, xmax);
+    L.rescue = (Rescue *)ws.buf(ws.rescue, sizeof(Rescue) * L.rcap);
+    L.exact = (ExactItem *)ws.buf(ws.exact, sizeof(ExactItem) * L.xcap);
+    unsigned int *sc = (unsigned int *)ws.buf(ws.scalars, SCALAR_BYTES);
     C.sc = sc;
     C.flags = sc + 12;
     L.qcount = sc;
@@ -472,10 +518,14 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.dd = dist;
         C.hd = hit;
     } else {
-        char *ob = (char *)ensure(ws.out_d, (sizeof(double) + 8) * (G > 0 ? G : 1));
+        char *ob = (char *)ws.buf(ws.out_d, (sizeof(double) + 8) * (G > 0 ? G : 1));
         C.dd = dist ? (double *)ob : nullptr;
         C.hd = hit ? (uint8_t *)(ob + sizeof(double) * G) : nullptr;
     }
+    // every buffer is placed: stage the offsets (a static scratch too small
+    // for the call stops here, before anything is copied or launched)
+    if (ws.arena_full) throw ScratchFull{ws.arena_used};
+    check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
 }
 
 // Device validation (flags in the scalar block) fused with the row boxes: the
@@ -582,6 +632,7 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->sort_passes = (K.bits() + 7) / 8;
     stats->tile = C.P.tk;
     stats->queue_passes = C.passes;
+    stats->queue_skew = (int64_t)cnt_h[C_SKEW];
 }
 
 sd3_status device_error(sd3_ctx *ctx, const HipError &e) {
@@ -590,22 +641,45 @@ sd3_status device_error(sd3_ctx *ctx, const HipError &e) {
     return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
 }
 
-sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist, uint8_t *hit,
-               const sd3_opts *opts_in, sd3_stats *stats, void *stream, int mode) {
+// What a finished call's scalars say about its work lists.
+enum Overflow { OVF_NONE = 0, OVF_RESCUE = 1, OVF_EXACT = 2, OVF_OTHER = 3 };
+Overflow overflow_kind(const Call &C, const unsigned int *sc_h, const unsigned long long *cnt_h) {
+    if (sc_h[0] > C.L.qcap || cnt_h[C_QUEUE_OVF] != 0) return OVF_OTHER;
+    if (sc_h[2] > C.L.rcap) return OVF_RESCUE;
+    if (sc_h[4] > C.L.xcap) return OVF_EXACT;
+    return OVF_NONE;
+}
+
+// One call on workspace `ws` (the context's own, or its static scratch).
+// When a work list overflows, the call is computed again instead of failing:
+// a full rescue list (FP32 pairs the bounds did not settle) by the plain FP64
+// pass, which needs no rescue list and gives the same bits; a full exact list
+// with a list four times longer (up to the workspace's limit).  `depth`
+// counts those re-runs.
+sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms *b, double *dist,
+               uint8_t *hit, const sd3_opts *opts_in, sd3_stats *stats, void *stream, int mode,
+               int depth = 0) {
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx) return SD3_E_INVALID_ARG;
     ctx->err.clear();
     sd3_opts opts;
     sd3_status st = check_call(ctx, a, b, dist, hit, opts_in, mode, opts);
     if (st != SD3_OK) return st;
+    const bool stat = ws.arena != nullptr;
     const int tk = choose_tile(ctx, opts, mode, a, b);
     hipStream_t s = (hipStream_t)stream;
+    Overflow ovf = OVF_NONE;
+    int64_t xcap_used = 0;
     try {
         check(hipSetDevice(ctx->device), "hipSetDevice");
         PhaseClock clk{ctx, s, opts.timing != 0};
         clk.mark(0);
         Call C;
-        plan_call(ctx, ctx->ws, a, b, opts, mode, tk, dist, hit, C, s);
+        if (stat) {
+            ws.arena_used = 0;
+            ws.arena_full = false;
+        }
+        plan_call(ctx, ws, a, b, opts, mode, tk, dist, hit, C, s);
         char *rb = readback_area(ctx);
         const unsigned int *sc_h = (const unsigned int *)rb;
         const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
@@ -635,43 +709,68 @@ sd3_status run(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dis
         check(hipMemcpyAsync(rb, C.sc, SCALAR_BYTES, hipMemcpyDeviceToHost, s), "D2H counters");
         check(hipStreamSynchronize(s), "sync");
         check(hipGetLastError(), "kernel launch");
-        st = call_status(ctx, C, sc_h, cnt_h);
+        st = flags_status(ctx, sc_h);
         if (st != SD3_OK) return st;
-        const int64_t G = C.P.G;
-        if (a->mem == SD3_MEM_HOST && G > 0) {
-            if (dist) check(hipMemcpyAsync(dist, C.dd, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H dist");
-            if (hit) check(hipMemcpyAsync(hit, C.hd, G, hipMemcpyDeviceToHost, s), "D2H hit");
-            clk.mark(7);
-            check(hipStreamSynchronize(s), "sync");
-        } else if (a->mem == SD3_MEM_HOST) {
-            clk.mark(7);
-            check(hipStreamSynchronize(s), "sync");
-        }
-        if (stats) {
-            fill_counts(C, sc_h, cnt_h, stats);
-            stats->ms_total =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            clk.read(stats->ms_phase);
-            if (kev)
-                for (int c = 0; c < KE_CLASSES; c++) {
-                    double ms = 0.0;
-                    for (int i = 0; i < std::min(kev->n[c], 16); i++) {
-                        float f = 0.0f;
-                        check(hipEventElapsedTime(&f, kev->ev[c][2 * i], kev->ev[c][2 * i + 1]), "elapsed");
-                        ms += f;
+        ovf = overflow_kind(C, sc_h, cnt_h);
+        xcap_used = C.L.xcap;
+        if (ovf == OVF_NONE) {
+            const int64_t G = C.P.G;
+            if (a->mem == SD3_MEM_HOST && G > 0) {
+                if (dist) check(hipMemcpyAsync(dist, C.dd, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H dist");
+                if (hit) check(hipMemcpyAsync(hit, C.hd, G, hipMemcpyDeviceToHost, s), "D2H hit");
+                clk.mark(7);
+                check(hipStreamSynchronize(s), "sync");
+            } else if (a->mem == SD3_MEM_HOST) {
+                clk.mark(7);
+                check(hipStreamSynchronize(s), "sync");
+            }
+            if (stats) {
+                fill_counts(C, sc_h, cnt_h, stats);
+                stats->fallback = depth;
+                stats->ms_total =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                clk.read(stats->ms_phase);
+                if (kev)
+                    for (int c = 0; c < KE_CLASSES; c++) {
+                        double ms = 0.0;
+                        for (int i = 0; i < std::min(kev->n[c], 16); i++) {
+                            float f = 0.0f;
+                            check(hipEventElapsedTime(&f, kev->ev[c][2 * i], kev->ev[c][2 * i + 1]), "elapsed");
+                            ms += f;
+                        }
+                        stats->ms_kernel[c] = ms;
+                        stats->n_kernel[c] = std::min(kev->n[c], 16);
                     }
-                    stats->ms_kernel[c] = ms;
-                    stats->n_kernel[c] = std::min(kev->n[c], 16);
-                }
+            }
+            return SD3_OK;
         }
     } catch (const HipError &e) {
         return device_error(ctx, e);
+    } catch (const ScratchFull &f) {
+        return fail(ctx, SD3_E_CAPACITY, "the call needs " + std::to_string(f.need) +
+                                             " bytes of static scratch; the limit is " +
+                                             std::to_string(ws.arena_cap));
     } catch (const std::bad_alloc &) {
         return fail(ctx, SD3_E_NOMEM, "host allocation failed");
     } catch (...) {
         return fail(ctx, SD3_E_DEVICE, "unexpected error");
     }
-    return SD3_OK;
+    // a work list overflowed: compute the call again (the outputs are untouched)
+    sd3_opts again = opts;
+    if (ovf == OVF_RESCUE && opts.precision == SD3_PREC_FP32_RESCUE && depth < 4) {
+        again.precision = SD3_PREC_FP64;
+        again.tile = tk;
+        return run(ctx, ws, a, b, dist, hit, &again, stats, stream, mode, depth + 1);
+    }
+    const int64_t xmax = stat ? (int64_t)NOALLOC_EXACT : (int64_t)EXACT_CAP_MAX;
+    if (ovf == OVF_EXACT && xcap_used < xmax && depth < 8) {
+        again.exact_cap = std::min<int64_t>(xcap_used * 4, xmax);
+        again.tile = tk;
+        return run(ctx, ws, a, b, dist, hit, &again, stats, stream, mode, depth + 1);
+    }
+    return fail(ctx, SD3_E_CAPACITY, ovf == OVF_RESCUE  ? "rescue list overflow"
+                                     : ovf == OVF_EXACT ? "exact list overflow"
+                                                        : "tile-pair queue overflow");
 }
 
 }  // namespace
@@ -770,12 +869,212 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
 
 sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
                         uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream) {
-    return run(ctx, a, b, dist, hit, opts, stats, stream, 0);
+    return ctx ? run(ctx, ctx->ws, a, b, dist, hit, opts, stats, stream, 0) : SD3_E_INVALID_ARG;
 }
 
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
                           const sd3_opts *opts, sd3_stats *stats, void *stream) {
-    return run(ctx, a, b, nullptr, hit, opts, stats, stream, 1);
+    return ctx ? run(ctx, ctx->ws, a, b, nullptr, hit, opts, stats, stream, 1) : SD3_E_INVALID_ARG;
+}
+
+sd3_status sd3_segments(sd3_ctx *ctx, int32_t op, const double *seg, int64_t n, int32_t seg_mem,
+                        const sd3_geoms *mesh, double r, double *dist, uint8_t *flag, sd3_stats *stats,
+                        void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx) return SD3_E_INVALID_ARG;
+    ctx->err.clear();
+    std::string msg;
+    sd3_status st = check_geoms(mesh, msg);
+    if (st != SD3_OK) return fail(ctx, st, msg);
+    if (mesh->count != 1) return fail(ctx, SD3_E_INVALID_ARG, "the mesh must be a batch of one row");
+    if (op != SD3_SEG_DISTANCE && op != SD3_SEG_INTERSECTS && op != SD3_SEG_WITHIN)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown segment operator");
+    if (n < 0 || (n > 0 && !seg)) return fail(ctx, SD3_E_INVALID_ARG, "segments are NULL or n < 0");
+    if (seg_mem != mesh->mem) return fail(ctx, SD3_E_INVALID_ARG, "segments and mesh differ in memory kind");
+    if ((op == SD3_SEG_DISTANCE && !dist) || (op != SD3_SEG_DISTANCE && !flag))
+        return fail(ctx, SD3_E_INVALID_ARG, "output pointer is NULL");
+    if (op == SD3_SEG_WITHIN && !(r >= 0.0 && r <= 1.7976931348623157e308))
+        return fail(ctx, SD3_E_INVALID_ARG, "r must be finite and >= 0");
+    const int64_t nv = mesh->v_off[1], nt = mesh->t_off[1];
+    if (nt >= ((int64_t)1 << 25)) return fail(ctx, SD3_E_INVALID_ARG, "mesh too large (at most 2^25 - 1 triangles)");
+    if (seg_mem == SD3_MEM_HOST) {
+        st = check_host_data(mesh, msg);
+        if (st != SD3_OK) return fail(ctx, st, msg);
+        for (int64_t i = 0; i < 6 * n; i++) {
+            const double x = std::fabs(seg[i]);
+            if (!(x <= 1.7976931348623157e308))
+                return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate in segment " + std::to_string(i / 6));
+            if (x != 0.0 && (x < 0x1p-256 || x > 0x1p256))
+                return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256] in segment " +
+                                                  std::to_string(i / 6));
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    const int mode = op == SD3_SEG_DISTANCE ? 0 : (op == SD3_SEG_INTERSECTS ? 1 : 2);
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        const double *dseg = seg;
+        const double *xyz = mesh->xyz;
+        const int32_t *tri = mesh->tri;
+        if (seg_mem == SD3_MEM_HOST) {
+            char *in = (char *)ensure(ws.seg_in, sizeof(double) * (6 * n + 3 * nv) + sizeof(int32_t) * 3 * nt + 64);
+            double *ds = (double *)in;
+            double *dx = ds + 6 * n;
+            int32_t *dt = (int32_t *)(dx + 3 * nv);
+            if (n) check(hipMemcpyAsync(ds, seg, sizeof(double) * 6 * n, hipMemcpyHostToDevice, s), "H2D segments");
+            if (nv) check(hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D mesh xyz");
+            if (nt) check(hipMemcpyAsync(dt, tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D mesh tri");
+            dseg = ds;
+            xyz = dx;
+            tri = dt;
+        }
+        const int64_t ntiles = (nt + SEG_MESH_TILE - 1) / SEG_MESH_TILE;
+        double *P = (double *)ensure(ws.seg_mesh, sizeof(double) * (SEG_MESH_FIELDS * nt + 6 * ntiles + 6) + 64);
+        double *tbox = P + SEG_MESH_FIELDS * nt;
+        double *mbox = tbox + 6 * ntiles;
+        unsigned int *sc = (unsigned int *)ensure(ws.scalars, SCALAR_BYTES);
+        uint32_t *flags = (uint32_t *)sc;
+        unsigned long long *cnt = (unsigned long long *)(sc + 16);
+        double *odist = dist;
+        uint8_t *oflag = flag;
+        if (seg_mem == SD3_MEM_HOST) {
+            char *o = (char *)ensure(ws.seg_out, (sizeof(double) + 1) * (n > 0 ? n : 1) + 64);
+            odist = dist ? (double *)o : nullptr;
+            oflag = flag ? (uint8_t *)(o + sizeof(double) * (n > 0 ? n : 1)) : nullptr;
+        }
+        launch_seg_validate(dseg, n, xyz, nv, tri, nt, flags, cnt, s);
+        ensure_pinned(ctx, 0);
+        char *rb = readback_area(ctx);
+        if (seg_mem == SD3_MEM_DEVICE) {
+            // device inputs are validated before any kernel reads them
+            check(hipMemcpyAsync(rb, sc, 64, hipMemcpyDeviceToHost, s), "D2H flags");
+            check(hipStreamSynchronize(s), "sync");
+            const uint32_t f = ((const uint32_t *)rb)[0] | ((const uint32_t *)rb)[1];
+            if (f & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
+            if (f & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
+            if (f & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside the mesh");
+        }
+        launch_seg_mesh(xyz, nv, tri, nt, P, tbox, mbox, s);
+        int &gp = ctx->seg_grid[mode];
+        if (gp == 0) gp = ctx->cus * seg_blocks_per_cu(mode);
+        launch_segs(mode, dseg, n, P, nt, tbox, mbox, r, mode == 0 ? odist : nullptr, oflag, flags, cnt, gp, s);
+        check(hipGetLastError(), "kernel launch");
+        check(hipMemcpyAsync(rb, sc, SCALAR_BYTES, hipMemcpyDeviceToHost, s), "D2H counters");
+        if (seg_mem == SD3_MEM_HOST && n > 0) {
+            if (dist) check(hipMemcpyAsync(dist, odist, sizeof(double) * n, hipMemcpyDeviceToHost, s), "D2H dist");
+            if (flag) check(hipMemcpyAsync(flag, oflag, n, hipMemcpyDeviceToHost, s), "D2H flags");
+        }
+        check(hipStreamSynchronize(s), "sync");
+        const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->tile_pairs_total = ntiles * ((n + 63) / 64);
+            stats->tri_pairs_boxed = (int64_t)cnt_h[0];
+            stats->tri_pairs_fp64 = (int64_t)cnt_h[1];
+            stats->exact = (int64_t)cnt_h[2];
+            stats->tile = SEG_MESH_TILE;
+            stats->ms_total =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    } catch (const HipError &e) {
+        return device_error(ctx, e);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, SD3_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, SD3_E_DEVICE, "unexpected error");
+    }
+    return SD3_OK;
+}
+
+sd3_status sd3_volume(sd3_ctx *ctx, const sd3_geoms *g, double *vol, sd3_stats *stats, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx) return SD3_E_INVALID_ARG;
+    ctx->err.clear();
+    std::string msg;
+    sd3_status st = check_geoms(g, msg);
+    if (st != SD3_OK) return fail(ctx, st, msg);
+    if (!vol) return fail(ctx, SD3_E_INVALID_ARG, "output pointer is NULL");
+    if (g->mem == SD3_MEM_HOST) {
+        st = check_host_data(g, msg);
+        if (st != SD3_OK) return fail(ctx, st, msg);
+    }
+    const int64_t G = g->count, nv = g->v_off[G], nt = g->t_off[G];
+    const int64_t CH = volume_chunk();
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    try {
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        // work items: (row, chunk) with the rows' offsets, staged in one copy:
+        // [v_off | t_off | item offsets (G+1) | first triangle of each item |
+        //  row of each item (int32)]
+        int64_t nitems = 0;
+        for (int64_t r = 0; r < G; r++) nitems += (g->t_off[r + 1] - g->t_off[r] + CH - 1) / CH;
+        const size_t bytes = sizeof(int64_t) * (3 * (G + 1) + nitems) + sizeof(int32_t) * (nitems + 1);
+        char *hs = ensure_pinned(ctx, bytes);
+        int64_t *h_voff = (int64_t *)hs, *h_toff = h_voff + (G + 1), *h_witem = h_toff + (G + 1);
+        int64_t *h_wfirst = h_witem + (G + 1);
+        int32_t *h_wrow = (int32_t *)(h_wfirst + nitems);
+        memcpy(h_voff, g->v_off, sizeof(int64_t) * (G + 1));
+        memcpy(h_toff, g->t_off, sizeof(int64_t) * (G + 1));
+        int64_t it = 0;
+        for (int64_t r = 0; r < G; r++) {
+            h_witem[r] = it;
+            for (int64_t t = g->t_off[r]; t < g->t_off[r + 1]; t += CH) {
+                h_wfirst[it] = t;
+                h_wrow[it] = (int32_t)r;
+                it++;
+            }
+        }
+        h_witem[G] = it;
+        char *ds = (char *)ensure(ws.vol_items, bytes + 64);
+        check(hipMemcpyAsync(ds, hs, bytes, hipMemcpyHostToDevice, s), "H2D volume items");
+        const int64_t *d_voff = (const int64_t *)ds, *d_toff = d_voff + (G + 1), *d_witem = d_toff + (G + 1);
+        const int64_t *d_wfirst = d_witem + (G + 1);
+        const int32_t *d_wrow = (const int32_t *)(d_wfirst + nitems);
+        const double *xyz = g->xyz;
+        const int32_t *tri = g->tri;
+        if (g->mem == SD3_MEM_HOST) {
+            SideState &sd = ws.side[0];
+            double *x = (double *)ensure(sd.xyz, sizeof(double) * 3 * nv);
+            int32_t *t = (int32_t *)ensure(sd.tri, sizeof(int32_t) * 3 * nt);
+            if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
+            if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
+            xyz = x;
+            tri = t;
+        }
+        void *part = ensure(ws.vol_part, 16 * (size_t)(nitems > 0 ? nitems : 1) + sizeof(double) * (G > 0 ? G : 1));
+        double *dvol = g->mem == SD3_MEM_HOST ? (double *)((char *)part + 16 * (size_t)(nitems > 0 ? nitems : 1))
+                                              : vol;
+        unsigned int *sc = (unsigned int *)ensure(ws.scalars, SCALAR_BYTES);
+        launch_volume(xyz, nv, tri, d_voff, d_toff, d_wrow, d_wfirst, nitems, d_witem, G, part, dvol,
+                      (uint32_t *)sc, ctx->cus * 8, s);
+        check(hipGetLastError(), "kernel launch");
+        char *rb = readback_area(ctx);
+        check(hipMemcpyAsync(rb, sc, 4, hipMemcpyDeviceToHost, s), "D2H flags");
+        check(hipStreamSynchronize(s), "sync");
+        const uint32_t f = *(const uint32_t *)rb;
+        if (f & V_NONFINITE) return fail(ctx, SD3_E_NONFINITE, "non-finite coordinate");
+        if (f & V_RANGE) return fail(ctx, SD3_E_RANGE, "coordinate magnitude outside [2^-256, 2^256]");
+        if (f & V_INDEX) return fail(ctx, SD3_E_INDEX_RANGE, "triangle index outside its row");
+        if (g->mem == SD3_MEM_HOST && G > 0) {
+            check(hipMemcpyAsync(vol, dvol, sizeof(double) * G, hipMemcpyDeviceToHost, s), "D2H volume");
+            check(hipStreamSynchronize(s), "sync");
+        }
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->sort_items = nt;
+            stats->ms_total =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    } catch (const HipError &e) {
+        return device_error(ctx, e);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, SD3_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, SD3_E_DEVICE, "unexpected error");
+    }
+    return SD3_OK;
 }
 
 sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd3_geoms *b,
@@ -933,7 +1232,7 @@ sd3_status sd3_autotune(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, const sd
         for (int c = 0; c < 3 && st == SD3_OK; c++) {
             opts.tile = cand[c];
             auto t0 = std::chrono::steady_clock::now();
-            st = run(ctx, a, b, mode == 0 ? dist : nullptr, hit, &opts, nullptr, stream, mode);
+            st = run(ctx, ctx->ws, a, b, mode == 0 ? dist : nullptr, hit, &opts, nullptr, stream, mode);
             auto t1 = std::chrono::steady_clock::now();
             if (r > 0) ms[c].push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
         }
@@ -964,6 +1263,17 @@ sd3_status sd3_mlp_forward(sd3_ctx *ctx, const float *params, const float *x, in
     return guarded(ctx, [&] {
         MlpScratch s = mlp_scratch(ctx, n);
         mlp_forward(params, x, n, s, y, (hipStream_t)stream);
+    });
+}
+
+sd3_status sd3_mlp_score(sd3_ctx *ctx, const float *params, const float *x, int64_t n, float *y,
+                         void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    if (!params || n < 0 || (n > 0 && (!x || !y))) return fail(ctx, SD3_E_INVALID_ARG, "bad MLP arguments");
+    return guarded(ctx, [&] {
+        const int64_t waves = (n + 3) / 4;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (int64_t)ctx->cus * 2));
+        launch_rank_score(params, x, n, y, grid, (hipStream_t)stream);
     });
 }
 

@@ -10,7 +10,7 @@ namespace sd3 {
 constexpr int TK_DEFAULT = 64;
 constexpr int TK_MAX = 128;
 __host__ __device__ constexpr bool tile_size_ok(int tk) { return tk == 32 || tk == 64 || tk == 128; }
-constexpr int WG = 256;  // threads per workgroup in the tile-pair kernels
+constexpr int WG = 256;  // threads per workgroup of the block-wide kernels
 
 constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
 constexpr double U32 = 5.9604644775390625e-08;  // 2^-24

@@ -71,6 +71,7 @@ enum Counter : int {
     C_RESCUE_OVF = 8,
     C_EXACT_OVF = 9,
     C_LOGGED = 10,
+    C_SKEW = 11,  // waves that found the block's queue entry changed under them
     C_NCOUNTERS = 16,
 };
 
@@ -165,6 +166,10 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
 // (weights `ranker`) and keeps each row's lowest score in the row state.
 void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
                  const float *ranker, int grid, hipStream_t s);
+// The learned seed round's scorer applied to feature rows x [n][MLP_IN] -> y [n]
+// (the device function k_rank uses).
+void launch_rank_score(const float *W, const float *x, int64_t n, float *y, int grid,
+                       hipStream_t s);
 int pairs_blocks_per_cu(int precision, int mode, int tk);
 void launch_pairs(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int precision,
                   int mode, int grid, hipStream_t s);
@@ -187,5 +192,30 @@ void launch_seed_reset(RowState *rows, int64_t G, unsigned int *seedhead, hipStr
 void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit, Lists &L,
                      const uint32_t *vflags, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);
+
+// Volume of each row (sd3_volume.hip): work items are (row, chunk of
+// volume_chunk() triangles); part holds 16 bytes per item; flags[0] takes the
+// validation bits.
+int volume_chunk();
+void launch_volume(const double *xyz, int64_t nv, const int32_t *tri, const int64_t *v_off,
+                   const int64_t *t_off, const int32_t *wrow, const int64_t *wfirst, int64_t nitems,
+                   const int64_t *witem, int64_t G, void *part, double *vol, uint32_t *flags, int grid,
+                   hipStream_t s);
+
+// Segments / points against one mesh (sd3_segments.hip).  Mesh preparation:
+// P [nt][36] FP64 triangles (30 derived fields, box), tile boxes [ceil(nt/64)][6]
+// and the mesh box mbox[6].  flags[0] (segments) and flags[1] (mesh) take the
+// validation bits; cnt[0..2]: box tests, full pair tests, exact tests.
+constexpr int SEG_MESH_TILE = 64;
+constexpr int SEG_MESH_FIELDS = 36;
+void launch_seg_validate(const double *seg, int64_t n, const double *xyz, int64_t nv, const int32_t *tri,
+                         int64_t nt, uint32_t *flags, unsigned long long *cnt, hipStream_t s);
+void launch_seg_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, double *P,
+                     double *tbox, double *mbox, hipStream_t s);
+int seg_blocks_per_cu(int mode);
+// mode 0: dist (+ hit if non-null), 1: hit = intersects, 2: hit = distance <= r
+void launch_segs(int mode, const double *seg, int64_t n, const double *P, int64_t nt, const double *tbox,
+                 const double *mbox, double r, double *dist, uint8_t *hit, const uint32_t *flags,
+                 unsigned long long *cnt, int grid, hipStream_t s);
 
 }  // namespace sd3

@@ -1426,163 +1426,12 @@ __device__ __forceinline__ bool overlap_boxes(const T (&alo)[3], const T (&ahi)[
     return keep;
 }
 
-constexpr int QB = 8;  // most queue entries a block claims per refill
-
-struct TPShared {
-    int2 be[QB];              // prefetched queue entries, their bounds and tiles
-    float blb[QB];
-    TileMeta bmA[QB], bmB[QB];
-    RowState brow[QB];        // the rows' state when the batch was gathered
-    TP32 bc[QB];              // per entry: FP32 constants (FP32 pass)
-    double bT2[QB];           // per entry: squared triangle-box cull threshold
-    unsigned bq0;             // queue index of be[0]
-    int bn, bi, qb;           // entries prefetched, next to take, entries per refill
-    int q, live, ta, tb, g, na, nb, logged;
-    float lbf;
-    double ub, m;
-    double ub_now;    // row upper bound + margin after this tile pair (rescue limit)
-    float T2f;        // FP32 triangle-box cull threshold (squared)
-    double T2d;       // FP64 triangle-box cull threshold (squared)
-    TP32 c;
-    unsigned int cnt;
-    unsigned int gcnt;  // surviving group pairs
-    float redf[4];
-    double redd[4];
-};
-
-// Wave 0 claims the next batch of up to S.qb queue entries (a block's first
-// batch is its static share, later ones come from the shared head) and
-// gathers the entries, their bounds and both tiles' metadata into LDS, one
-// lane per load.
-template <int PREC, int MODE>
-__device__ __forceinline__ void tp_refill(TPShared &S, const Lists &L, unsigned qcount,
-                                          const TileMeta *mA, const TileMeta *mB, RowState *rows,
-                                          bool first) {
-    const int lane = lane_id();
-    const unsigned qb = (unsigned)S.qb;
-    unsigned q0 = 0;
-    if (lane == 0) q0 = (first ? (unsigned)blockIdx.x : gridDim.x + atomicAdd(L.qhead, 1u)) * qb;
-    q0 = __shfl(q0, 0);
-    // an entry with e.x < 0 is a row without a seed choice (seed pass)
-    int ex = -1, ey = -1;
-    if ((unsigned)lane < qb && q0 + lane < qcount) {
-        unsigned q = q0 + lane;
-        bool have = true;
-        if (L.seed_pass) {
-            // seed pass: entry g is row g's chosen queue entry
-            const unsigned long long best = rows[q].best;
-            have = best != ~0ull;
-            q = (unsigned)(best & 0xffffffffu);
-            rows[q0 + lane].seed_q = have ? (int)q : -1;
-        }
-        int2 e = make_int2(-1, -1);
-        float lb = 0.0f;
-        if (have) {
-            e = L.queue[q];
-            lb = L.qlb[q];
-        }
-        ex = e.x;
-        ey = e.y;
-        S.be[lane] = e;
-        S.blb[lane] = lb;
-    }
-    const int k = lane >> 1;
-    const int tx = __shfl(ex, k), ty = __shfl(ey, k);
-    int row = 0;
-    if (lane < 2 * QB && (unsigned)k < qb && q0 + k < qcount && tx >= 0) {
-        if (lane & 1) {
-            S.bmB[k] = mB[ty];
-        } else {
-            S.bmA[k] = mA[tx];
-            row = S.bmA[k].row;
-        }
-    }
-    // the rows' state, one lane per entry (a stale upper bound is still an
-    // upper bound: it only prunes less)
-    const int rk = __shfl(row, 2 * (lane & (QB - 1)));
-    const bool own = lane < QB && (unsigned)lane < qb && q0 + lane < qcount && ex >= 0;
-    if (own) S.brow[lane] = rows[rk];
-    // each entry's tile-pair constants and (distance) cull threshold, one lane
-    // per entry (from the row state just gathered: the pop only copies them)
-    __builtin_amdgcn_wave_barrier();
-    if (own && (PREC == 0 || MODE == 0)) {
-        const TileMeta &a = S.bmA[lane], &b = S.bmB[lane];
-        const RowState &R = S.brow[lane];
-        const double ub = bits_to_double(R.ub), m = row_margin(R, ub);
-        if (PREC == 0) {
-            const TP32 c = tp32_consts(a, b);
-            S.bc[lane] = c;
-            if (MODE == 0) {
-                const double T = (ub + m + c.eps_c) / (1.0 - 4.0 * U32);
-                S.bT2[lane] = T * T * (1.0 + 16.0 * U32);
-            }
-        } else {
-            const double T = (ub + m) * (1.0 + 8.0 * U64);
-            S.bT2[lane] = T * T;
-        }
-    }
-    if (lane == 0) {
-        S.bq0 = q0;
-        S.bn = q0 < qcount ? (int)min(qb, qcount - q0) : 0;
-        S.bi = 0;
-    }
-}
-
-// Thread 0 takes the next prefetched tile pair, reads its row's state and
-// computes its constants; S.q = -1 once the block's batch is empty.
-__device__ __forceinline__ void tp_pop(TPShared &S, const Lists &L, RowState *rows, int precision,
-                                       int mode) {
-    S.live = 0;
-    S.cnt = 0;
-    S.gcnt = 0;
-    if (S.bi >= S.bn) {
-        S.q = -1;
-        return;
-    }
-    const int k = S.bi++;
-    const unsigned q = S.bq0 + (unsigned)k;
-    S.q = (int)q;
-    const int2 e = S.be[k];
-    if (e.x < 0) return;  // a row without a seed choice
-    const TileMeta &a = S.bmA[k];
-    const TileMeta &b = S.bmB[k];
-    const RowState *R = &S.brow[k];
-    double ub = bits_to_double(R->ub);
-    uint32_t hit = R->hit;
-    double m = row_margin(*R, ub);
-    S.ta = e.x;
-    S.tb = e.y;
-    S.g = a.row;
-    S.na = a.n;
-    S.nb = b.n;
-    S.ub = ub;
-    S.m = m;
-    S.lbf = S.blb[k];
-    S.logged = 0;
-    if (hit) return;
-    if (!L.seed_pass && (int)q == R->seed_q) return;  // already evaluated as the seed
-    if (mode == 0 && (double)S.lbf > ub + m) {
-        // pruned at dequeue: its box bound is the logged (lower-bound) outcome
-        if (L.log) {
-            log_tile_pair(L, a, b, R->scale, S.lbf, S.lbf, a.row);
-            S.logged = 1;
-        }
-        return;
-    }
-    S.live = 1;
-    if (precision == 0) S.c = S.bc[k];
-    if (mode == 0) {
-        const double T2 = S.bT2[k];
-        if (precision == 0) S.T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
-        else S.T2d = T2;
-    }
-}
-
 // Stage slot j of one tile into LDS: FP32 copies shifted by sh, or FP64.
 template <int TK>
-__device__ __forceinline__ void stage32(float *dst, const float *src_tile, const float *sh, int j) {
+__device__ __forceinline__ void stage32(float *dst, const float *src_tile, float sx, float sy,
+                                        float sz, int j) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j] + (sh ? sh[c % 3] : 0.0f);
+    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j] + (c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);
     tri_prep32(TriRef<float>{dst + j, TK});
 }
 
@@ -1598,18 +1447,6 @@ __device__ __forceinline__ void stage64(double *dst, const double *src_tile, int
         dst[(F_LO + k) * TK + j] = fmin(x0, fmin(x1, x2));
         dst[(F_HI + k) * TK + j] = fmax(x0, fmax(x1, x2));
     }
-}
-
-// Ballot-compacted append of (a | b << 8) to the LDS pair list (the upper 16
-// bits of an entry are filled later with the pair's lower bound).
-__device__ __forceinline__ void list_push(bool keep, int a, int b, uint32_t *list,
-                                          unsigned int *cnt) {
-    unsigned long long m = __ballot(keep);
-    if (m == 0) return;
-    unsigned int base = 0;
-    if (lane_id() == 0) base = atomicAdd(cnt, (unsigned int)__popcll(m));
-    base = __shfl(base, 0);
-    if (keep) list[base + __popcll(m & lanes_below())] = (uint32_t)(a | (b << 8));
 }
 
 // A lower bound rounded down to its upper 16 bits (negative bounds become 0:
@@ -1635,244 +1472,413 @@ __device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, un
     }
 }
 
-// FP32 variants whose LDS allows three blocks per CU are held to the
-// registers of three waves per SIMD.
+
+constexpr int QB = 8;       // most queue entries a wave claims at once
+constexpr int RING = 128;   // LDS ring of triangle pairs awaiting their test (two batches)
+constexpr int TLCAP = 256;  // FP32 pairs awaiting the rescue decision of their tile pair
+
+// Lane i's value in every lane (i wave-uniform): v_readlane into a scalar.
+__device__ __forceinline__ int rl_i(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ float rl_f(float v, int i) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+__device__ __forceinline__ double rl_d(double v, int i) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, i);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), i);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// LDS written by some lanes of a wave and read by others: the wave's LDS
+// operations complete in issue order, so keeping the compiler from moving
+// them across this point is all that is needed (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One claimed queue entry, held in the registers of the lane of its index in
+// the wave's batch: its tiles, row and counts, the row's state when the batch
+// was gathered (a stale upper bound is still an upper bound: it only prunes
+// less), the FP32 constants of the tile pair and its triangle-box cull
+// threshold.
+struct Entry {
+    int ta, tb, g, na, nb, seed_q, hit;
+    float lbf;
+    double ub, msc;  // row upper bound and margin scale
+    float sh0, sh1, sh2, eu, elb, eps_f, box_tol;
+    double T2;
+};
+
+// Gathers entry q0 + lane of the batch into lane `lane`'s registers (lanes at
+// and beyond the batch size keep ta = -1).  In the seed pass entry g is row
+// g's chosen queue entry.  Returns 1 in the lanes whose two tiles name
+// different rows (an inconsistency the caller counts; never expected).
+template <int PREC, int MODE>
+__device__ __forceinline__ int wave_gather(Entry &E, const Lists &L, unsigned qcount,
+                                           const TileMeta *mA, const TileMeta *mB,
+                                           RowState *rows, unsigned q0, unsigned qb) {
+    const int lane = lane_id();
+    E.ta = -1;
+    E.tb = -1;
+    E.hit = 0;
+    E.seed_q = -1;
+    int bad = 0;
+    if ((unsigned)lane < qb && q0 + lane < qcount) {
+        unsigned q = q0 + lane;
+        bool have = true;
+        if (L.seed_pass) {
+            const unsigned long long best = rows[q].best;
+            have = best != ~0ull;
+            q = (unsigned)(best & 0xffffffffu);
+            rows[q0 + lane].seed_q = have ? (int)q : -1;
+        }
+        if (have) {
+            const int2 e = L.queue[q];
+            const float lb = L.qlb[q];
+            const TileMeta a = mA[e.x], b = mB[e.y];
+            const RowState R = rows[a.row];
+            bad = a.row != b.row;
+            E.ta = e.x;
+            E.tb = e.y;
+            E.g = a.row;
+            E.na = a.n;
+            E.nb = b.n;
+            E.lbf = lb;
+            E.hit = (int)R.hit;
+            E.seed_q = R.seed_q;
+            const double ub = bits_to_double(R.ub), m = row_margin(R, ub);
+            E.ub = ub;
+            E.msc = R.margin_scale;
+            if (PREC == 0) {
+                const TP32 c = tp32_consts(a, b);
+                E.sh0 = c.sh[0];
+                E.sh1 = c.sh[1];
+                E.sh2 = c.sh[2];
+                E.eu = c.eu;
+                E.elb = c.elb;
+                E.eps_f = c.eps_f;
+                E.box_tol = c.box_tol;
+                if (MODE == 0) {
+                    const double T = (ub + m + c.eps_c) / (1.0 - 4.0 * U32);
+                    E.T2 = T * T * (1.0 + 16.0 * U32);
+                }
+            } else if (MODE == 0) {
+                const double T = (ub + m) * (1.0 + 8.0 * U64);
+                E.T2 = T * T;
+            }
+        }
+    }
+    return bad;
+}
+
+// Upper bound of the row distance from the smallest FP32 candidate dm of a
+// tile pair (see sd3_pair32.h), rounded up once more for the FP64 compare.
+__device__ __forceinline__ double fp32_upper(float dm, float eu) {
+    const double U = sqrt((double)dm) * (1.0 + 4.0 * U32) + (double)eu;
+    return U * (1.0 + 4.0 * U64);
+}
+
+// One wave per tile pair.  Each wave claims batches of up to QB queue
+// entries (its first batch is its static share, later ones come from the
+// shared head, claimed one batch ahead so the atomic's latency overlaps the
+// current batch), gathers them into its lanes' registers, and evaluates them
+// one by one: both tiles staged into the wave's own LDS (FP32 copies shifted
+// into the B tile's frame, or FP64), a cull of 8 x 8 slot-group boxes, then
+// of triangle boxes, with the surviving triangle pairs compacted by ballots
+// into an LDS ring and tested 64 at a time, one pair per lane.  Distance: the
+// wave reduces its minimum into the row bound with one atomic and rescues the
+// FP32 pairs whose certified lower bound does not exceed the row bound that
+// atomic returns (plus margin); intersects: certified hits set the row flag,
+// undecided pairs go to the rescue (FP32) or exact (FP64) list.  Nothing is
+// shared between waves but the queue head, the rows' state and the lists, so
+// there is no workgroup barrier.
 template <int PREC, int MODE, int TK>
-__global__ __launch_bounds__(256, PREC == 0 && TK <= 64 ? 3 : 1) void k_pairs(const float *t32A, const double *t64A,
-                                               const TileMeta *mA, const float *t32B,
-                                               const double *t64B, const TileMeta *mB,
-                                               RowState *rows, Lists L) {
+__global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t64A,
+                                              const TileMeta *mA, const float *t32B,
+                                              const double *t64B, const TileMeta *mB,
+                                              RowState *rows, Lists L) {
     static_assert(tile_size_ok(TK), "tile size");
     constexpr int NF = F_NTRI32;
-    // groups of 8 consecutive slots: group boxes are culled first, and only
-    // surviving group pairs are expanded to triangle pairs
     constexpr int NG = TK / 8, NGP = NG * NG;
+    constexpr bool TESTED_LIST = PREC == 0 && MODE == 0;
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
     __shared__ Tt sA[NF * TK];
     __shared__ Tt sB[NF * TK];
     __shared__ Tt gbox[2][NG][6];  // [side][group][lo xyz, hi xyz]
-    __shared__ uint32_t list[TK * TK];
     __shared__ uint32_t glist[NGP];
-    __shared__ TPShared S;
-    const int tid = threadIdx.x, w = tid >> 6;
+    __shared__ uint32_t ring[RING];
+    __shared__ uint32_t tl[TESTED_LIST ? TLCAP : 1];
+    const int lane = lane_id();
+    const unsigned long long below = lanes_below();
     const unsigned qcount = L.seed_pass ? (unsigned)L.nrows : min(*L.qcount, L.qcap);
-    unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0;
-    // entries per refill: 1 for short queues (every block starts at once), up
+    const unsigned nwave = gridDim.x;
+    // entries per claim: 1 for short queues (every wave starts at once), up
     // to QB for long ones (one atomic and one gather per batch)
-    if (tid == 0) {
-        S.qb = (int)max(1u, min((unsigned)QB, qcount / (gridDim.x * 4u)));
-        S.bi = 0;
-        S.bn = 0;
-    }
-    __syncthreads();
-    if ((unsigned)blockIdx.x * (unsigned)S.qb >= qcount) return;
-    bool first = true;
+    const unsigned qb = max(1u, min((unsigned)QB, qcount / (nwave * 4u)));
+    unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0, n_bad = 0;
+    unsigned claim = blockIdx.x;
     for (;;) {
-        if (S.bi >= S.bn) {  // block-uniform: written by thread 0 before the last barrier
-            if (w == 0) tp_refill<PREC, MODE>(S, L, qcount, mA, mB, rows, first);
-            first = false;
-            __syncthreads();
-        }
-        if (tid == 0) tp_pop(S, L, rows, PREC, MODE);
-        __syncthreads();
-        if (S.q < 0) break;
-        if (S.live) {
-            // threads [0, TK) stage A's slots, threads [128, 128 + TK) B's;
-            // each group of 8 consecutive staging lanes reduces its group box
-            {
-                const bool sa = tid < TK, sb = tid >= 128 && tid < 128 + TK;
-                if (sa) {
-                    if (PREC == 0) stage32<TK>((float *)sA, t32A + (int64_t)S.ta * 9 * TK, S.c.sh, tid);
-                    else stage64<TK>((double *)sA, t64A + (int64_t)S.ta * 9 * TK, tid);
-                } else if (sb) {
-                    if (PREC == 0) stage32<TK>((float *)sB, t32B + (int64_t)S.tb * 9 * TK, nullptr, tid - 128);
-                    else stage64<TK>((double *)sB, t64B + (int64_t)S.tb * 9 * TK, tid - 128);
+        const unsigned q0 = claim * qb;
+        if (q0 >= qcount) break;
+        Entry E;
+        n_bad += wave_gather<PREC, MODE>(E, L, qcount, mA, mB, rows, q0, qb);
+        unsigned nxt = 0;
+        if (lane == 0) nxt = nwave + atomicAdd(L.qhead, 1u);
+        const int bn = (int)min(qb, qcount - q0);
+        for (int i = 0; i < bn; i++) {
+            const int ta = rl_i(E.ta, i);
+            if (ta < 0) continue;  // a row without a seed choice
+            if (rl_i(E.hit, i)) continue;
+            if (!L.seed_pass && (int)(q0 + (unsigned)i) == rl_i(E.seed_q, i)) continue;  // seeded already
+            const int tb = rl_i(E.tb, i), g = rl_i(E.g, i);
+            const int na = rl_i(E.na, i), nb = rl_i(E.nb, i);
+            const float lbf = rl_f(E.lbf, i);
+            const double ub = rl_d(E.ub, i), msc = rl_d(E.msc, i);
+            const double m = msc + 1.4551915228366852e-11 * ub;  // row_margin
+            if (MODE == 0 && (double)lbf > ub + m) {
+                // pruned at dequeue: its box bound is the logged (lower-bound) outcome
+                if (L.log && lane == 0) log_tile_pair(L, mA[ta], mB[tb], rows[g].scale, lbf, lbf, g);
+                continue;
+            }
+            n_eval++;
+            float sh[3] = {0.0f, 0.0f, 0.0f}, eu = 0.0f, elb = 0.0f, eps_f = 0.0f, box_tol = 0.0f;
+            if (PREC == 0) {
+                sh[0] = rl_f(E.sh0, i);
+                sh[1] = rl_f(E.sh1, i);
+                sh[2] = rl_f(E.sh2, i);
+                eu = rl_f(E.eu, i);
+                elb = rl_f(E.elb, i);
+                eps_f = rl_f(E.eps_f, i);
+                box_tol = rl_f(E.box_tol, i);
+            }
+            float T2f = 0.0f;
+            double T2d = 0.0;
+            if (MODE == 0) {
+                const double T2 = rl_d(E.T2, i);
+                if (PREC == 0) T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
+                else T2d = T2;
+            }
+            // stage both tiles: slot s of [A slots | B slots], 64 at a time;
+            // each group of 8 consecutive slots (8 lanes) reduces its box
+#pragma unroll
+            for (int s0 = 0; s0 < 2 * TK; s0 += 64) {
+                const int s = s0 + lane;
+                const bool onB = s >= TK;
+                const int j = onB ? s - TK : s;
+                Tt *dst = onB ? sB : sA;
+                if (PREC == 0)
+                    stage32<TK>((float *)dst, onB ? t32B + (int64_t)tb * 9 * TK : t32A + (int64_t)ta * 9 * TK,
+                                onB ? 0.0f : sh[0], onB ? 0.0f : sh[1], onB ? 0.0f : sh[2], j);
+                else
+                    stage64<TK>((double *)dst, onB ? t64B + (int64_t)tb * 9 * TK : t64A + (int64_t)ta * 9 * TK, j);
+                Tt bx[6];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    bx[k] = dst[(F_LO + k) * TK + j];
+                    bx[3 + k] = dst[(F_HI + k) * TK + j];
                 }
-                if (w == 0 || w == 2 || (TK == 128 && (w == 1 || w == 3))) {
-                    const Tt *src = tid < 128 ? sA : sB;
-                    const int j = tid & 127;
-                    Tt bx[6];
+#pragma unroll
+                for (int o = 1; o < 8; o <<= 1)
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        bx[k] = (sa || sb) ? src[(F_LO + k) * TK + j] : (Tt)0;
-                        bx[3 + k] = (sa || sb) ? src[(F_HI + k) * TK + j] : (Tt)0;
+                        bx[k] = fmin(bx[k], __shfl_xor(bx[k], o));
+                        bx[3 + k] = fmax(bx[3 + k], __shfl_xor(bx[3 + k], o));
                     }
+                if ((j & 7) == 0)
 #pragma unroll
-                    for (int o = 1; o < 8; o <<= 1)
-#pragma unroll
-                        for (int k = 0; k < 3; k++) {
-                            bx[k] = fmin(bx[k], __shfl_xor(bx[k], o));
-                            bx[3 + k] = fmax(bx[3 + k], __shfl_xor(bx[3 + k], o));
-                        }
-                    if ((sa || sb) && (j & 7) == 0)
-#pragma unroll
-                        for (int k = 0; k < 6; k++) gbox[sa ? 0 : 1][j >> 3][k] = bx[k];
-                }
+                    for (int k = 0; k < 6; k++) gbox[onB ? 1 : 0][j >> 3][k] = bx[k];
             }
-            __syncthreads();
-            // phase 1a: group-box pairs, compacted into glist
-            {
-                const int ga = tid / NG, gb = tid % NG;
-                bool keep = tid < NGP && ga * 8 < S.na && gb * 8 < S.nb;
+            wave_lds_sync();
+            // group-box pairs, compacted into glist
+            unsigned gcnt = 0;
+#pragma unroll
+            for (int p0 = 0; p0 < NGP; p0 += 64) {
+                const int p = p0 + lane, ga = p / NG, gb = p % NG;
+                bool keep = p < NGP && ga * 8 < na && gb * 8 < nb;
                 if (keep) {
                     const Tt alo[3] = {gbox[0][ga][0], gbox[0][ga][1], gbox[0][ga][2]};
                     const Tt ahi[3] = {gbox[0][ga][3], gbox[0][ga][4], gbox[0][ga][5]};
                     const Tt blo[3] = {gbox[1][gb][0], gbox[1][gb][1], gbox[1][gb][2]};
                     const Tt bhi[3] = {gbox[1][gb][3], gbox[1][gb][4], gbox[1][gb][5]};
                     if (MODE == 0) {
-                        Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
-                        if (PREC == 0) keep = (float)g2 <= S.T2f;
-                        else keep = (double)g2 <= S.T2d;
+                        const Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
+                        keep = PREC == 0 ? (float)g2 <= T2f : (double)g2 <= T2d;
                     } else {
-                        keep = overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)S.c.box_tol : (Tt)0);
+                        keep = overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)box_tol : (Tt)0);
                     }
                 }
-                if (tid < ((NGP + 63) & ~63)) list_push(keep, ga, gb, glist, &S.gcnt);
+                const unsigned long long mk = __ballot(keep);
+                if (keep) glist[gcnt + __popcll(mk & below)] = (uint32_t)(ga | (gb << 8));
+                gcnt += (unsigned)__popcll(mk);
             }
-            __syncthreads();
-            // phase 1b: one wave per surviving group pair, lane -> (a, b)
-            const unsigned gcnt = S.gcnt;
-            for (unsigned gi = w; gi < gcnt; gi += 4) {
-                const uint32_t ge = glist[gi];
-                const int a = (int)(ge & 255) * 8 + (lane_id() >> 3);
-                const int b = (int)((ge >> 8) & 255) * 8 + (lane_id() & 7);
-                bool keep = a < S.na && b < S.nb;
-                const Tt alo[3] = {sA[F_LO * TK + a], sA[(F_LO + 1) * TK + a], sA[(F_LO + 2) * TK + a]};
-                const Tt ahi[3] = {sA[F_HI * TK + a], sA[(F_HI + 1) * TK + a], sA[(F_HI + 2) * TK + a]};
-                const Tt blo[3] = {sB[F_LO * TK + b], sB[(F_LO + 1) * TK + b], sB[(F_LO + 2) * TK + b]};
-                const Tt bhi[3] = {sB[F_HI * TK + b], sB[(F_HI + 1) * TK + b], sB[(F_HI + 2) * TK + b]};
-                if (MODE == 0) {
-                    Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
-                    if (PREC == 0) keep = keep && (float)g2 <= S.T2f;
-                    else keep = keep && (double)g2 <= S.T2d;
-                } else {
-                    keep = keep && overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)S.c.box_tol : (Tt)0);
-                }
-                list_push(keep, a, b, list, &S.cnt);
-            }
-            __syncthreads();
-            const unsigned cnt = S.cnt;
-            n_eval += tid == 0;
-            n_boxed += tid == 0 ? (unsigned long long)NGP + 64ull * gcnt : 0;
-            n_tested += tid == 0 ? cnt : 0;
-            // phase 2: full tests of the surviving pairs
+            wave_lds_sync();
+            n_boxed += (unsigned long long)NGP + 64ull * gcnt;
+            // the pairs of each surviving group pair (lane -> (a, b)) through
+            // their triangle-box test into the ring; full batches of 64 are
+            // tested at once
             Tt tmin = (Tt)__builtin_inf();
-            for (unsigned k = tid; k < cnt; k += 256) {
-                int a = list[k] & 255, b = (list[k] >> 8) & 255;
+            unsigned rc = 0, rd = 0, tc = 0;
+            auto test_batch = [&](unsigned n) __attribute__((always_inline)) {
+                const bool on = (unsigned)lane < n;
+                uint32_t e = on ? ring[(rd + lane) & (RING - 1)] : 0u;
+                const int a = e & 255, b = (e >> 8) & 255;
                 if (PREC == 0) {
                     TriRef<float> TA{(float *)sA + a, TK}, TB{(float *)sB + b, TK};
                     if (MODE == 0) {
-                        // the rescue decision waits for this tile pair's own
-                        // upper bound (below): keep the lower bound
-                        Pair32 r = pair32(TA, TB, S.c.elb);
-                        tmin = fmin(tmin, (Tt)r.d2);
-                        list[k] = (uint32_t)(a | (b << 8)) | (lb_down16(r.lb) << 16);
+                        uint32_t te = 0;
+                        if (on) {
+                            const Pair32 r = pair32(TA, TB, elb);
+                            tmin = fmin(tmin, (Tt)r.d2);
+                            te = (uint32_t)(a | (b << 8)) | (lb_down16(r.lb) << 16);
+                        }
+                        if (tc + n > (unsigned)TLCAP) {
+                            // the tested list is full: decide its pairs now
+                            // against the row bound at dequeue lowered by this
+                            // tile pair's own minimum so far (a larger limit
+                            // than the final one: it only rescues more)
+                            const float dm = wave_min((float)tmin);
+                            const double lim0 = dm < __builtin_inff() ? fmin(ub, fp32_upper(dm, eu)) : ub;
+                            const double lim = lim0 + msc + 1.4551915228366852e-11 * lim0;
+                            wave_lds_sync();
+                            for (unsigned k = lane; k < tc; k += 64) {
+                                const uint32_t x = tl[k];
+                                const float lb = __uint_as_float((x >> 16) << 16);
+                                const bool resc = (double)lb <= lim;
+                                Rescue it{ta, tb, (uint32_t)((x & 255) | (((x >> 8) & 255) << 16)), lb};
+                                global_push(resc, it, L.rescue, L.rcount, L.rcap);
+                                n_resc += resc;
+                            }
+                            tc = 0;
+                            wave_lds_sync();
+                        }
+                        if (on) tl[tc + lane] = te;
+                        tc += n;
                     } else {
-                        int c = isect32(TA, TB, S.c.eps_f);
-                        // not settled by planes and crossings: a certified
-                        // separating plane along the closest direction still
-                        // proves the pair disjoint
-                        if (c == 2 && pair32(TA, TB, S.c.elb).lb > 0.0f) c = 0;
-                        if (c == 1) atomicOr(&rows[S.g].hit, 1u);
-                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0.0f};
+                        int c = 0;
+                        if (on) {
+                            c = isect32(TA, TB, eps_f);
+                            // not settled by planes and crossings: a certified
+                            // separating plane along the closest direction
+                            // still proves the pair disjoint
+                            if (c == 2 && pair32(TA, TB, elb).lb > 0.0f) c = 0;
+                        }
+                        if (__ballot(c == 1) && lane == 0) atomicOr(&rows[g].hit, 1u);
+                        Rescue it{ta, tb, (uint32_t)(a | (b << 16)), 0.0f};
                         global_push(c == 2, it, L.rescue, L.rcount, L.rcap);
                         n_resc += c == 2;
                     }
                 } else {
                     TriRef<double> TA{(double *)sA + a, TK}, TB{(double *)sB + b, TK};
-                    // distance and intersects both use the full FP64 pair
-                    // test: its separating-plane certificate settles the
-                    // disjoint pairs whose orientation signs are exact zeros
-                    Pair64 r = pair64(TA, TB);
-                    int st = r.status;
-                    double d2 = r.d2;
-                    if (MODE == 0) tmin = fmin(tmin, (Tt)r.d2);
-                    if (st == 1) atomicOr(&rows[S.g].hit, 1u);
-                    ExactItem it{S.ta, S.tb, (uint32_t)(a | (b << 16)), 0, d2};
+                    // distance and intersects both use the full FP64 pair test:
+                    // its separating-plane certificate settles the disjoint
+                    // pairs whose orientation signs are exact zeros
+                    int st = 0;
+                    double d2 = 0.0;
+                    if (on) {
+                        const Pair64 r = pair64(TA, TB);
+                        st = r.status;
+                        d2 = r.d2;
+                        if (MODE == 0) tmin = fmin(tmin, (Tt)r.d2);
+                    }
+                    if (__ballot(st == 1) && lane == 0) atomicOr(&rows[g].hit, 1u);
+                    ExactItem it{ta, tb, (uint32_t)(a | (b << 16)), 0, d2};
                     global_push(st == 2, it, L.exact, L.xcount, L.xcap);
                     n_exact += st == 2;
                 }
+                rd += n;
+            };
+            for (unsigned gi = 0; gi < gcnt; gi++) {
+                const uint32_t ge = glist[gi];
+                const int a = (int)(ge & 255) * 8 + (lane >> 3);
+                const int b = (int)((ge >> 8) & 255) * 8 + (lane & 7);
+                bool keep = a < na && b < nb;
+                const Tt alo[3] = {sA[F_LO * TK + a], sA[(F_LO + 1) * TK + a], sA[(F_LO + 2) * TK + a]};
+                const Tt ahi[3] = {sA[F_HI * TK + a], sA[(F_HI + 1) * TK + a], sA[(F_HI + 2) * TK + a]};
+                const Tt blo[3] = {sB[F_LO * TK + b], sB[(F_LO + 1) * TK + b], sB[(F_LO + 2) * TK + b]};
+                const Tt bhi[3] = {sB[F_HI * TK + b], sB[(F_HI + 1) * TK + b], sB[(F_HI + 2) * TK + b]};
+                if (MODE == 0) {
+                    const Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
+                    keep = keep && (PREC == 0 ? (float)g2 <= T2f : (double)g2 <= T2d);
+                } else {
+                    keep = keep && overlap_boxes(alo, ahi, blo, bhi, PREC == 0 ? (Tt)box_tol : (Tt)0);
+                }
+                const unsigned long long mk = __ballot(keep);
+                if (keep) ring[(rc + __popcll(mk & below)) & (RING - 1)] = (uint32_t)(a | (b << 8));
+                rc += (unsigned)__popcll(mk);
+                if (rc - rd >= 64) {
+                    wave_lds_sync();
+                    test_batch(64);
+                }
             }
+            if (rc > rd) {
+                wave_lds_sync();
+                test_batch(rc - rd);
+            }
+            n_tested += rc;
             if (MODE == 0) {
-                tmin = wave_min(tmin);
-                if (lane_id() == 0) {
-                    if (PREC == 0) S.redf[w] = (float)tmin;
-                    else S.redd[w] = (double)tmin;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    RowState *R = rows + S.g;
-                    if (PREC == 0) {
-                        float dm = fminf(fminf(S.redf[0], S.redf[1]), fminf(S.redf[2], S.redf[3]));
-                        // the row's upper bound now (this tile pair's and every
-                        // earlier result, from the atomic's return value): only
-                        // pairs that may still beat it are rescued; with no pair
-                        // tested there is nothing to rescue
-                        double ub_now = S.ub;
-                        if (dm < __builtin_inff()) {
-                            double U = sqrt((double)dm) * (1.0 + 4.0 * U32) + (double)S.c.eu;
-                            unsigned long long mine = double_to_bits(U * (1.0 + 4.0 * U64));
-                            unsigned long long prev = atomicMin(&R->ub, mine);
-                            ub_now = bits_to_double(prev < mine ? prev : mine);
-                        }
-                        S.ub_now = ub_now + row_margin(*R, ub_now);
-                    } else {
-                        double dm = fmin(fmin(S.redd[0], S.redd[1]), fmin(S.redd[2], S.redd[3]));
-                        if (dm < __builtin_inf()) {
-                            atomic_min_pos(&R->d2, dm);
-                            atomic_min_pos(&R->ub, sqrt(dm));
-                        }
-                    }
-                    if (L.log) {
-                        // smallest tested candidate distance, else the cull
-                        // threshold (every untested pair lies beyond it)
-                        double dm = PREC == 0 ? (double)fminf(fminf(S.redf[0], S.redf[1]),
-                                                              fminf(S.redf[2], S.redf[3]))
-                                              : fmin(fmin(S.redd[0], S.redd[1]),
-                                                     fmin(S.redd[2], S.redd[3]));
-                        double T2 = PREC == 0 ? (double)S.T2f : S.T2d;
-                        double out = sqrt(fmin(dm, T2));
-                        log_tile_pair(L, mA[S.ta], mB[S.tb], R->scale, S.lbf, out, S.g);
-                    }
-                }
+                const Tt dm = wave_min(tmin);
                 if (PREC == 0) {
-                    // phase 3: rescue the pairs whose lower bound does not
-                    // exceed the row's upper bound plus margin
-                    __syncthreads();
-                    const double lim = S.ub_now;
-                    for (unsigned k = tid; k < cnt; k += 256) {
-                        uint32_t e = list[k];
-                        float lb = __uint_as_float((e >> 16) << 16);
-                        bool resc = (double)lb <= lim;
-                        int a = e & 255, b = (e >> 8) & 255;
-                        Rescue it{S.ta, S.tb, (uint32_t)(a | (b << 16)), lb};
+                    // the row's upper bound now (this tile pair's and every
+                    // earlier result, from the atomic's return value): only
+                    // pairs that may still beat it are rescued; with no pair
+                    // tested there is nothing to rescue
+                    double ub_now = ub;
+                    if ((float)dm < __builtin_inff()) {
+                        const double U = fp32_upper((float)dm, eu);
+                        const unsigned long long mine = double_to_bits(U);
+                        unsigned long long prev = 0;
+                        if (lane == 0) prev = atomicMin(&rows[g].ub, mine);
+                        prev = (unsigned long long)rl_d(__longlong_as_double((long long)prev), 0) ;
+                        ub_now = bits_to_double(prev < mine ? prev : mine);
+                    }
+                    const double lim = ub_now + msc + 1.4551915228366852e-11 * ub_now;
+                    wave_lds_sync();
+                    for (unsigned k = lane; k < tc; k += 64) {
+                        const uint32_t x = tl[k];
+                        const float lb = __uint_as_float((x >> 16) << 16);
+                        const bool resc = (double)lb <= lim;
+                        Rescue it{ta, tb, (uint32_t)((x & 255) | (((x >> 8) & 255) << 16)), lb};
                         global_push(resc, it, L.rescue, L.rcount, L.rcap);
                         n_resc += resc;
                     }
+                } else if (lane == 0 && (double)dm < __builtin_inf()) {
+                    atomic_min_pos(&rows[g].d2, (double)dm);
+                    atomic_min_pos(&rows[g].ub, sqrt((double)dm));
+                }
+                if (L.log && lane == 0) {
+                    // smallest tested candidate distance, else the cull
+                    // threshold (every untested pair lies beyond it)
+                    const double T2 = PREC == 0 ? (double)T2f : T2d;
+                    const double out = sqrt(fmin((double)dm, T2));
+                    log_tile_pair(L, mA[ta], mB[tb], rows[g].scale, lbf, out, g);
                 }
             }
+            wave_lds_sync();  // LDS reads of this tile pair before the next staging
         }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        atomicAdd(&L.counters[C_TP_EVAL], n_eval);
-        atomicAdd(&L.counters[C_TRI_BOXED], n_boxed);
-        atomicAdd(&L.counters[PREC == 0 ? C_TRI32 : C_TRI64], n_tested);
+        claim = (unsigned)__builtin_amdgcn_readfirstlane((int)nxt);
     }
     n_resc = wave_sum(n_resc);
     n_exact = wave_sum(n_exact);
-    if (lane_id() == 0) {
+    n_bad = wave_sum(n_bad);
+    if (lane == 0) {
+        if (n_eval) atomicAdd(&L.counters[C_TP_EVAL], n_eval);
+        if (n_boxed) atomicAdd(&L.counters[C_TRI_BOXED], n_boxed);
+        if (n_tested) atomicAdd(&L.counters[PREC == 0 ? C_TRI32 : C_TRI64], n_tested);
         if (n_resc) atomicAdd(&L.counters[C_RESCUED], n_resc);
         if (n_exact) atomicAdd(&L.counters[C_EXACT], n_exact);
+        if (n_bad) atomicAdd(&L.counters[C_SKEW], n_bad);
     }
 }
+
 
 template <int P, int M>
 static int occupancy_tk(int tk) {
     int n = 0;
-    hipError_t e = tk == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 32>, WG, 0)
-                   : tk == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 64>, WG, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 128>, WG, 0);
+    hipError_t e = tk == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 32>, 64, 0)
+                   : tk == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 64>, 64, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<P, M, 128>, 64, 0);
     return e == hipSuccess && n >= 1 ? n : 1;
 }
 
@@ -1885,7 +1891,7 @@ template <int P, int M>
 static void launch_pairs_tk(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L, int grid,
                             hipStream_t s) {
 #define SD3_LAUNCH_PAIRS(T)                                                                          \
-    hipLaunchKernelGGL((k_pairs<P, M, T>), dim3(grid), dim3(WG), 0, s, A.t32, A.t64, A.meta, B.t32, \
+    hipLaunchKernelGGL((k_pairs<P, M, T>), dim3(grid), dim3(64), 0, s, A.t32, A.t64, A.meta, B.t32, \
                        B.t64, B.meta, rows, L)
     if (A.tk == 32) SD3_LAUNCH_PAIRS(32);
     else if (A.tk == 64) SD3_LAUNCH_PAIRS(64);
@@ -2258,6 +2264,30 @@ __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta
 void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
                  const float *ranker, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_rank, dim3(grid), dim3(256), 0, s, A.meta, B.meta, rows, L, ranker);
+}
+
+// The seed round's scorer on given feature rows (x: [n][MLP_IN]): the same
+// LDS weight layout and the same wave-wide evaluation as k_rank, one row per
+// wave iteration, so its outputs are exactly the scores k_rank ranks by.
+__global__ __launch_bounds__(256) void k_rank_score(const float *W, const float *x, int64_t n,
+                                                    float *y) {
+    __shared__ MlpLds M;
+    if ((int64_t)blockIdx.x * 4 >= n) return;
+    mlp_stage(M, W);
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += nw) {
+        float f[MLP_IN];
+        for (int k = 0; k < MLP_IN; k++) f[k] = x[i * MLP_IN + k];
+        const float sc = mlp_wave_score(M, f);
+        if (lane == 0) y[i] = sc;
+    }
+}
+
+void launch_rank_score(const float *W, const float *x, int64_t n, float *y, int grid,
+                       hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_rank_score, dim3(grid), dim3(256), 0, s, W, x, n, y);
 }
 
 // Before each later queue pass's filter: no row has a seed choice yet, and

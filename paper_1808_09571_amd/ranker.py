@@ -100,17 +100,42 @@ def load(path=WEIGHTS, device="cuda:0"):
 
 
 def training_pairs():
-    """Training workloads, disjoint from the benchmark's seeds: TIN pairs with
-    other noise seeds and clearances, and tube/blob rows."""
+    """TIN training workloads, disjoint from the benchmark's seeds: TIN pairs
+    with other noise seeds and clearances."""
     pairs = []
     for k, (gap, n) in enumerate([(0.01, 256), (0.05, 256), (0.002, 256), (0.01, 384)]):
         A, B = synth.config_tin_pair(n=n, extent=1000.0 * n / 512, gap=gap,
                                      seeds=(31 + 2 * k, 32 + 2 * k))
         pairs.append(([A], [B]))
-    A, B = synth.config_tube_blob_batch(rows=64, seed=101, tube_tri=(200, 4000),
-                                        blob_tri=(1000, 20000))
-    pairs.append((A, B))
     return pairs
+
+
+def batch_training_pairs(seed):
+    """One chunk of 128 rows of the drill-hole / ore-body batch distribution
+    (the benchmark's batch uses seed 3; training seeds start at 1000)."""
+    return synth.config_tube_blob_batch(rows=128, seed=seed)
+
+
+def collect_records(ctx, records, verbose=False):
+    """Logged (features, target) records from the TIN training pairs and from
+    batch-distribution chunks of seeds 1000, 1001, ... until ``records``
+    records are gathered.  Returns device tensors and the seeds used."""
+    import torch
+    xs, ts = [], []
+    X, t = collect(ctx, to_batches(training_pairs()))
+    xs.append(X)
+    ts.append(t)
+    n, seed = X.shape[0], 1000
+    while n < records:
+        A, B = batch_training_pairs(seed)
+        X, t = collect(ctx, to_batches([(A, B)]))
+        xs.append(X)
+        ts.append(t)
+        n += X.shape[0]
+        if verbose:
+            print(f"seed {seed}: {n} records", flush=True)
+        seed += 1
+    return torch.cat(xs), torch.cat(ts), list(range(1000, seed))
 
 
 def evaluate(ctx, ba, bb, params, precision="fp32"):
@@ -128,25 +153,33 @@ def evaluate(ctx, ba, bb, params, precision="fp32"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=WEIGHTS)
-    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--records", type=int, default=1_000_000,
+                    help="logged tile-pair outcomes to train on (TIN pairs + batch chunks)")
     ap.add_argument("--report", default=None, help="write a JSON summary here")
     args = ap.parse_args()
     ctx = sd3.Context(0)
     t0 = time.time()
-    X, t = collect(ctx, to_batches(training_pairs()))
+    X, t, seeds = collect_records(ctx, args.records, verbose=True)
     t1 = time.time()
     params, hist = train(ctx, X, t, steps=args.steps, verbose=True)
     t2 = time.time()
     save(params, args.out)
+    heldout = {}
+    same = True
     A, B = synth.config_tin_pair()
-    ba, bb = to_batches([([A], [B])])[0]
-    ev = evaluate(ctx, ba, bb, params)
-    same = all(np.array_equal(ev[o]["dist"].view(np.int64), ev["none"]["dist"].view(np.int64))
-               for o in ev)
-    summary = {"records": int(X.shape[0]), "collect_s": t1 - t0, "train_s": t2 - t1,
+    held = [("tin512_seeds_1_2", [A], [B]),
+            ("batch_seed3_rows_0_511",) + tuple(synth.config_tube_blob_batch(rows=512, seed=3))]
+    for name, HA, HB in held:
+        ba, bb = to_batches([(HA, HB)])[0]
+        ev = evaluate(ctx, ba, bb, params)
+        same = same and all(np.array_equal(ev[o]["dist"].view(np.int64), ev["none"]["dist"].view(np.int64))
+                            for o in ev)
+        heldout[name] = {o: ev[o]["tile_pairs_evaluated"] for o in ev}
+    summary = {"records": int(X.shape[0]), "batch_training_seeds": [seeds[0], seeds[-1]] if seeds else [],
+               "collect_s": t1 - t0, "train_s": t2 - t1, "steps": args.steps,
                "loss_first": hist[0][1], "loss_last": hist[-1][1],
-               "heldout_tin512": {o: ev[o]["tile_pairs_evaluated"] for o in ev},
-               "identical_results": bool(same)}
+               "heldout_tile_pairs_evaluated": heldout, "identical_results": bool(same)}
     print(json.dumps(summary), flush=True)
     if args.report:
         with open(args.report, "w") as f:

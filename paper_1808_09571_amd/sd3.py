@@ -30,12 +30,13 @@ STATUS = {
 }
 
 KIND = {"distance": 0, "intersects": 1}
+SEG_OP = {"distance": 0, "intersects": 1, "within": 2}
 TILES = (32, 64, 128)
 
 EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
            "sd3_graph_create", "sd3_graph_launch", "sd3_graph_result", "sd3_graph_destroy",
-           "sd3_autotune", "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step",
-           "sd3_validate", "sd3_status_string", "sd3_last_error"]
+           "sd3_autotune", "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step", "sd3_mlp_score",
+           "sd3_validate", "sd3_status_string", "sd3_last_error", "sd3_segments", "sd3_volume"]
 
 
 class Geoms(ctypes.Structure):
@@ -48,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("ranker", ctypes.c_void_p), ("log", ctypes.c_void_p),
                 ("log_cap", ctypes.c_int64), ("queue_cap", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 3)]
+                ("rescue_cap", ctypes.c_int64), ("exact_cap", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("logged", ctypes.c_int64), ("ms_kernel", ctypes.c_double * 4),
                 ("n_kernel", ctypes.c_int64 * 4), ("sort_items", ctypes.c_int64),
                 ("sort_key_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("queue_passes", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("queue_passes", ctypes.c_int32),
+                ("queue_skew", ctypes.c_int64), ("fallback", ctypes.c_int32),
+                ("reserved32", ctypes.c_int32)]
 
     KERNELS = ("scatter", "tiles", "filter", "pairs")
 
@@ -124,6 +128,8 @@ def load(path: str = LIB_PATH):
     vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
     lib.sd3_mlp_forward.argtypes = [vp, vp, vp, i64, vp, vp]
     lib.sd3_mlp_forward.restype = ctypes.c_int
+    lib.sd3_mlp_score.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.sd3_mlp_score.restype = ctypes.c_int
     lib.sd3_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     lib.sd3_mlp_loss_grad.restype = ctypes.c_int
     lib.sd3_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
@@ -140,6 +146,10 @@ def load(path: str = LIB_PATH):
     lib.sd3_graph_destroy.restype = ctypes.c_int
     lib.sd3_autotune.argtypes = [vp, i32, P(Geoms), P(Geoms), P(Opts), i32, P(TuneReport), vp]
     lib.sd3_autotune.restype = ctypes.c_int
+    lib.sd3_segments.argtypes = [vp, i32, vp, i64, i32, P(Geoms), ctypes.c_double, vp, vp, P(Stats), vp]
+    lib.sd3_segments.restype = ctypes.c_int
+    lib.sd3_volume.argtypes = [vp, P(Geoms), vp, P(Stats), vp]
+    lib.sd3_volume.restype = ctypes.c_int
     lib.sd3_status_string.argtypes = [ctypes.c_int]
     lib.sd3_status_string.restype = ctypes.c_char_p
     lib.sd3_last_error.argtypes = [ctypes.c_void_p]
@@ -218,13 +228,16 @@ class Context:
         raise SD3Error(st, self.lib.sd3_last_error(self.handle).decode())
 
     @staticmethod
-    def _opts(precision, order, timing=False, ranker=None, log=None, tile=0, queue_cap=0):
+    def _opts(precision, order, timing=False, ranker=None, log=None, tile=0, queue_cap=0,
+              rescue_cap=0, exact_cap=0):
         o = Opts()
         o.precision = PREC[precision]
         o.order = ORDER[order]
         o.timing = 1 if timing else 0
         o.tile = int(tile)
         o.queue_cap = int(queue_cap)
+        o.rescue_cap = int(rescue_cap)
+        o.exact_cap = int(exact_cap)
         if ranker is not None:
             assert ranker.is_cuda and ranker.dtype.itemsize == 4 and ranker.numel() == MLP_NPARAM
             o.ranker = ranker.data_ptr()
@@ -252,7 +265,8 @@ class Context:
         return d, h, (d.ctypes.data if want_dist else None), h.ctypes.data
 
     def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                 timing=False, ranker=None, log=None, tile=0, queue_cap=0):
+                 timing=False, ranker=None, log=None, tile=0, queue_cap=0, rescue_cap=0,
+                 exact_cap=0):
         """Row-wise 3D distance (and the exact intersects flag as a by-product).
         order="learned" needs ``ranker`` (float32 [MLP_NPARAM] on the device);
         ``log`` (float32 [cap, LOG_STRIDE] on the device) receives one training
@@ -261,7 +275,7 @@ class Context:
         ga, gb = a.geoms(), b.geoms()
         d, h, dp, hp = self._outputs(a, True)
         s = Stats()
-        o = self._opts(precision, order, timing, ranker, log, tile, queue_cap)
+        o = self._opts(precision, order, timing, ranker, log, tile, queue_cap, rescue_cap, exact_cap)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
@@ -269,18 +283,69 @@ class Context:
         return (d, h, s.as_dict()) if stats else (d, h)
 
     def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                   timing=False, tile=0, queue_cap=0):
+                   timing=False, tile=0, queue_cap=0, rescue_cap=0, exact_cap=0):
         """Row-wise exact 3D intersects."""
         ga, gb = a.geoms(), b.geoms()
         _, h, _, hp = self._outputs(a, False)
         s = Stats()
-        o = self._opts(precision, order, timing, tile=tile, queue_cap=queue_cap)
+        o = self._opts(precision, order, timing, tile=tile, queue_cap=queue_cap,
+                       rescue_cap=rescue_cap, exact_cap=exact_cap)
         st = self.lib.sd3_intersects(self.handle, ctypes.byref(ga), ctypes.byref(gb), hp,
                                      ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
             self._raise(st)
         return (h, s.as_dict()) if stats else h
 
+
+    def volume(self, g: Batch):
+        """Volume of each row (divergence theorem, double-double sums)."""
+        G = g.count
+        gg = g.geoms()
+        if g.on_device:
+            import torch
+            v = torch.empty(G, dtype=torch.float64, device=g.xyz.device)
+            vp_, stream = v.data_ptr(), ctypes.c_void_p(torch.cuda.current_stream(g.xyz.device).cuda_stream)
+        else:
+            v = np.empty(G, dtype=np.float64)
+            vp_, stream = v.ctypes.data, None
+        st = self.lib.sd3_volume(self.handle, ctypes.byref(gg), vp_, None, stream)
+        if st != 0:
+            self._raise(st)
+        return v
+
+    def segments(self, op, seg, mesh: Batch, r=0.0, stats=False):
+        """Segments (or points, P0 == P1) against one mesh (a Batch of one row).
+        ``seg``: float64 [n, 2, 3], a numpy array (host) or a torch tensor on the
+        mesh's device.  op "distance" returns (dist, hit), "intersects" and
+        "within" (distance <= r) return the flags."""
+        if mesh.count != 1:
+            raise ValueError("the mesh must be a batch of one row")
+        g = mesh.geoms()
+        if mesh.on_device:
+            import torch
+            assert seg.dtype == torch.float64 and seg.is_contiguous() and seg.device == mesh.xyz.device
+            n = int(seg.numel() // 6)
+            sp, mem = seg.data_ptr(), MEM_DEVICE
+            dev = mesh.xyz.device
+            d = torch.empty(n, dtype=torch.float64, device=dev)
+            f = torch.empty(n, dtype=torch.uint8, device=dev)
+            dp, fp = d.data_ptr(), f.data_ptr()
+            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        else:
+            seg = np.ascontiguousarray(seg, dtype=np.float64)
+            n = int(seg.size // 6)
+            sp, mem = seg.ctypes.data, MEM_HOST
+            d = np.empty(n, dtype=np.float64)
+            f = np.empty(n, dtype=np.uint8)
+            dp, fp = d.ctypes.data, f.ctypes.data
+            stream = None
+        st_ = Stats()
+        st = self.lib.sd3_segments(self.handle, SEG_OP[op], sp, n, mem, ctypes.byref(g), float(r),
+                                   dp if op == "distance" else None, fp, ctypes.byref(st_), stream)
+        if st != 0:
+            self._raise(st)
+        out = (d, f) if op == "distance" else f
+        return (out, st_.as_dict()) if stats else out
 
     def graph(self, kind, a: Batch, b: Batch, precision="fp32", order="bound", ranker=None,
               tile=0, queue_cap=0):
@@ -383,6 +448,17 @@ class Ranker:
         y = torch.empty(n, dtype=torch.float32, device=x.device)
         st = self.lib.sd3_mlp_forward(self.ctx.handle, _dev(params, MLP_NPARAM), _dev(x), n,
                                       _dev(y), self._stream(x))
+        if st != 0:
+            self.ctx._raise(st)
+        return y
+
+    def score(self, params, x):
+        """The learned seed round's in-kernel scorer on feature rows x."""
+        import torch
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        st = self.lib.sd3_mlp_score(self.ctx.handle, _dev(params, MLP_NPARAM), _dev(x), n,
+                                    _dev(y), self._stream(x))
         if st != 0:
             self.ctx._raise(st)
         return y

@@ -450,3 +450,36 @@ def config_tube_blob_batch(rows=4096, seed=3, tube_tri=(200, 20000),
         path = np.concatenate([bwd[::-1], fwd[1:]], axis=0)
         A.append(tube(path, radius=tube_radius))
     return A, B
+
+
+def drill_holes(n_holes, segs, seed, extent, top, step=(1.0, 3.0), turn=0.05):
+    """Drill holes as polylines of ``segs`` segments each (the segment workload
+    of Sec. 4): collars uniform over [-extent, extent]^2 at height top + U[0, 10],
+    initial direction downward with a dip of U[60, 90] degrees from the
+    horizontal and a uniform azimuth, each step of length U[step] after a small
+    random change of direction (Gaussian of deviation ``turn``, renormalised).
+    Returns the segments as a float64 array [n_holes * segs, 2, 3], hole by hole
+    (consecutive segments of a hole are adjacent)."""
+    g = rng(seed)
+    collar = np.c_[g.uniform(-extent, extent, size=(n_holes, 2)), top + g.uniform(0.0, 10.0, n_holes)]
+    dip = np.radians(g.uniform(60.0, 90.0, n_holes))
+    az = g.uniform(0.0, 2.0 * math.pi, n_holes)
+    d = np.c_[np.cos(dip) * np.cos(az), np.cos(dip) * np.sin(az), -np.sin(dip)]
+    pts = np.empty((n_holes, segs + 1, 3), dtype=np.float64)
+    pts[:, 0] = collar
+    for s in range(segs):
+        d = d + g.normal(0.0, turn, size=(n_holes, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        pts[:, s + 1] = pts[:, s] + g.uniform(step[0], step[1], size=(n_holes, 1)) * d
+    return np.ascontiguousarray(np.stack([pts[:, :-1], pts[:, 1:]], axis=2).reshape(-1, 2, 3))
+
+
+def config_drillholes(holes=100_000, segs=50, seed=11, faces=500, radius=50.0):
+    """Segment workload of Sec. 4: ``holes`` x ``segs`` drill-hole segments (5 M by
+    default) against one ore body, a noisy closed blob of ``faces`` triangles
+    (frequency-5 geodesic sphere: 500 faces) of radius ``radius`` at the origin.
+    Collars cover [-1.5 R, 1.5 R]^2 above the body; holes reach about 100 units
+    down, so a part of them pass through or near it."""
+    body = blob(faces, radius, (0.0, 0.0, 0.0), seed + 1)
+    seg = drill_holes(holes, segs, seed, 1.5 * radius, 1.3 * radius + 5.0)
+    return seg, body

@@ -253,3 +253,32 @@ def test_device_validation_errors(ctx):
     d, h = ctx.distance(a, b)
     assert float(d.cpu()[0]) == 1.0 and int(h.cpu()[0]) == 0
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dist", ["intgrid", "nearplane"])
+def test_work_list_overflow_falls_back_exactly(ctx, dist):
+    """A full rescue list (FP32 pairs the bounds did not settle) makes the call
+    compute again in plain FP64; a full exact list is enlarged and the call
+    computed again.  Forced here with tiny capacities: the results stay equal
+    to the oracle and to the unforced call, bit for bit."""
+    A, B = _pair_rows(dist, 300, 123)
+    ico = [synth.config_icospheres(s) for s in range(4)]
+    A += [a for a, _ in ico]
+    B += [b for _, b in ico]
+    d_o, h_o = _oracle_rows(A, B)
+    pa, pb = synth.pack(A), synth.pack(B)
+    ba, bb = sd3.Batch.from_packed(pa, "cuda:0"), sd3.Batch.from_packed(pb, "cuda:0")
+    d0, h0, s0 = ctx.distance(ba, bb, stats=True)
+    assert s0["fallback"] == 0 and s0["rescued"] > 1 and s0["exact"] > 1
+    ref = d0.cpu().numpy().view(np.int64).copy()
+    for kw in ({"rescue_cap": 1}, {"exact_cap": 1}, {"rescue_cap": 1, "exact_cap": 1}):
+        d, h, st = ctx.distance(ba, bb, stats=True, **kw)
+        assert st["fallback"] >= 1, kw
+        assert np.array_equal(d.cpu().numpy().view(np.int64), ref), kw
+        _check(A, B, d.cpu().numpy(), h.cpu().numpy(), d_o, h_o)
+        hi, si = ctx.intersects(ba, bb, stats=True, **kw)
+        assert np.array_equal(hi.cpu().numpy().astype(bool), h_o), kw
+    # host-memory inputs take the same path
+    hb_a, hb_b = sd3.Batch.from_packed(pa), sd3.Batch.from_packed(pb)
+    d, h, st = ctx.distance(hb_a, hb_b, stats=True, rescue_cap=1)
+    assert st["fallback"] >= 1 and np.array_equal(d.view(np.int64), ref)

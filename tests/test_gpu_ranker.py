@@ -52,6 +52,29 @@ def test_forward_and_gradient_match_fp64_reference(ctx, n):
     assert np.all(np.abs(g - g_ref) <= 1e-4 * np.abs(g_ref).max() + 1e-6)
 
 
+@pytest.mark.parametrize("n", [1, 5, 300, 4099])
+def test_on_path_scorer_matches_fp64_reference(ctx, n):
+    # the learned seed round's scorer (the device function k_rank ranks by,
+    # with its padded LDS rows and 16-byte dot products) against the numpy
+    # FP64 forward pass, on feature rows like the logged ones and on wide
+    # random ones
+    g = np.random.default_rng(100 + n)
+    p = (g.normal(size=mlp.NPARAM) * 0.2).astype(np.float32)
+    X = g.normal(size=(n, mlp.NIN)).astype(np.float32)
+    X[: n // 2, :8] = np.abs(X[: n // 2, :8]) * 3.0   # log2(1 + x) features are >= 0
+    X[: n // 2, 8:] = g.uniform(1 / 64, 1.0, size=(n // 2, 2))  # triangle fractions
+    r = sd3.Ranker(ctx)
+    y = r.score(_dev(p), _dev(X)).cpu().numpy()
+    y_ref, _ = mlp.forward(p.astype(np.float64), X.astype(np.float64))
+    err = np.abs(y - y_ref) / (1.0 + np.abs(y_ref))
+    assert np.all(err <= 1e-4), (float(err.max()), int(np.argmax(err)))
+    # the shipped weights too
+    w = ranker.load(device="cuda:0")
+    y = r.score(w, _dev(X)).cpu().numpy()
+    y_ref, _ = mlp.forward(w.cpu().numpy().astype(np.float64), X.astype(np.float64))
+    assert np.all(np.abs(y - y_ref) <= 1e-4 * (1.0 + np.abs(y_ref)))
+
+
 def test_adam_matches_reference(ctx):
     g = np.random.default_rng(3)
     p = g.normal(size=mlp.NPARAM)

@@ -77,11 +77,12 @@ def test_batch_4096_rows(ctx):
     for _ in range(2):
         g.launch()
         gi.launch()
-    g.result()
-    gi.result()
+    assert g.result(stats=True)["queue_skew"] == 0
+    assert gi.result(stats=True)["queue_skew"] == 0
     d32, h32 = g.dist.cpu().numpy(), g.hit.cpu().numpy().astype(bool)
     hi32 = gi.hit.cpu().numpy().astype(bool)
-    d64, h64 = ctx.distance(ba, bb, precision="fp64", tile=64)
+    d64, h64, s64 = ctx.distance(ba, bb, precision="fp64", tile=64, stats=True)
+    assert s64["queue_skew"] == 0
     d64, h64 = d64.cpu().numpy(), h64.cpu().numpy().astype(bool)
     # properties on every row
     assert np.array_equal(_bits(d32), _bits(d64)) and np.array_equal(h32, h64)
@@ -120,9 +121,10 @@ def test_batch_rows_every_variant_agrees(ctx):
         for order in ("learned", "bound", "none"):
             for tile in sd3.TILES:
                 print(f"batch512: {prec} {order} {tile}", flush=True)
-                d, h = ctx.distance(ba, bb, precision=prec, order=order, tile=tile,
-                                    ranker=w if order == "learned" else None)
-                hi = ctx.intersects(ba, bb, precision=prec, tile=tile)
+                d, h, sd = ctx.distance(ba, bb, precision=prec, order=order, tile=tile,
+                                        ranker=w if order == "learned" else None, stats=True)
+                hi, si = ctx.intersects(ba, bb, precision=prec, tile=tile, stats=True)
+                assert sd["queue_skew"] == 0 and si["queue_skew"] == 0, (prec, order, tile)
                 got = (_bits(d.cpu().numpy()).copy(), h.cpu().numpy().astype(bool))
                 assert np.array_equal(got[1], hi.cpu().numpy().astype(bool)), (prec, order, tile)
                 if ref is None:

@@ -316,3 +316,31 @@ def test_pruning_adversarial(olib):
     dp, hp, npr = _mesh(A, B, olib, mode="pruned", threads=1)
     assert (dp, hp) == (d, h) and not h
     assert abs(d - 6.9) < 0.11   # the k == 0 triangle of the cluster
+
+
+SEGMENT_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "segment_forms.json")
+
+
+def segment_cases():
+    with open(SEGMENT_GOLDEN) as f:
+        g = json.load(f)
+    T = (np.asarray(g["triangle"], float), np.array([[0, 1, 2]], np.int32))
+    out = []
+    for c in g["cases"]:
+        p, q = c["segment"]
+        S = (np.array([p, q, q], float), np.array([[0, 1, 2]], np.int32))
+        out.append((c["name"], S, T, c["distance"], c["intersects"]))
+    return out
+
+
+@pytest.mark.parametrize("case", segment_cases(), ids=lambda c: c[0])
+def test_segment_and_point_closed_forms(case, olib):
+    # segment / point against a triangle (the paper's primitives, Sec. 3.2.2
+    # items (i)-(iii), Sec. 3.2.3 Eq. 4) through the oracle's degenerate-triangle
+    # handling, both argument orders and both modes
+    name, S, T, d_want, h_want = case
+    for A, B in ((S, T), (T, S)):
+        for mode in ("all", "pruned"):
+            d, h, _ = oracle.mesh(A, B, mode=mode, lib=olib)
+            assert h == h_want, name
+            assert abs(d - d_want) <= 1e-15 * max(1.0, d_want), (name, d, d_want)

@@ -60,3 +60,40 @@ def test_first_adam_step_closed_form():
     p1, m, v = mlp.adam(p, g, np.zeros(4), np.zeros(4), 1, lr=0.1, eps=1e-8)
     # step 1: bias-corrected m = g, v = g^2, so the update is lr * g / (|g| + eps)
     assert np.allclose(p1, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_constant_gradient_closed_form():
+    # with a constant gradient g the moments after k steps are (1 - beta1^k) g
+    # and (1 - beta2^k) g^2, so each bias-corrected step moves every parameter
+    # by exactly lr * g / (|g| + eps): after k steps p_k = p_0 - k lr g / (|g| + eps).
+    # A bias correction with a wrong exponent (say beta ** 1 instead of
+    # beta ** step) agrees at step 1 and fails here from step 2 on.
+    g = np.array([0.5, -2.0, 1e-3, 3.0, -1e-2])
+    p = np.array([1.0, -1.0, 0.25, 0.0, 2.0])
+    m = np.zeros(5)
+    v = np.zeros(5)
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    step_size = lr * g / (np.abs(g) + eps)
+    p0 = p.copy()
+    for k in range(1, 9):
+        p, m, v = mlp.adam(p, g, m, v, k, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        assert np.allclose(m, (1.0 - b1 ** k) * g, rtol=1e-12, atol=0)
+        assert np.allclose(v, (1.0 - b2 ** k) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(p, p0 - k * step_size, rtol=1e-12, atol=1e-15)
+
+
+def test_adam_mutant_bias_exponent_fails_the_pin():
+    # a planted slip in the bias correction (exponent fixed at 1) passes the
+    # step-1 pin but not the constant-gradient pin above
+    def adam_bad(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        return p - lr * (m / (1.0 - beta1)) / (np.sqrt(v / (1.0 - beta2)) + eps), m, v
+
+    g = np.array([0.5, -2.0])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    p1, _, _ = adam_bad(p, g, m, v, 1, lr=0.1)
+    assert np.allclose(p1, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    for k in range(1, 4):
+        p, m, v = adam_bad(p, g, m, v, k, lr=0.1)
+    assert not np.allclose(p, -3 * 0.1 * g / (np.abs(g) + 1e-8), rtol=1e-6)
