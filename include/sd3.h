@@ -115,8 +115,21 @@ typedef struct sd3_opts {
     int64_t rescue_cap;  /* 0, or a smaller bound of the FP32 rescue list (2^24) */
     int64_t exact_cap;   /* 0, or the starting bound of the exact-arithmetic list
                             (2^22) */
-    int64_t reserved[1];
+    int32_t semantics;   /* SD3_SURFACE (default) or SD3_SOLID */
+    int32_t reserved32;
 } sd3_opts;
+
+/*
+ * What a row's mesh stands for.  SD3_SURFACE: the union of its closed
+ * triangles (a mesh nested inside a closed mesh does not meet it).  SD3_SOLID:
+ * the closed region a closed, consistently oriented, connected mesh bounds
+ * (the paper's ore bodies, Sec. 4): two rows meet when their surfaces meet or
+ * a vertex of one lies inside the other solid (exact ray parity); the
+ * distance is then 0, otherwise the surface distance.  The meshes are not
+ * checked for being closed.  Eager calls only (graphs: SD3_E_INVALID_ARG).
+ */
+#define SD3_SURFACE 0
+#define SD3_SOLID 1
 
 #define SD3_TILE_AUTO 0
 #define SD3_TILE_32 32

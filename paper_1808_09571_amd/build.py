@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsd3.so")
-SOURCES = ["sd3_kernels.hip", "sd3_segments.hip", "sd3_volume.hip", "sd3_mlp.hip", "sd3_api.hip"]
+SOURCES = ["sd3_kernels.hip", "sd3_segments.hip", "sd3_volume.hip", "sd3_solid.hip", "sd3_mlp.hip", "sd3_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

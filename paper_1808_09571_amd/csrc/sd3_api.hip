@@ -60,6 +60,7 @@ struct Workspace {
     DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, vcode, small, grpA, grpB, wi_lb, wlist;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
+    DevBuf solid;                      // solid semantics: queries, directions, results
     // work-list capacities (a call's options may lower them)
     int64_t queue_budget = QUEUE_BUDGET;
     unsigned int rescue_cap = RESCUE_CAP, exact_cap = EXACT_CAP;
@@ -88,7 +89,7 @@ struct Workspace {
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
                         &vals0, &vals1, &hist, &part, &rowid, &vcode, &small, &grpA, &grpB, &wi_lb,
-                        &wlist, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part};
+                        &wlist, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
 };
@@ -310,6 +311,8 @@ sd3_status check_call(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, cons
     if (opts.queue_cap < 0) return fail(ctx, SD3_E_INVALID_ARG, "queue_cap < 0");
     if (opts.rescue_cap < 0 || opts.exact_cap < 0 || opts.rescue_cap > INT32_MAX || opts.exact_cap > INT32_MAX)
         return fail(ctx, SD3_E_INVALID_ARG, "rescue_cap / exact_cap outside [0, 2^31)");
+    if (opts.semantics != SD3_SURFACE && opts.semantics != SD3_SOLID)
+        return fail(ctx, SD3_E_INVALID_ARG, "unknown semantics");
     if (opts.log && (opts.log_cap < 0 || a->mem != SD3_MEM_DEVICE))
         return fail(ctx, SD3_E_INVALID_ARG, "log needs a device buffer and log_cap >= 0");
     if (a->mem == SD3_MEM_HOST) {
@@ -641,6 +644,49 @@ sd3_status device_error(sd3_ctx *ctx, const HipError &e) {
     return fail(ctx, SD3_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
 }
 
+// Solid semantics after the surface results are in: point-in-solid queries
+// for both sides of every row (rows already meeting return at once), again
+// with the next ray direction for those whose direction was degenerate, then
+// the rows whose solids meet get distance 0 and hit 1.  Host buffers: the
+// context's pinned staging (the static scratch's for allocation-free calls).
+void solid_pass(sd3_ctx *ctx, Workspace &ws, Call &C, hipStream_t s, char *host, size_t host_cap) {
+    const int64_t G = C.P.G, nq = 2 * G;
+    if (G == 0) return;
+    uint8_t *res = (uint8_t *)ws.buf(ws.solid, (size_t)nq * 6 + 64);
+    uint8_t *dir = res + nq;
+    int32_t *queries = (int32_t *)(((uintptr_t)(dir + nq) + 3) & ~(uintptr_t)3);
+    if (ws.arena_full) throw ScratchFull{ws.arena_used};
+    if ((size_t)nq * 6 + 64 > host_cap) throw HipError{hipErrorOutOfMemory, "solid staging"};
+    int32_t *hq = (int32_t *)host;
+    uint8_t *hdir = (uint8_t *)(hq + nq);
+    uint8_t *hres = hdir + nq;
+    for (int64_t i = 0; i < nq; i++) {
+        hq[i] = (int32_t)i;
+        hdir[i] = 0;
+    }
+    const SolidSide A{C.A.xyz, C.A.tri, C.A.v_off, C.A.t_off};
+    const SolidSide B{C.B.xyz, C.B.tri, C.B.v_off, C.B.t_off};
+    int64_t n = nq;
+    for (int round = 0; round < SOLID_DIRS && n > 0; round++) {
+        check(hipMemcpyAsync(dir, hdir, nq, hipMemcpyHostToDevice, s), "H2D directions");
+        check(hipMemcpyAsync(queries, hq, sizeof(int32_t) * n, hipMemcpyHostToDevice, s), "H2D queries");
+        launch_inside(A, B, C.rows, queries, n, dir, res, ctx->cus * 4, s);
+        check(hipMemcpyAsync(hres, res, nq, hipMemcpyDeviceToHost, s), "D2H inside");
+        check(hipStreamSynchronize(s), "sync");
+        int64_t m = 0;
+        for (int64_t k = 0; k < n; k++) {
+            const int32_t code = hq[k];
+            if (hres[code] & 2) {
+                hdir[code]++;
+                hq[m++] = code;
+            }
+        }
+        n = m;
+    }
+    if (n > 0) throw HipError{hipErrorUnknown, "no generic ray direction for a point-in-solid query"};
+    launch_solid_apply(res, G, C.dd, C.hd, C.rows, C.L, C.flags, s);
+}
+
 // What a finished call's scalars say about its work lists.
 enum Overflow { OVF_NONE = 0, OVF_RESCUE = 1, OVF_EXACT = 2, OVF_OTHER = 3 };
 Overflow overflow_kind(const Call &C, const unsigned int *sc_h, const unsigned long long *cnt_h) {
@@ -683,6 +729,7 @@ sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         char *rb = readback_area(ctx);
         const unsigned int *sc_h = (const unsigned int *)rb;
         const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
+        alignas(16) char rbcopy[SCALAR_BYTES];
         enqueue_validate(C, s);
         if (a->mem == SD3_MEM_DEVICE) {
             // device inputs are validated before any kernel reads them
@@ -713,6 +760,16 @@ sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         if (st != SD3_OK) return st;
         ovf = overflow_kind(C, sc_h, cnt_h);
         xcap_used = C.L.xcap;
+        if (ovf == OVF_NONE && opts.semantics == SD3_SOLID) {
+            // the staging below may move the pinned buffer the scalars were
+            // read into: keep a copy of them
+            memcpy(rbcopy, rb, SCALAR_BYTES);
+            sc_h = (const unsigned int *)rbcopy;
+            cnt_h = (const unsigned long long *)(rbcopy + 64);
+            const size_t hb = (size_t)C.P.G * 12 + 64;
+            solid_pass(ctx, ws, C, s, ensure_pinned(ctx, hb), hb);
+            check(hipGetLastError(), "kernel launch");
+        }
         if (ovf == OVF_NONE) {
             const int64_t G = C.P.G;
             if (a->mem == SD3_MEM_HOST && G > 0) {
@@ -1091,6 +1148,7 @@ sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, cons
     if (st != SD3_OK) return st;
     if (a->mem != SD3_MEM_DEVICE) return fail(ctx, SD3_E_INVALID_ARG, "graphs need device-resident batches");
     if (opts.timing || opts.log) return fail(ctx, SD3_E_INVALID_ARG, "graphs support neither timing nor log");
+    if (opts.semantics != SD3_SURFACE) return fail(ctx, SD3_E_INVALID_ARG, "graphs support surface semantics only");
     const int tk = choose_tile(ctx, opts, mode, a, b);
     sd3_graph *g = new (std::nothrow) sd3_graph();
     if (!g) return fail(ctx, SD3_E_NOMEM, "host allocation failed");

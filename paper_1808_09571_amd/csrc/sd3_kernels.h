@@ -193,6 +193,22 @@ void launch_finalize(const RowState *rows, int64_t G, double *dist, uint8_t *hit
                      const uint32_t *vflags, hipStream_t s);
 void launch_reset_queue(Lists &L, hipStream_t s);
 
+// Solid semantics (sd3_solid.hip): point-in-solid queries by exact ray
+// parity.  Query code 2 g + s: the first vertex of side s's row g against
+// side 1 - s's row g; dir[code] selects the ray direction; res[code] bits:
+// 1 inside, 2 degenerate direction (run again with another), 4 on the surface.
+constexpr int SOLID_DIRS = 8;
+struct SolidSide {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off, *t_off;  // [G+1] device
+};
+void launch_inside(const SolidSide &A, const SolidSide &B, const RowState *rows, const int32_t *queries,
+                   int64_t nq, const uint8_t *dir, uint8_t *res, int grid, hipStream_t s);
+// rows whose solids meet (res) get distance 0 and hit 1 (unless the call failed)
+void launch_solid_apply(const uint8_t *res, int64_t G, double *dist, uint8_t *hit, const RowState *rows,
+                        Lists &L, const uint32_t *vflags, hipStream_t s);
+
 // Volume of each row (sd3_volume.hip): work items are (row, chunk of
 // volume_chunk() triangles); part holds 16 bytes per item; flags[0] takes the
 // validation bits.

@@ -31,6 +31,7 @@ STATUS = {
 
 KIND = {"distance": 0, "intersects": 1}
 SEG_OP = {"distance": 0, "intersects": 1, "within": 2}
+SEMANTICS = {"surface": 0, "solid": 1}
 TILES = (32, 64, 128)
 
 EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
@@ -50,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("ranker", ctypes.c_void_p), ("log", ctypes.c_void_p),
                 ("log_cap", ctypes.c_int64), ("queue_cap", ctypes.c_int64),
                 ("rescue_cap", ctypes.c_int64), ("exact_cap", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 1)]
+                ("semantics", ctypes.c_int32), ("reserved32", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -229,8 +230,9 @@ class Context:
 
     @staticmethod
     def _opts(precision, order, timing=False, ranker=None, log=None, tile=0, queue_cap=0,
-              rescue_cap=0, exact_cap=0):
+              rescue_cap=0, exact_cap=0, semantics="surface"):
         o = Opts()
+        o.semantics = SEMANTICS[semantics]
         o.precision = PREC[precision]
         o.order = ORDER[order]
         o.timing = 1 if timing else 0
@@ -266,7 +268,7 @@ class Context:
 
     def distance(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
                  timing=False, ranker=None, log=None, tile=0, queue_cap=0, rescue_cap=0,
-                 exact_cap=0):
+                 exact_cap=0, semantics="surface"):
         """Row-wise 3D distance (and the exact intersects flag as a by-product).
         order="learned" needs ``ranker`` (float32 [MLP_NPARAM] on the device);
         ``log`` (float32 [cap, LOG_STRIDE] on the device) receives one training
@@ -275,7 +277,8 @@ class Context:
         ga, gb = a.geoms(), b.geoms()
         d, h, dp, hp = self._outputs(a, True)
         s = Stats()
-        o = self._opts(precision, order, timing, ranker, log, tile, queue_cap, rescue_cap, exact_cap)
+        o = self._opts(precision, order, timing, ranker, log, tile, queue_cap, rescue_cap, exact_cap,
+                       semantics)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
@@ -283,13 +286,13 @@ class Context:
         return (d, h, s.as_dict()) if stats else (d, h)
 
     def intersects(self, a: Batch, b: Batch, precision="fp32", order="bound", stats=False,
-                   timing=False, tile=0, queue_cap=0, rescue_cap=0, exact_cap=0):
+                   timing=False, tile=0, queue_cap=0, rescue_cap=0, exact_cap=0, semantics="surface"):
         """Row-wise exact 3D intersects."""
         ga, gb = a.geoms(), b.geoms()
         _, h, _, hp = self._outputs(a, False)
         s = Stats()
         o = self._opts(precision, order, timing, tile=tile, queue_cap=queue_cap,
-                       rescue_cap=rescue_cap, exact_cap=exact_cap)
+                       rescue_cap=rescue_cap, exact_cap=exact_cap, semantics=semantics)
         st = self.lib.sd3_intersects(self.handle, ctypes.byref(ga), ctypes.byref(gb), hp,
                                      ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:

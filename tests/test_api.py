@@ -186,3 +186,25 @@ def test_binding_layouts_match_header(tmp_path):
             assert getattr(py[t], m).offset == int(v), k
         else:
             assert ctypes.sizeof(py[k]) == int(v), k
+
+
+def test_segment_volume_and_score_entry_points_reject_null(lib):
+    b = _batch([synth.cube()])
+    g = b.geoms()
+    seg = np.zeros((2, 2, 3))
+    out = np.zeros(2)
+    flag = np.zeros(2, np.uint8)
+    st = lib.sd3_segments(None, 0, seg.ctypes.data, 2, 0, ctypes.byref(g), 0.0, out.ctypes.data,
+                          flag.ctypes.data, None, None)
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+    st = lib.sd3_volume(None, ctypes.byref(g), out.ctypes.data, None, None)
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+    st = lib.sd3_mlp_score(None, None, None, 0, None, None)
+    assert sd3.STATUS[st] == "SD3_E_INVALID_ARG"
+
+
+def test_opts_fields_have_defaults(lib):
+    o = sd3.Opts()
+    o.rescue_cap, o.exact_cap, o.semantics = 5, 6, 7
+    lib.sd3_default_opts(ctypes.byref(o))
+    assert o.rescue_cap == 0 and o.exact_cap == 0 and o.semantics == 0

@@ -135,3 +135,41 @@ def test_planted_mistakes_fail_a_pin():
                lambda u, v, w: dot(v, cross(sub(v, u), sub(w, u))) / 6 - 1]  # shifted
     for mt in mutants:
         assert exact(box, mt) != want
+
+
+# --- point in solid (solid semantics): the oracle's winding number ---------
+def test_winding_number_inside_outside(olib):
+    # a closed outward mesh winds once around interior points and not at all
+    # around exterior ones, whatever the mesh (a topological invariant)
+    cube = synth.cube((0.0, 0.0, 0.0), 1.0)
+    for p, w in (((0.5, 0.5, 0.5), 1.0), ((0.01, 0.99, 0.5), 1.0), ((1.5, 0.5, 0.5), 0.0),
+                 ((-3.0, 2.0, 1.0), 0.0)):
+        assert abs(oracle.winding(cube, p, lib=olib) - w) < 1e-12, p
+    for m in (synth.icosphere(3), synth.blob(5000, 2.0, (0.0, 0.0, 0.0), 9), _octahedron(1.0)):
+        assert abs(oracle.winding(m, (0.1, -0.05, 0.2), lib=olib) - 1.0) < 1e-12
+        assert abs(oracle.winding(m, (4.0, 1.0, -2.0), lib=olib)) < 1e-12
+        flipped = (m[0], m[1][:, ::-1].copy())
+        assert abs(oracle.winding(flipped, (0.1, -0.05, 0.2), lib=olib) + 1.0) < 1e-12
+
+
+def test_solid_semantics_of_nested_meshes(olib):
+    outer = synth.icosphere(3)
+    inner = synth.icosphere(2, radius=0.5, center=(0.1, 0.0, -0.05))
+    d_s, h_s, _ = oracle.mesh(inner, outer, lib=olib)
+    assert not h_s and d_s > 0.3
+    assert oracle.mesh_solid(inner, outer, lib=olib) == (0.0, True)
+    assert oracle.mesh_solid(outer, inner, lib=olib) == (0.0, True)
+    far = synth.icosphere(2, radius=0.5, center=(3.0, 0.0, 0.0))
+    d, h, _ = oracle.mesh(far, outer, lib=olib)
+    assert oracle.mesh_solid(far, outer, lib=olib) == (d, False)
+    # a planted mistake (the solid angle without its factor 2) puts interior
+    # points at winding 1/2, which the 1/2 threshold no longer separates
+    x, t = outer
+    p = np.array([0.1, 0.0, 0.0])
+    tot = 0.0
+    for tri in t:
+        a, b, c = (x[i] - p for i in tri)
+        la, lb, lc = (np.linalg.norm(v) for v in (a, b, c))
+        tot += math.atan2(np.dot(a, np.cross(b, c)),
+                          la * lb * lc + np.dot(a, b) * lc + np.dot(a, c) * lb + np.dot(b, c) * la)
+    assert abs(tot / (4 * math.pi) - 0.5) < 1e-9
