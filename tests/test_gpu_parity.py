@@ -169,8 +169,9 @@ def test_ragged_soups(ctx):
 
 
 def test_icospheres(ctx):
+    # the icosphere configuration: seeds 0..63
     A, B = [], []
-    for seed in range(16):
+    for seed in range(64):
         a, b = synth.config_icospheres(seed)
         A.append(a)
         B.append(b)
