@@ -1482,11 +1482,13 @@ __device__ __forceinline__ int rl_i(int v, int i) { return __builtin_amdgcn_read
 __device__ __forceinline__ float rl_f(float v, int i) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
-__device__ __forceinline__ double rl_d(double v, int i) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+__device__ __forceinline__ unsigned long long rl_u64(unsigned long long b, int i) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, i);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), i);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double rl_d(double v, int i) {
+    return __longlong_as_double((long long)rl_u64((unsigned long long)__double_as_longlong(v), i));
 }
 
 // LDS written by some lanes of a wave and read by others: the wave's LDS
@@ -1830,7 +1832,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                         const unsigned long long mine = double_to_bits(U);
                         unsigned long long prev = 0;
                         if (lane == 0) prev = atomicMin(&rows[g].ub, mine);
-                        prev = (unsigned long long)rl_d(__longlong_as_double((long long)prev), 0) ;
+                        prev = rl_u64(prev, 0);  // the bit pattern, not a numeric conversion
                         ub_now = bits_to_double(prev < mine ? prev : mine);
                     }
                     const double lim = ub_now + msc + 1.4551915228366852e-11 * ub_now;

@@ -4,8 +4,10 @@ distance of Sec. 3.2.2 (items (i)-(iii)), the intersection of Sec. 3.2.3
 (Eq. 4, closed constraints) and the distance-threshold filter.
 
 Bar: flags bit-exact against the oracle (which takes a segment as the
-degenerate triangle (P0, P1, P1)); distances within 1e-12 relative; the
-segment path bit-identical to sd3_distance on the same degenerate triangles;
+degenerate triangle (P0, P1, P1)); distances within 1e-12 relative, or within
+the FP64 error model 1e-12 d + 64 u S (S the extent of the segment and the
+mesh) when the gap is below 1e-6 S, where FP64 resolves the extent but not
+the gap to 12 digits (the same bar as the mesh path); the segment path bit-identical to sd3_distance on the same degenerate triangles;
 the threshold filter exactly (distance <= r) of the distance the library
 returns.
 """
@@ -46,6 +48,17 @@ def _seg_dev(seg, device):
 
 def _np(x):
     return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+
+
+U = 2.0 ** -53
+
+
+def _tol(seg_i, mesh, d_o):
+    """Distance tolerance of one segment: 1e-12 relative, plus 64 u S below
+    1e-6 S (S = largest extent of the segment's and the mesh's joint box)."""
+    pts = np.vstack([np.asarray(seg_i, np.float64).reshape(-1, 3), mesh[0]])
+    S = float(np.max(pts.max(axis=0) - pts.min(axis=0)))
+    return 1e-12 * d_o + 64 * U * S if d_o < 1e-6 * S else 1e-12 * d_o
 
 
 def _oracle_segments(seg, mesh, idx):
@@ -151,7 +164,7 @@ def test_million_drillhole_segments_vs_500_face_body(ctx):
         if h_o[k]:
             assert d[i] == 0.0
         else:
-            assert abs(d[i] - d_o[k]) <= 1e-12 * d_o[k], (i, d[i], d_o[k])
+            assert abs(d[i] - d_o[k]) <= _tol(seg[i], body, d_o[k]), (i, d[i], d_o[k])
 
 
 def test_segment_errors(ctx):
