@@ -1473,9 +1473,10 @@ __device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, un
 }
 
 
-constexpr int QB = 8;       // most queue entries a wave claims at once
+constexpr int QB = 16;      // most queue entries a wave claims at once
 constexpr int RING = 128;   // LDS ring of triangle pairs awaiting their test (two batches)
 constexpr int TLCAP = 256;  // FP32 pairs awaiting the rescue decision of their tile pair
+constexpr unsigned RCHUNK = 128;  // rescue-list slots a wave claims at once
 
 // Lane i's value in every lane (i wave-uniform): v_readlane into a scalar.
 __device__ __forceinline__ int rl_i(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
@@ -1500,17 +1501,50 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A wave's share of the rescue list: it claims RCHUNK slots with one atomic
+// and fills them in order, so that most appends need no global atomic (and no
+// wait on one).  Slots left unused when the wave finishes are written with
+// ta = -1, which the rescue kernels skip; the list's count is the number of
+// slots claimed (an overflow is still detected from it).
+struct RescueChunk {
+    unsigned base = 0, left = 0;  // wave-uniform
+    // every lane of the wave calls this (keep may be false)
+    __device__ __forceinline__ void push(bool keep, const Rescue &item, const Lists &L) {
+        const unsigned long long m = __ballot(keep);
+        if (m == 0) return;
+        const unsigned n = (unsigned)__popcll(m);
+        const unsigned pos = (unsigned)__popcll(m & lanes_below());
+        unsigned idx;
+        if (n <= left) {
+            idx = base + pos;
+            base += n;
+            left -= n;
+        } else {
+            unsigned nb = 0;
+            if (lane_id() == 0) nb = atomicAdd(L.rcount, RCHUNK);
+            nb = (unsigned)__builtin_amdgcn_readfirstlane((int)nb);
+            idx = pos < left ? base + pos : nb + (pos - left);
+            base = nb + (n - left);
+            left = RCHUNK - (n - left);
+        }
+        if (keep && idx < L.rcap) L.rescue[idx] = item;
+    }
+    __device__ __forceinline__ void close(const Lists &L) {
+        for (unsigned j = (unsigned)lane_id(); j < left; j += 64)
+            if (base + j < L.rcap) L.rescue[base + j] = Rescue{-1, -1, 0u, 0.0f};
+    }
+};
+
 // One claimed queue entry, held in the registers of the lane of its index in
 // the wave's batch: its tiles, row and counts, the row's state when the batch
 // was gathered (a stale upper bound is still an upper bound: it only prunes
-// less), the FP32 constants of the tile pair and its triangle-box cull
-// threshold.
+// less), and the FP32 constants of the tile pair.
 struct Entry {
     int ta, tb, g, na, nb, seed_q, hit;
     float lbf;
     double ub, msc;  // row upper bound and margin scale
     float sh0, sh1, sh2, eu, elb, eps_f, box_tol;
-    double T2;
+    double eps_c;
 };
 
 // Gathers entry q0 + lane of the batch into lane `lane`'s registers (lanes at
@@ -1550,8 +1584,7 @@ __device__ __forceinline__ int wave_gather(Entry &E, const Lists &L, unsigned qc
             E.lbf = lb;
             E.hit = (int)R.hit;
             E.seed_q = R.seed_q;
-            const double ub = bits_to_double(R.ub), m = row_margin(R, ub);
-            E.ub = ub;
+            E.ub = bits_to_double(R.ub);
             E.msc = R.margin_scale;
             if (PREC == 0) {
                 const TP32 c = tp32_consts(a, b);
@@ -1562,13 +1595,7 @@ __device__ __forceinline__ int wave_gather(Entry &E, const Lists &L, unsigned qc
                 E.elb = c.elb;
                 E.eps_f = c.eps_f;
                 E.box_tol = c.box_tol;
-                if (MODE == 0) {
-                    const double T = (ub + m + c.eps_c) / (1.0 - 4.0 * U32);
-                    E.T2 = T * T * (1.0 + 16.0 * U32);
-                }
-            } else if (MODE == 0) {
-                const double T = (ub + m) * (1.0 + 8.0 * U64);
-                E.T2 = T * T;
+                E.eps_c = c.eps_c;
             }
         }
     }
@@ -1586,16 +1613,20 @@ __device__ __forceinline__ double fp32_upper(float dm, float eu) {
 // entries (its first batch is its static share, later ones come from the
 // shared head, claimed one batch ahead so the atomic's latency overlaps the
 // current batch), gathers them into its lanes' registers, and evaluates them
-// one by one: both tiles staged into the wave's own LDS (FP32 copies shifted
-// into the B tile's frame, or FP64), a cull of 8 x 8 slot-group boxes, then
-// of triangle boxes, with the surviving triangle pairs compacted by ballots
-// into an LDS ring and tested 64 at a time, one pair per lane.  Distance: the
-// wave reduces its minimum into the row bound with one atomic and rescues the
-// FP32 pairs whose certified lower bound does not exceed the row bound that
-// atomic returns (plus margin); intersects: certified hits set the row flag,
-// undecided pairs go to the rescue (FP32) or exact (FP64) list.  Nothing is
-// shared between waves but the queue head, the rows' state and the lists, so
-// there is no workgroup barrier.
+// one by one.  The global loads of the next live entry's two tiles (and of
+// its row's current upper bound) are issued as soon as the current entry is
+// staged, so they travel while the current entry is culled and tested.  Per
+// entry: both tiles staged into the wave's own LDS (FP32 copies shifted into
+// the B tile's frame, or FP64), a cull of 8 x 8 slot-group boxes, then of
+// triangle boxes, with the surviving triangle pairs compacted by ballots into
+// an LDS ring and tested 64 at a time, one pair per lane.  Distance: the wave
+// lowers the row bound with one atomic whose result it does not wait for,
+// and rescues the FP32 pairs whose certified lower bound does not exceed the
+// smaller of the row bound read at staging and its own upper bound (plus
+// margin); intersects: certified hits set the row flag, undecided pairs go
+// to the rescue (FP32) or exact (FP64) list.  Nothing is shared between
+// waves but the queue head, the rows' state and the lists, so there is no
+// workgroup barrier.
 template <int PREC, int MODE, int TK>
 __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t64A,
                                               const TileMeta *mA, const float *t32B,
@@ -1604,6 +1635,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
     static_assert(tile_size_ok(TK), "tile size");
     constexpr int NF = F_NTRI32;
     constexpr int NG = TK / 8, NGP = NG * NG;
+    constexpr int NS = 2 * TK / 64;  // staging slots per lane: [A slots | B slots]
     constexpr bool TESTED_LIST = PREC == 0 && MODE == 0;
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
     __shared__ Tt sA[NF * TK];
@@ -1620,6 +1652,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
     // to QB for long ones (one atomic and one gather per batch)
     const unsigned qb = max(1u, min((unsigned)QB, qcount / (nwave * 4u)));
     unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0, n_bad = 0;
+    RescueChunk rch;
     unsigned claim = blockIdx.x;
     for (;;) {
         const unsigned q0 = claim * qb;
@@ -1629,23 +1662,48 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
         unsigned nxt = 0;
         if (lane == 0) nxt = nwave + atomicAdd(L.qhead, 1u);
         const int bn = (int)min(qb, qcount - q0);
-        for (int i = 0; i < bn; i++) {
-            const int ta = rl_i(E.ta, i);
-            if (ta < 0) continue;  // a row without a seed choice
-            if (rl_i(E.hit, i)) continue;
-            if (!L.seed_pass && (int)(q0 + (unsigned)i) == rl_i(E.seed_q, i)) continue;  // seeded already
-            const int tb = rl_i(E.tb, i), g = rl_i(E.g, i);
+        // entry i is evaluated unless its row has no seed choice, already
+        // meets, was seeded with it, or its box bound exceeds the row bound
+        // (plus margin) gathered with the batch (wave-uniform)
+        auto live = [&](int i) __attribute__((always_inline)) {
+            if (rl_i(E.ta, i) < 0 || rl_i(E.hit, i)) return false;
+            if (!L.seed_pass && (int)(q0 + (unsigned)i) == rl_i(E.seed_q, i)) return false;
+            if (MODE == 0) {
+                const double ub = rl_d(E.ub, i), msc = rl_d(E.msc, i);
+                if ((double)rl_f(E.lbf, i) > ub + msc + 1.4551915228366852e-11 * ub) return false;
+            }
+            return true;
+        };
+        // raw tile data of the entry staged next, and its row's upper bound
+        Tt raw[NS][9];
+        unsigned long long raw_ub = ~0ull;
+        int pf = -1;
+        auto load_raw = [&](int j) __attribute__((always_inline)) {
+            const int ja = rl_i(E.ta, j), jb = rl_i(E.tb, j);
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                const int sl = s * 64 + lane;
+                const bool onB = sl >= TK;
+                const int jj = onB ? sl - TK : sl;
+                const Tt *src = PREC == 0 ? (const Tt *)(onB ? t32B + (int64_t)jb * 9 * TK : t32A + (int64_t)ja * 9 * TK)
+                                          : (const Tt *)(onB ? t64B + (int64_t)jb * 9 * TK : t64A + (int64_t)ja * 9 * TK);
+#pragma unroll
+                for (int c = 0; c < 9; c++) raw[s][c] = src[c * TK + jj];
+            }
+            if (MODE == 0) raw_ub = rows[rl_i(E.g, j)].ub;
+            pf = j;
+        };
+        int i = 0;
+        while (i < bn && !live(i)) i++;
+        for (; i < bn;) {
+            if (pf != i) load_raw(i);
+            const int ta = rl_i(E.ta, i), tb = rl_i(E.tb, i), g = rl_i(E.g, i);
             const int na = rl_i(E.na, i), nb = rl_i(E.nb, i);
             const float lbf = rl_f(E.lbf, i);
-            const double ub = rl_d(E.ub, i), msc = rl_d(E.msc, i);
-            const double m = msc + 1.4551915228366852e-11 * ub;  // row_margin
-            if (MODE == 0 && (double)lbf > ub + m) {
-                // pruned at dequeue: its box bound is the logged (lower-bound) outcome
-                if (L.log && lane == 0) log_tile_pair(L, mA[ta], mB[tb], rows[g].scale, lbf, lbf, g);
-                continue;
-            }
+            const double msc = rl_d(E.msc, i);
             n_eval++;
             float sh[3] = {0.0f, 0.0f, 0.0f}, eu = 0.0f, elb = 0.0f, eps_f = 0.0f, box_tol = 0.0f;
+            double eps_c = 0.0;
             if (PREC == 0) {
                 sh[0] = rl_f(E.sh0, i);
                 sh[1] = rl_f(E.sh1, i);
@@ -1654,27 +1712,34 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 elb = rl_f(E.elb, i);
                 eps_f = rl_f(E.eps_f, i);
                 box_tol = rl_f(E.box_tol, i);
+                eps_c = rl_d(E.eps_c, i);
             }
-            float T2f = 0.0f;
-            double T2d = 0.0;
-            if (MODE == 0) {
-                const double T2 = rl_d(E.T2, i);
-                if (PREC == 0) T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
-                else T2d = T2;
-            }
-            // stage both tiles: slot s of [A slots | B slots], 64 at a time;
-            // each group of 8 consecutive slots (8 lanes) reduces its box
+            // stage both tiles from the raw registers: slot s of [A slots |
+            // B slots], 64 at a time; each group of 8 consecutive slots (8
+            // lanes) reduces its box
 #pragma unroll
-            for (int s0 = 0; s0 < 2 * TK; s0 += 64) {
-                const int s = s0 + lane;
-                const bool onB = s >= TK;
-                const int j = onB ? s - TK : s;
+            for (int s = 0; s < NS; s++) {
+                const int sl = s * 64 + lane;
+                const bool onB = sl >= TK;
+                const int j = onB ? sl - TK : sl;
                 Tt *dst = onB ? sB : sA;
-                if (PREC == 0)
-                    stage32<TK>((float *)dst, onB ? t32B + (int64_t)tb * 9 * TK : t32A + (int64_t)ta * 9 * TK,
-                                onB ? 0.0f : sh[0], onB ? 0.0f : sh[1], onB ? 0.0f : sh[2], j);
-                else
-                    stage64<TK>((double *)dst, onB ? t64B + (int64_t)tb * 9 * TK : t64A + (int64_t)ta * 9 * TK, j);
+                if (PREC == 0) {
+                    const float sx = onB ? 0.0f : sh[0], sy = onB ? 0.0f : sh[1], sz = onB ? 0.0f : sh[2];
+#pragma unroll
+                    for (int c = 0; c < 9; c++)
+                        dst[c * TK + j] = (Tt)raw[s][c] + (Tt)(c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);
+                    tri_prep32(TriRef<float>{(float *)dst + j, TK});
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 9; c++) dst[c * TK + j] = raw[s][c];
+                    tri_prep64(TriRef<double>{(double *)dst + j, TK});
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const Tt x0 = raw[s][k], x1 = raw[s][3 + k], x2 = raw[s][6 + k];
+                        dst[(F_LO + k) * TK + j] = fmin(x0, fmin(x1, x2));
+                        dst[(F_HI + k) * TK + j] = fmax(x0, fmax(x1, x2));
+                    }
+                }
                 Tt bx[6];
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
@@ -1691,6 +1756,27 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 if ((j & 7) == 0)
 #pragma unroll
                     for (int k = 0; k < 6; k++) gbox[onB ? 1 : 0][j >> 3][k] = bx[k];
+            }
+            // the row bound now: the batch's, or the one read with the tiles
+            double ub = rl_d(E.ub, i);
+            if (MODE == 0) ub = fmin(ub, bits_to_double(rl_u64(raw_ub, 0)));
+            // the next live entry's loads travel while this one is worked
+            // (FP32 tiles; the FP64 copies would take twice the registers)
+            int nx = i + 1;
+            while (nx < bn && !live(nx)) nx++;
+            if (PREC == 0 && nx < bn) load_raw(nx);
+            float T2f = 0.0f;
+            double T2d = 0.0;
+            if (MODE == 0) {
+                const double m = msc + 1.4551915228366852e-11 * ub;
+                if (PREC == 0) {
+                    const double T = (ub + m + eps_c) / (1.0 - 4.0 * U32);
+                    const double T2 = T * T * (1.0 + 16.0 * U32);
+                    T2f = T2 < 3.0e38 ? (float)(T2 * (1.0 + 0x1p-20)) : __builtin_inff();
+                } else {
+                    const double T = (ub + m) * (1.0 + 8.0 * U64);
+                    T2d = T * T;
+                }
             }
             wave_lds_sync();
             // group-box pairs, compacted into glist
@@ -1722,6 +1808,17 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
             // tested at once
             Tt tmin = (Tt)__builtin_inf();
             unsigned rc = 0, rd = 0, tc = 0;
+            auto rescue_tested = [&](double lim) __attribute__((always_inline)) {
+                // every lane runs every round (the chunk state stays uniform)
+                for (unsigned k0 = 0; k0 < tc; k0 += 64) {
+                    const unsigned k = k0 + (unsigned)lane;
+                    const uint32_t x = k < tc ? tl[k] : 0u;
+                    const float lb = __uint_as_float((x >> 16) << 16);
+                    const bool resc = k < tc && (double)lb <= lim;
+                    rch.push(resc, Rescue{ta, tb, (uint32_t)((x & 255) | (((x >> 8) & 255) << 16)), lb}, L);
+                    n_resc += resc;
+                }
+            };
             auto test_batch = [&](unsigned n) __attribute__((always_inline)) {
                 const bool on = (unsigned)lane < n;
                 uint32_t e = on ? ring[(rd + lane) & (RING - 1)] : 0u;
@@ -1737,21 +1834,13 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                         }
                         if (tc + n > (unsigned)TLCAP) {
                             // the tested list is full: decide its pairs now
-                            // against the row bound at dequeue lowered by this
-                            // tile pair's own minimum so far (a larger limit
-                            // than the final one: it only rescues more)
+                            // against the row bound lowered by this tile
+                            // pair's own minimum so far (a larger limit than
+                            // the final one: it only rescues more)
                             const float dm = wave_min((float)tmin);
                             const double lim0 = dm < __builtin_inff() ? fmin(ub, fp32_upper(dm, eu)) : ub;
-                            const double lim = lim0 + msc + 1.4551915228366852e-11 * lim0;
                             wave_lds_sync();
-                            for (unsigned k = lane; k < tc; k += 64) {
-                                const uint32_t x = tl[k];
-                                const float lb = __uint_as_float((x >> 16) << 16);
-                                const bool resc = (double)lb <= lim;
-                                Rescue it{ta, tb, (uint32_t)((x & 255) | (((x >> 8) & 255) << 16)), lb};
-                                global_push(resc, it, L.rescue, L.rcount, L.rcap);
-                                n_resc += resc;
-                            }
+                            rescue_tested(lim0 + msc + 1.4551915228366852e-11 * lim0);
                             tc = 0;
                             wave_lds_sync();
                         }
@@ -1768,7 +1857,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                         }
                         if (__ballot(c == 1) && lane == 0) atomicOr(&rows[g].hit, 1u);
                         Rescue it{ta, tb, (uint32_t)(a | (b << 16)), 0.0f};
-                        global_push(c == 2, it, L.rescue, L.rcount, L.rcap);
+                        rch.push(c == 2, it, L);
                         n_resc += c == 2;
                     }
                 } else {
@@ -1822,29 +1911,21 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
             if (MODE == 0) {
                 const Tt dm = wave_min(tmin);
                 if (PREC == 0) {
-                    // the row's upper bound now (this tile pair's and every
-                    // earlier result, from the atomic's return value): only
-                    // pairs that may still beat it are rescued; with no pair
-                    // tested there is nothing to rescue
+                    // the row bound from this tile pair's own minimum goes out
+                    // with an atomic that is not waited for; the rescue limit
+                    // is the smaller of that minimum's bound and the row bound
+                    // read with the tiles (every other result it can miss
+                    // only makes the limit larger: more pairs are rescued,
+                    // and the rescue kernel filters them again)
                     double ub_now = ub;
                     if ((float)dm < __builtin_inff()) {
                         const double U = fp32_upper((float)dm, eu);
-                        const unsigned long long mine = double_to_bits(U);
-                        unsigned long long prev = 0;
-                        if (lane == 0) prev = atomicMin(&rows[g].ub, mine);
-                        prev = rl_u64(prev, 0);  // the bit pattern, not a numeric conversion
-                        ub_now = bits_to_double(prev < mine ? prev : mine);
+                        if (lane == 0) atomicMin(&rows[g].ub, double_to_bits(U));
+                        ub_now = fmin(ub_now, U);
                     }
                     const double lim = ub_now + msc + 1.4551915228366852e-11 * ub_now;
                     wave_lds_sync();
-                    for (unsigned k = lane; k < tc; k += 64) {
-                        const uint32_t x = tl[k];
-                        const float lb = __uint_as_float((x >> 16) << 16);
-                        const bool resc = (double)lb <= lim;
-                        Rescue it{ta, tb, (uint32_t)((x & 255) | (((x >> 8) & 255) << 16)), lb};
-                        global_push(resc, it, L.rescue, L.rcount, L.rcap);
-                        n_resc += resc;
-                    }
+                    rescue_tested(lim);
                 } else if (lane == 0 && (double)dm < __builtin_inf()) {
                     atomic_min_pos(&rows[g].d2, (double)dm);
                     atomic_min_pos(&rows[g].ub, sqrt((double)dm));
@@ -1858,9 +1939,22 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 }
             }
             wave_lds_sync();  // LDS reads of this tile pair before the next staging
+            i = nx;
+        }
+        if (MODE == 0 && L.log) {
+            // entries pruned at dequeue: their box bound is the logged
+            // (lower-bound) outcome
+            for (int k = 0; k < bn; k++)
+                if (rl_i(E.ta, k) >= 0 && !rl_i(E.hit, k) && !live(k) &&
+                    (L.seed_pass || (int)(q0 + (unsigned)k) != rl_i(E.seed_q, k)) && lane == 0) {
+                    const int kg = rl_i(E.g, k);
+                    log_tile_pair(L, mA[rl_i(E.ta, k)], mB[rl_i(E.tb, k)], rows[kg].scale, rl_f(E.lbf, k),
+                                  rl_f(E.lbf, k), kg);
+                }
         }
         claim = (unsigned)__builtin_amdgcn_readfirstlane((int)nxt);
     }
+    rch.close(L);
     n_resc = wave_sum(n_resc);
     n_exact = wave_sum(n_exact);
     n_bad = wave_sum(n_bad);
@@ -1956,6 +2050,7 @@ __device__ void rescue_items(const TriSrc &SA, const TriSrc &SB, RowState *rows,
     unsigned long long n64 = 0, nex = 0;
     for (unsigned i = first; i < n; i += step) {
         Rescue e = L.rescue[i];
+        if (e.ta < 0) continue;  // an unused slot of a wave's claimed chunk
         int a = e.slots & 0xffff, b = e.slots >> 16;
         // the vertices depend on the entry alone: their loads go out beside
         // the row state's, not after its checks
