@@ -208,6 +208,32 @@ sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, do
                         uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream);
 
 /*
+ * sd3_distance for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results (bit for bit), but every device buffer of the call is
+ * carved from one static device array of 128 MiB that each GPU holds from the
+ * library's load until the process ends, and host staging comes from pinned
+ * memory sd3_create allocated.  The call allocates no device or pinned memory
+ * and calls no allocating HIP routine (its host bookkeeping uses the C++
+ * heap).  The caller passes inputs and outputs as for sd3_distance.
+ *   Limits: at most 4096 rows; the call's buffers (sort keys, tiles, a
+ *   tile-pair queue of at most 2^21 entries per pass, a rescue list of 2^20
+ *   and an exact list of 2^18 entries) must fit in the 128 MiB, which holds
+ *   roughly 1e6 triangles in all (host inputs are staged there too).
+ *   Errors: those of sd3_distance; SD3_E_CAPACITY (outputs untouched, message
+ *   in sd3_last_error) when the call needs more rows or more scratch;
+ *   SD3_E_INVALID_ARG for opts->timing (HIP events would be created).
+ *   A rescue-list overflow recomputes on the plain FP64 pass as sd3_distance
+ *   does, inside the same scratch.
+ * Every allocation-free call on one GPU shares that GPU's array and its
+ * contents are those of the last call: calls that overlap on one GPU (other
+ * host threads, other contexts, unsynchronised streams) race and must not be
+ * issued.  Each call clears what it needs before use.
+ */
+sd3_status sd3_distance_noalloc(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
+                                uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream);
+
+/*
  * 3D intersects, row by row (Sec. 3.2.3: per-face crossing tests of Eq. 4,
  * combined with OR).  hit : [count] bytes, 1 where the rows share a point.
  * Memory kinds, stream and error behaviour as for sd3_distance.

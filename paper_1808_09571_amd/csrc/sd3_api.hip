@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,7 +17,45 @@
 
 using namespace sd3;
 
+// Allocation-free calls (sd3_distance_noalloc): every device buffer of such a
+// call is carved from this array.  Each GPU the library runs on holds its own
+// copy (at its own address) until the process ends; every allocation-free
+// call on one GPU shares it, so such calls must not overlap on a GPU.  Host
+// code never passes `scratch` itself to a kernel or a copy (on the host it is
+// only a stand-in for the symbol): it uses the per-device address that
+// hipGetSymbolAddress returns at set-up (scratch_on_device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on HIP device `device`, resolved once per
+// device with that device current (the caller's current device is restored).
+hipError_t scratch_on_device(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        e = hipSetDevice(device);
+        if (e != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[device] = p;
+    }
+    *out = scratch_ptr[device];
+    return hipSuccess;
+}
 
 struct DevBuf {
     void *p = nullptr;
@@ -44,6 +83,10 @@ constexpr unsigned int EXACT_CAP_MAX = 1u << 26;  // largest exact list an eager
 constexpr unsigned int NOALLOC_QUEUE = 1u << 21;
 constexpr unsigned int NOALLOC_RESCUE = 1u << 20;
 constexpr unsigned int NOALLOC_EXACT = 1u << 18;
+constexpr int64_t NOALLOC_MAX_ROWS = 4096;  // bounds the pinned staging below
+// pinned host staging allocated at context creation, enough for the offsets
+// (9 arrays of G + 1) and the solid-semantics queries of NOALLOC_MAX_ROWS rows
+constexpr size_t NOALLOC_HOST_BYTES = sizeof(int64_t) * 9 * (NOALLOC_MAX_ROWS + 1) + 12 * NOALLOC_MAX_ROWS + 4096;
 
 // The buffers of a call outgrew the static scratch (bytes needed so far).
 struct ScratchFull {
@@ -110,6 +153,7 @@ struct sd3_ctx {
     int cus = 0;
     std::string err;
     Workspace ws;
+    Workspace sws;        // allocation-free calls: carved from the device's `scratch`
     DevBuf mlp;           // ranker training scratch
     void *pin = nullptr;  // pinned host staging: offsets up, counters down
     size_t pin_cap = 0;
@@ -176,6 +220,14 @@ char *ensure_pinned(sd3_ctx *ctx, size_t bytes) {
 }
 
 char *readback_area(sd3_ctx *ctx) { return (char *)ctx->pin + ctx->pin_cap - 512; }
+
+// Pinned staging for a call on workspace `ws`: an allocation-free call only
+// uses what the context allocated at creation (its row limit keeps `bytes`
+// within it).
+char *staging(sd3_ctx *ctx, const Workspace &ws, size_t bytes) {
+    if (ws.arena && bytes + 512 > ctx->pin_cap) throw HipError{hipErrorOutOfMemory, "static host staging"};
+    return ensure_pinned(ctx, bytes);
+}
 
 sd3_status fail(sd3_ctx *ctx, sd3_status s, const std::string &msg) {
     if (ctx) ctx->err = msg;
@@ -376,6 +428,8 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     if (g->mem == SD3_MEM_HOST) {
         double *x = (double *)ws.buf(st.xyz, sizeof(double) * 3 * nv);
         int32_t *t = (int32_t *)ws.buf(st.tri, sizeof(int32_t) * 3 * nt);
+        // (a static scratch already too small stops before any copy)
+        if (ws.arena_full) throw ScratchFull{ws.arena_used};
         if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
         if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
         S.xyz = x;
@@ -433,7 +487,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
     // B v_off | B t_off | B tiles | work items | A blocks | B chunks]
     const int64_t G1 = G + 1;
-    int64_t *hs = (int64_t *)ensure_pinned(ctx, sizeof(int64_t) * 9 * G1);
+    int64_t *hs = (int64_t *)staging(ctx, ws, sizeof(int64_t) * 9 * G1);
     memcpy(hs, a->v_off, sizeof(int64_t) * G1);
     memcpy(hs + G1, a->t_off, sizeof(int64_t) * G1);
     memcpy(hs + 2 * G1, P.tileA.data(), sizeof(int64_t) * G1);
@@ -767,7 +821,7 @@ sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
             sc_h = (const unsigned int *)rbcopy;
             cnt_h = (const unsigned long long *)(rbcopy + 64);
             const size_t hb = (size_t)C.P.G * 12 + 64;
-            solid_pass(ctx, ws, C, s, ensure_pinned(ctx, hb), hb);
+            solid_pass(ctx, ws, C, s, staging(ctx, ws, hb), hb);
             check(hipGetLastError(), "kernel launch");
         }
         if (ovf == OVF_NONE) {
@@ -804,7 +858,7 @@ sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     } catch (const HipError &e) {
         return device_error(ctx, e);
     } catch (const ScratchFull &f) {
-        return fail(ctx, SD3_E_CAPACITY, "the call needs " + std::to_string(f.need) +
+        return fail(ctx, SD3_E_CAPACITY, "the call needs at least " + std::to_string(f.need) +
                                              " bytes of static scratch; the limit is " +
                                              std::to_string(ws.arena_cap));
     } catch (const std::bad_alloc &) {
@@ -898,10 +952,29 @@ sd3_status sd3_create(sd3_ctx **out, int device) {
     hipDeviceProp_t p;
     if (hipGetDeviceProperties(&p, device) != hipSuccess) return SD3_E_DEVICE;
     if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return SD3_E_NO_DEVICE;
+    // set-up of allocation-free calls: the device's copy of `scratch` and
+    // pinned staging for their offsets
+    void *sp = nullptr;
+    if (scratch_on_device(device, &sp) != hipSuccess) {
+        (void)hipGetLastError();
+        return SD3_E_DEVICE;
+    }
     sd3_ctx *c = new (std::nothrow) sd3_ctx();
     if (!c) return SD3_E_NOMEM;
     c->device = device;
     c->cus = p.multiProcessorCount;
+    c->sws.arena = (char *)sp;
+    c->sws.arena_cap = NOALLOC_SCRATCH_BYTES;
+    c->sws.queue_budget = NOALLOC_QUEUE;
+    c->sws.rescue_cap = NOALLOC_RESCUE;
+    c->sws.exact_cap = NOALLOC_EXACT;
+    try {
+        ensure_pinned(c, NOALLOC_HOST_BYTES);
+    } catch (const HipError &) {
+        (void)hipGetLastError();
+        delete c;
+        return SD3_E_NOMEM;
+    }
     *out = c;
     return SD3_OK;
 }
@@ -927,6 +1000,18 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
 sd3_status sd3_distance(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
                         uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream) {
     return ctx ? run(ctx, ctx->ws, a, b, dist, hit, opts, stats, stream, 0) : SD3_E_INVALID_ARG;
+}
+
+sd3_status sd3_distance_noalloc(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, double *dist,
+                                uint8_t *hit, const sd3_opts *opts, sd3_stats *stats, void *stream) {
+    if (!ctx) return SD3_E_INVALID_ARG;
+    ctx->err.clear();
+    if (opts && opts->timing)
+        return fail(ctx, SD3_E_INVALID_ARG, "timing is not available without allocation (it needs HIP events)");
+    if (a && b && (a->count > NOALLOC_MAX_ROWS || b->count > NOALLOC_MAX_ROWS))
+        return fail(ctx, SD3_E_CAPACITY, "allocation-free calls take at most " +
+                                             std::to_string(NOALLOC_MAX_ROWS) + " rows");
+    return run(ctx, ctx->sws, a, b, dist, hit, opts, stats, stream, 0);
 }
 
 sd3_status sd3_intersects(sd3_ctx *ctx, const sd3_geoms *a, const sd3_geoms *b, uint8_t *hit,
@@ -1095,7 +1180,9 @@ sd3_status sd3_volume(sd3_ctx *ctx, const sd3_geoms *g, double *vol, sd3_stats *
             SideState &sd = ws.side[0];
             double *x = (double *)ensure(sd.xyz, sizeof(double) * 3 * nv);
             int32_t *t = (int32_t *)ensure(sd.tri, sizeof(int32_t) * 3 * nt);
-            if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
+            // (a static scratch already too small stops before any copy)
+        if (ws.arena_full) throw ScratchFull{ws.arena_used};
+        if (nv) check(hipMemcpyAsync(x, g->xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "H2D xyz");
             if (nt) check(hipMemcpyAsync(t, g->tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "H2D tri");
             xyz = x;
             tri = t;

@@ -37,7 +37,8 @@ TILES = (32, 64, 128)
 EXPORTS = ["sd3_default_opts", "sd3_create", "sd3_destroy", "sd3_distance", "sd3_intersects",
            "sd3_graph_create", "sd3_graph_launch", "sd3_graph_result", "sd3_graph_destroy",
            "sd3_autotune", "sd3_mlp_forward", "sd3_mlp_loss_grad", "sd3_adam_step", "sd3_mlp_score",
-           "sd3_validate", "sd3_status_string", "sd3_last_error", "sd3_segments", "sd3_volume"]
+           "sd3_validate", "sd3_status_string", "sd3_last_error", "sd3_segments", "sd3_volume",
+           "sd3_distance_noalloc"]
 
 
 class Geoms(ctypes.Structure):
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
     lib.sd3_distance.argtypes = [ctypes.c_void_p, P(Geoms), P(Geoms), ctypes.c_void_p,
                                  ctypes.c_void_p, P(Opts), P(Stats), ctypes.c_void_p]
     lib.sd3_distance.restype = ctypes.c_int
+    lib.sd3_distance_noalloc.argtypes = lib.sd3_distance.argtypes
+    lib.sd3_distance_noalloc.restype = ctypes.c_int
     lib.sd3_intersects.argtypes = [ctypes.c_void_p, P(Geoms), P(Geoms), ctypes.c_void_p,
                                    P(Opts), P(Stats), ctypes.c_void_p]
     lib.sd3_intersects.restype = ctypes.c_int
@@ -281,6 +284,33 @@ class Context:
                        semantics)
         st = self.lib.sd3_distance(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
                                    ctypes.byref(o), ctypes.byref(s), self._stream(a))
+        if st != 0:
+            self._raise(st)
+        return (d, h, s.as_dict()) if stats else (d, h)
+
+    def distance_noalloc(self, a: Batch, b: Batch, out=None, precision="fp32", order="bound",
+                         stats=False, ranker=None, tile=0, queue_cap=0, rescue_cap=0, exact_cap=0,
+                         semantics="surface"):
+        """sd3_distance_noalloc: the same results as ``distance`` with every
+        device buffer taken from the library's static scratch (no allocation
+        in the call).  ``out``: (dist, hit) outputs of ``a.count`` rows in the
+        inputs' memory (float64, uint8), else allocated here."""
+        ga, gb = a.geoms(), b.geoms()
+        if out is None:
+            d, h, dp, hp = self._outputs(a, True)
+        else:
+            d, h = out
+            if a.on_device:
+                dp, hp = d.data_ptr(), h.data_ptr()
+            else:
+                dp, hp = d.ctypes.data, h.ctypes.data
+            if len(d) != a.count or len(h) != a.count:
+                raise ValueError("outputs must hold one value per row")
+        s = Stats()
+        o = self._opts(precision, order, False, ranker, None, tile, queue_cap, rescue_cap, exact_cap,
+                       semantics)
+        st = self.lib.sd3_distance_noalloc(self.handle, ctypes.byref(ga), ctypes.byref(gb), dp, hp,
+                                           ctypes.byref(o), ctypes.byref(s), self._stream(a))
         if st != 0:
             self._raise(st)
         return (d, h, s.as_dict()) if stats else (d, h)
