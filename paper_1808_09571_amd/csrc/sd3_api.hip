@@ -83,10 +83,13 @@ constexpr unsigned int EXACT_CAP_MAX = 1u << 26;  // largest exact list an eager
 constexpr unsigned int NOALLOC_QUEUE = 1u << 21;
 constexpr unsigned int NOALLOC_RESCUE = 1u << 20;
 constexpr unsigned int NOALLOC_EXACT = 1u << 18;
+// offset arrays of G + 1 staged per call: v_off, t_off and tile offsets of
+// both sides, work items, A blocks, B chunks, sort blocks of both sides
+constexpr int N_OFFSETS = 11;
 constexpr int64_t NOALLOC_MAX_ROWS = 4096;  // bounds the pinned staging below
 // pinned host staging allocated at context creation, enough for the offsets
 // (9 arrays of G + 1) and the solid-semantics queries of NOALLOC_MAX_ROWS rows
-constexpr size_t NOALLOC_HOST_BYTES = sizeof(int64_t) * 9 * (NOALLOC_MAX_ROWS + 1) + 12 * NOALLOC_MAX_ROWS + 4096;
+constexpr size_t NOALLOC_HOST_BYTES = sizeof(int64_t) * N_OFFSETS * (NOALLOC_MAX_ROWS + 1) + 12 * NOALLOC_MAX_ROWS + 4096;
 
 // The buffers of a call outgrew the static scratch (bytes needed so far).
 struct ScratchFull {
@@ -100,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, rowid, vcode, small, grpA, grpB, wi_lb, wlist;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, small, grpA, grpB, wi_lb, wlist;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -131,7 +134,7 @@ struct Workspace {
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &rowid, &vcode, &small, &grpA, &grpB, &wi_lb,
+                        &vals0, &vals1, &hist, &part, &vcode, &small, &grpA, &grpB, &wi_lb,
                         &wlist, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
@@ -143,6 +146,8 @@ struct Plan {
     std::vector<int64_t> tileA, tileB;  // [G+1] tile offsets
     std::vector<int64_t> wi;            // [G+1] work-item offsets
     std::vector<int64_t> blkA, chkB;    // [G+1] A-block (64 tiles) / B-chunk (256 tiles) offsets
+    std::vector<int64_t> sbA, sbB;      // [G+1] sort blocks of each row (rsi items each)
+    int rsi = RS_ITEMS;                 // items per sort block
     int64_t potential = 0;              // sum of tilesA * tilesB
 };
 
@@ -484,10 +489,23 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         P.wi[g + 1] = P.wi[g] + (na > 0 && nb > 0 ? ((na + 63) / 64) * ((nb + 255) / 256) : 0);
         P.potential += na * nb;
     }
+    // sort blocks: each row's items in blocks of rsi (larger blocks for large
+    // sorts)
+    {
+        const int64_t n = a->t_off[G] + b->t_off[G];
+        P.rsi = n <= SMALL_SORT ? RS_ITEMS : 2 * RS_ITEMS;
+        P.sbA.assign(G + 1, 0);
+        P.sbB.assign(G + 1, 0);
+        for (int64_t g = 0; g < G; g++) {
+            P.sbA[g + 1] = P.sbA[g] + (a->t_off[g + 1] - a->t_off[g] + P.rsi - 1) / P.rsi;
+            P.sbB[g + 1] = P.sbB[g] + (b->t_off[g + 1] - b->t_off[g] + P.rsi - 1) / P.rsi;
+        }
+    }
     // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
-    // B v_off | B t_off | B tiles | work items | A blocks | B chunks]
+    // B v_off | B t_off | B tiles | work items | A blocks | B chunks | A sort
+    // blocks | B sort blocks]
     const int64_t G1 = G + 1;
-    int64_t *hs = (int64_t *)staging(ctx, ws, sizeof(int64_t) * 9 * G1);
+    int64_t *hs = (int64_t *)staging(ctx, ws, sizeof(int64_t) * N_OFFSETS * G1);
     memcpy(hs, a->v_off, sizeof(int64_t) * G1);
     memcpy(hs + G1, a->t_off, sizeof(int64_t) * G1);
     memcpy(hs + 2 * G1, P.tileA.data(), sizeof(int64_t) * G1);
@@ -497,23 +515,25 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     memcpy(hs + 6 * G1, P.wi.data(), sizeof(int64_t) * G1);
     memcpy(hs + 7 * G1, P.blkA.data(), sizeof(int64_t) * G1);
     memcpy(hs + 8 * G1, P.chkB.data(), sizeof(int64_t) * G1);
-    int64_t *ds = (int64_t *)ws.buf(ws.small, sizeof(int64_t) * 9 * G1);
+    memcpy(hs + 9 * G1, P.sbA.data(), sizeof(int64_t) * G1);
+    memcpy(hs + 10 * G1, P.sbB.data(), sizeof(int64_t) * G1);
+    int64_t *ds = (int64_t *)ws.buf(ws.small, sizeof(int64_t) * N_OFFSETS * G1);
     const bool fp64 = opts.precision == SD3_PREC_FP64;
     setup_side(ws, 0, a, P.tileA[G], tk, fp64, ds, C.A, s);
     setup_side(ws, 1, b, P.tileB[G], tk, fp64, ds + 3 * G1, C.B, s);
     C.A.boxrep = C.B.boxrep = std::max(C.A.boxrep, C.B.boxrep);
     {
         int64_t n = C.A.nt + C.B.nt;
-        int64_t nb = (n + RS_ITEMS - 1) / RS_ITEMS + 1;
-        C.PB.keys[0] = (uint64_t *)ws.buf(ws.keys0, sizeof(uint64_t) * n);
-        C.PB.keys[1] = (uint64_t *)ws.buf(ws.keys1, sizeof(uint64_t) * n);
+        const int64_t nb = P.sbA[G] + P.sbB[G];
+        C.PB.keys[0] = (uint32_t *)ws.buf(ws.keys0, sizeof(uint32_t) * n);
+        C.PB.keys[1] = (uint32_t *)ws.buf(ws.keys1, sizeof(uint32_t) * n);
         C.PB.vals[0] = (int32_t *)ws.buf(ws.vals0, sizeof(int32_t) * n);
         C.PB.vals[1] = (int32_t *)ws.buf(ws.vals1, sizeof(int32_t) * n);
-        C.PB.hist = (uint32_t *)ws.buf(ws.hist, sizeof(uint32_t) * 256 * nb);
-        C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * nb / 4096 + 2));
-        C.PB.rowid = (int32_t *)ws.buf(ws.rowid, sizeof(int32_t) * (n > 0 ? n : 1));
-        C.PB.vcode = n > SMALL_SORT ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
-                                    : nullptr;
+        C.PB.hist = (uint32_t *)ws.buf(ws.hist, sizeof(uint32_t) * 256 * (nb + 1));
+        C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * (nb + 1) / 4096 + 2));
+        C.PB.vcode = P.rsi > RS_ITEMS ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
+                                      : nullptr;
+        C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi};
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;
@@ -582,7 +602,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     // every buffer is placed: stage the offsets (a static scratch too small
     // for the call stops here, before anything is copied or launched)
     if (ws.arena_full) throw ScratchFull{ws.arena_used};
-    check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * 9 * G1, hipMemcpyHostToDevice, s), "H2D offsets");
+    check(hipMemcpyAsync(ds, hs, sizeof(int64_t) * N_OFFSETS * G1, hipMemcpyHostToDevice, s), "H2D offsets");
 }
 
 // Device validation (flags in the scalar block) fused with the row boxes: the
@@ -603,7 +623,7 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int64_t G = C.P.G;
     const int mode = C.mode;
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
-    launch_prep(A, B, C.PB, sort_key(G), C.rows, s, kev);
+    launch_prep(A, B, C.PB, sort_key(), C.rows, s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s, 0);
@@ -684,9 +704,9 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->exact = (int64_t)cnt_h[C_EXACT];
     stats->logged = (int64_t)cnt_h[C_LOGGED];
     stats->sort_items = C.A.nt + C.B.nt;
-    const SortKey K = sort_key(C.P.G);
-    stats->sort_key_bytes = K.bits() <= 32 ? 4 : 8;
-    stats->sort_passes = (K.bits() + 7) / 8;
+    const SortKey K = sort_key();
+    stats->sort_key_bytes = 4;
+    stats->sort_passes = K.passes;
     stats->tile = C.P.tk;
     stats->queue_passes = C.passes;
     stats->queue_skew = (int64_t)cnt_h[C_SKEW];

@@ -47,15 +47,30 @@ struct KernelEvents {
 constexpr int RS_ITEMS = 2048;
 constexpr int64_t SMALL_SORT = (int64_t)1 << 22;
 
+// Sort blocks: each row of each side is cut into blocks of `rsi` items (a
+// row's last block may be shorter, an empty row has none); A's blocks come
+// first.  A block's per-digit histogram goes to its row's region of the
+// histogram table, laid out [row][digit][block of the row] with A's rows
+// before B's, so one exclusive scan of the whole table gives every (row,
+// digit, block) its place in the sorted order: the sort orders items within
+// their row and never moves them across rows, and the keys hold Morton bits
+// only.
+struct SortSeg {
+    const int64_t *sbA, *sbB;      // [G+1] first sort block of each row (B's counted from nbA)
+    const int64_t *toffA, *toffB;  // [G+1] triangle offsets
+    int64_t G, ntA, nbA, nb;       // rows, A's items, A's blocks, all blocks
+    int rsi;                       // items per block
+};
+
 // Sort buffers shared by both sides (device).
 struct PrepBufs {
-    uint64_t *keys[2];  // [ntA + ntB] ping-pong
+    uint32_t *keys[2];  // [ntA + ntB] ping-pong
     int32_t *vals[2];
-    uint32_t *hist;     // [256 * blocks], blocks = ceil((ntA + ntB) / RS_ITEMS)
+    uint32_t *hist;     // [256 * blocks]
     uint32_t *part;     // [chunks]
-    int32_t *rowid;     // [ntA + ntB] row of each sort item (written by validation)
     uint32_t *vcode;    // [nvA + nvB] Morton code of every vertex, or nullptr (keys
                         // then quantise each first vertex themselves)
+    SortSeg seg;
 };
 
 // Counters (device, unsigned long long[16]).
@@ -122,10 +137,10 @@ int rowbox_replicas(int64_t nv, int64_t G);
 // Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
 // `passes` 8-bit radix passes (total bits = 8 * passes at most).
 struct SortKey {
-    int rowbits, mbits, passes;
-    int bits() const { return 1 + rowbits + mbits; }
+    int mbits, passes;
+    int bits() const { return mbits; }
 };
-SortKey sort_key(int64_t G);
+SortKey sort_key();
 // Morton keys of both sides (the same launch starts the row states from the
 // merged row boxes), the radix sort and the tiles.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,

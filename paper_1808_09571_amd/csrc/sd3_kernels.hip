@@ -95,7 +95,7 @@ __device__ void row_init_vals(RowState *rows, int64_t g, const unsigned long lon
 
 // Triangle blocks of the validation launch (blk counts A's blocks, then B's).
 __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, unsigned blk,
-                              uint32_t *flags, int32_t *rowid) {
+                              uint32_t *flags) {
     __shared__ int64_t g0s;
     const bool sa = blk < A.nblk;
     const TriSide &S = sa ? A : B;
@@ -125,7 +125,6 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
         const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
         for (int k = 0; k < 3; k++)
             if (tv[r][k] < 0 || tv[r][k] >= nvr) f = V_INDEX;
-        rowid[(sa ? 0 : A.nt) + t] = (int32_t)g;
     }
     if (f) atomicOr(flags + (sa ? 0 : 1), f);
 }
@@ -291,11 +290,11 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
 // Blocks [0, A.nblk) take side A's vertices, then B's vertices, then the
 // triangles of both sides.
 __global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, TriSide TA, TriSide TB,
-                                                int64_t G, uint32_t *flags, int32_t *rowid) {
+                                                int64_t G, uint32_t *flags) {
     const unsigned nvb = A.nblk + B.nblk;
     if (blockIdx.x < A.nblk) rowbox_side(A, G, blockIdx.x, flags);
     else if (blockIdx.x < nvb) rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
-    else validate_tris(TA, TB, G, blockIdx.x - nvb, flags, rowid);
+    else validate_tris(TA, TB, G, blockIdx.x - nvb, flags);
 }
 
 static unsigned rowbox_blocks(int64_t nv) {
@@ -323,7 +322,7 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
     TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
     const unsigned nblk = xa.nblk + xb.nblk + ta.nblk + tb.nblk;
     if (nblk > 0)
-        hipLaunchKernelGGL(k_rowbox, dim3(nblk), dim3(256), 0, s, xa, xb, ta, tb, G, flags, P.rowid);
+        hipLaunchKernelGGL(k_rowbox, dim3(nblk), dim3(256), 0, s, xa, xb, ta, tb, G, flags);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -335,12 +334,11 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-// key = side << rowbits+mbits | row << mbits | the top mbits of the 30-bit
-// Morton code of the triangle's first vertex, quantised on cubic cells of the row
-// box (the largest extent / 1024 on every axis, so a flat surface spends its
-// bits on its two long axes); value = triangle index within its side.  Both
-// sides in one launch (A's triangles, then B's), keys written at the width
-// the sort uses.
+// key = the top mbits of the 30-bit Morton code of the triangle's first
+// vertex, quantised on cubic cells of the row box (the largest extent / 1024
+// on every axis, so a flat surface spends its bits on its two long axes);
+// value = triangle index within its side.  Both sides in one launch (A's
+// triangles, then B's); the sort keeps every item within its row.
 
 // Row g's box component k (ordered bits) merged over the rep replicas.
 __device__ __forceinline__ unsigned long long merged_box(const unsigned long long *box, int rep,
@@ -446,30 +444,49 @@ __global__ __launch_bounds__(256) void k_vcode(VcodeSide A, VcodeSide B, int64_t
     else vcode_side(B, G, rep, blockIdx.x - A.nblk);
 }
 
-// One block of 1024 threads per radix-sort block of RS_ITEMS keys, so that
-// the histogram of the sort's first digit is counted here (written as
-// hist[digit * nblocks + block], the layout the scan expects).  Each thread
-// takes RS_ITEMS / 1024 items and issues all their index loads, then all
-// their vertex (VC: code) loads, before any store.
+// Sort block b of the row-segmented sort (every lane of the wave calls this):
+// its side, row, first item, length, and where its digit counts go in the
+// histogram table (digit d at hbase + d * hstride).
+struct SBlock {
+    int64_t i0, t0, g, hbase;
+    int n, hstride, side;
+};
+
+__device__ __forceinline__ SBlock sort_block(const SortSeg &S, int64_t b) {
+    SBlock k;
+    k.side = b >= S.nbA ? 1 : 0;
+    const int64_t bl = k.side ? b - S.nbA : b;
+    const int64_t *sb = k.side ? S.sbB : S.sbA;
+    const int64_t *to = k.side ? S.toffB : S.toffA;
+    k.g = wave_find_row(sb, S.G, bl);
+    const int64_t s0 = sb[k.g], s1 = sb[k.g + 1];
+    const int64_t j = bl - s0;
+    k.t0 = to[k.g] + j * S.rsi;
+    k.n = (int)min((int64_t)S.rsi, to[k.g + 1] - k.t0);
+    k.i0 = (k.side ? S.ntA : 0) + k.t0;
+    k.hstride = (int)(s1 - s0);
+    k.hbase = 256 * ((k.side ? S.nbA : 0) + s0) + j;
+    return k;
+}
+
+// One block of 1024 threads per sort block of RS_ITEMS keys (all in one row),
+// so that the histogram of the sort's first digit is counted here.  Each
+// thread takes RS_ITEMS / 1024 items and issues all their index loads, then
+// all their vertex (VC: code) loads, before any store.  Without per-vertex
+// codes the block's row box is merged once, by each wave, while those loads
+// are in flight.
 // The same launch starts every row's state from the merged row boxes (one
-// wave per row).  Without per-vertex codes and with replicas, each block
-// first merges the boxes of the first two rows of its A part and of its B
-// part into LDS (a row spread over replicas spans many sort blocks, so a
-// block rarely meets more); other rows are merged per item.
-template <typename KT, int RS_ITEMS, bool VC>
-__global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, const int32_t *rowid,
-                                                 int mbits, uint64_t side_key, KT *keys, int32_t *vals,
-                                                 uint32_t *hist, int nblocks, int rep, int64_t G,
-                                                 RowState *rows) {
+// wave per row).
+template <int RS_ITEMS, bool VC>
+__global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, SortSeg S, int mbits,
+                                                 uint32_t *keys, int32_t *vals, uint32_t *hist,
+                                                 int rep, int64_t G, RowState *rows) {
     constexpr int PER = RS_ITEMS / 1024;
     __shared__ uint32_t h[256];
-    __shared__ unsigned long long cb[2][2][6];  // [side][row - cr[side]][component]
-    __shared__ int64_t cr[2];                   // first row of the block's part of each side
     __shared__ unsigned long long rb[16][12];   // per wave: the merged boxes of the row it starts
-    const int64_t n = A.nt + B.nt;
     const int lane = lane_id();
     {
-        // the grid's last waves (of the ragged last block) start the rows
+        // the grid's last waves start the rows
         const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
         const int64_t wv = nwv - 1 - (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
         unsigned long long *m = rb[threadIdx.x >> 6];
@@ -480,32 +497,19 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
             __builtin_amdgcn_wave_barrier();
         }
     }
-    const int64_t i0 = (int64_t)blockIdx.x * RS_ITEMS, i1 = min(n, i0 + RS_ITEMS);
+    if ((int64_t)blockIdx.x >= S.nb) return;  // the one block of a call with no items
+    const SBlock k = sort_block(S, blockIdx.x);
+    const MortonSide &M = k.side ? B : A;
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
-    // wave 0, lanes 0 and 1: the rows of the first items of the block's A and
-    // B parts (loaded beside the items' own loads)
-    int64_t crl = -1;
-    if (!VC && rep > 1 && threadIdx.x < 2) {
-        const int64_t lo = threadIdx.x == 0 ? i0 : max(i0, A.nt);
-        const int64_t hi = threadIdx.x == 0 ? min(i1, A.nt) : i1;
-        if (lo < hi) crl = rowid[lo];
-    }
-    int64_t vi[PER], g[PER];
-    bool ok[PER], sa[PER];
+    const int64_t vb = M.v_off[k.g];
+    const int64_t nvr = M.v_off[k.g + 1] - vb;
+    int64_t vi[PER];
+    bool ok[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
-        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
-        ok[r] = i < n;
-        sa[r] = i < A.nt;
-        g[r] = ok[r] ? rowid[i] : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < PER; r++) {
-        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
-        const MortonSide &S = sa[r] ? A : B;
-        const int64_t t = ok[r] ? (sa[r] ? i : i - A.nt) : 0;
-        const int64_t nvr = S.v_off[g[r] + 1] - S.v_off[g[r]];
-        vi[r] = ok[r] ? S.v_off[g[r]] + corner(S.tri, t, 0, nvr) : 0;
+        const int j = r * 1024 + (int)threadIdx.x;
+        ok[r] = j < k.n;
+        vi[r] = ok[r] ? vb + corner(M.tri, k.t0 + j, 0, nvr) : vb;
     }
     // the key point is the triangle's first vertex (keys only order work)
     double cen[VC ? 1 : PER][3];
@@ -513,74 +517,60 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, con
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         if (VC) {
-            code[r] = ok[r] ? (sa[r] ? A.vcode : B.vcode)[vi[r]] : 0u;
+            code[r] = ok[r] ? M.vcode[vi[r]] : 0u;
         } else {
-            const double *X = sa[r] ? A.xyz : B.xyz;
 #pragma unroll
-            for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? X[3 * vi[r] + c] : 0.0;
+            for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? M.xyz[3 * vi[r] + c] : 0.0;
         }
     }
-    // wave 0 merges the replicas of those rows and the next ones (lanes 0-23:
-    // side, row offset, component) while the coordinates are in flight
-    if (!VC && rep > 1 && threadIdx.x < 64) {
-        const int sd = lane / 12, j = (lane / 6) & 1, k = lane % 6;
-        const int64_t c = __shfl(crl, lane < 24 ? sd : 0);
-        if (lane < 24 && c >= 0 && c + j < G) cb[sd][j][k] = merged_box(sd ? B.box : A.box, rep, G, c + j, k);
-        if (lane < 2) cr[lane] = crl;
+    double lo[3] = {0.0, 0.0, 0.0}, sc = 0.0;
+    if (!VC) {
+        const unsigned long long mb = lane < 6 ? merged_box(M.box, rep, G, k.g, lane) : 0ull;
+        unsigned long long b[6];
+        for (int c = 0; c < 6; c++) b[c] = __shfl(mb, c);
+        sc = row_cells(b, lo);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         if (!ok[r]) continue;
-        const int64_t i = (int64_t)blockIdx.x * RS_ITEMS + r * 1024 + threadIdx.x;
-        const int64_t gr = g[r];
-        if (!VC) {
-            const MortonSide &S = sa[r] ? A : B;
-            const int sd = sa[r] ? 0 : 1;
-            const int64_t j = rep > 1 ? gr - cr[sd] : -1;
-            const bool cached = j == 0 || j == 1;
-            unsigned long long b[6];
-            for (int k = 0; k < 6; k++) b[k] = cached ? cb[sd][j][k] : merged_box(S.box, rep, G, gr, k);
-            double lo[3];
-            const double sc = row_cells(b, lo);
-            code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
-        }
-        const KT key =
-            (KT)((sa[r] ? 0ull : side_key) | ((uint64_t)gr << mbits) | (code[r] >> (30 - mbits)));
-        keys[i] = key;
-        vals[i] = (int32_t)(sa[r] ? i : i - A.nt);
-        atomicAdd(&h[(uint32_t)key & 255u], 1u);
+        const int j = r * 1024 + (int)threadIdx.x;
+        if (!VC) code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
+        const uint32_t key = code[r] >> (30 - mbits);
+        keys[k.i0 + j] = key;
+        vals[k.i0 + j] = (int32_t)(k.t0 + j);
+        atomicAdd(&h[key & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 256 && (int)blockIdx.x < nblocks)
-        hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
 }
 
-// Stable LSD radix sort, 8-bit digits.  Blocks of 256 threads own 4096
-// consecutive items; per pass: digit histogram per block (the first pass's
-// comes from the key kernel), one exclusive scan over (digit, block), and a
-// stable scatter that ranks equal digits inside a wave with ballots.
+// Stable LSD radix sort, 8-bit digits, within rows.  Blocks of 256 threads
+// own one sort block (up to RS_ITEMS consecutive items of one row); per pass:
+// digit histogram per block (the first pass's comes from the key kernel), one
+// exclusive scan over (row, digit, block), and a stable scatter that ranks
+// equal digits inside a wave with ballots.
 
-template <typename KT, int RS_ITEMS>
-__global__ void k_hist(const KT *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+template <int RS_ITEMS>
+__global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *hist) {
     constexpr int PER = RS_ITEMS / 256;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
-    const int64_t base = (int64_t)blockIdx.x * RS_ITEMS;
-    // every load first, at clamped indices (n >= 2 here), so that the thread
+    const SBlock k = sort_block(S, blockIdx.x);
+    // every load first, at clamped indices (n >= 1 here), so that the thread
     // waits for one memory latency rather than one per item
-    KT k[PER];
+    uint32_t kv[PER];
 #pragma unroll
-    for (int r = 0; r < PER; r++) k[r] = keys[min(base + r * 256 + threadIdx.x, n - 1)];
+    for (int r = 0; r < PER; r++) kv[r] = keys[k.i0 + min(r * 256 + (int)threadIdx.x, k.n - 1)];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; r++)
-        if (base + r * 256 + threadIdx.x < n) atomicAdd(&h[(k[r] >> shift) & 255], 1u);
+        if (r * 256 + (int)threadIdx.x < k.n) atomicAdd(&h[(kv[r] >> shift) & 255], 1u);
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
 }
 
-// Exclusive scan of the (digit, block) histogram in chunks of 4096 entries:
+// Exclusive scan of the (row, digit, block) histogram in chunks of 4096 entries:
 // k_scan_local scans each chunk in LDS and records the chunk total, k_scan_top
 // scans the chunk totals; the scatter adds both parts.
 constexpr int SCAN_CHUNK = 4096;
@@ -636,11 +626,11 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
 // digit order and writes each digit's run to consecutive global addresses.
 // With at most 256 scan chunks the block scans the chunk totals itself
 // (ncraw > 0: part holds raw totals), which saves the top-level scan launch.
-template <typename KT, int RS_ITEMS>
-__global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *vin, KT *kout,
-                                                 int32_t *vout, int64_t n, int shift,
-                                                 const uint32_t *hist, const uint32_t *part,
-                                                 int nblocks, int ncraw) {
+template <int RS_ITEMS>
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout,
+                                                 int32_t *vout, SortSeg S, int shift,
+                                                 const uint32_t *hist, const uint32_t *part, int ncraw) {
+    using KT = uint32_t;
     constexpr int Q = RS_ITEMS / 4;   // items per wave
     constexpr int R = Q / 64;         // rounds per wave
     __shared__ uint32_t wc[4][256];   // per-wave digit counts, then per-wave offsets
@@ -649,7 +639,9 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
     __shared__ KT skey[RS_ITEMS];
     __shared__ int32_t sval[RS_ITEMS];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-    const int64_t b0 = (int64_t)blockIdx.x * RS_ITEMS;
+    const SBlock sbk = sort_block(S, blockIdx.x);
+    const int64_t b0 = sbk.i0;
+    const int64_t n = b0 + sbk.n;  // items of this block: [b0, n)
     if (ncraw > 0) {
         // exclusive scan of the raw chunk totals (one per thread) into loff
         __shared__ uint32_t csum[4];
@@ -661,11 +653,11 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
         for (int k = 0; k < w; k++) pre += csum[k];
         loff[tid] = pre;
         __syncthreads();
-        int64_t e = (int64_t)tid * nblocks + blockIdx.x;
+        int64_t e = sbk.hbase + (int64_t)tid * sbk.hstride;
         gbase[tid] = hist[e] + loff[e / SCAN_CHUNK];
         __syncthreads();
     } else {
-        int64_t e = (int64_t)tid * nblocks + blockIdx.x;
+        int64_t e = sbk.hbase + (int64_t)tid * sbk.hstride;
         gbase[tid] = hist[e] + part[e / SCAN_CHUNK];
     }
     for (int k = 0; k < 4; k++) wc[k][tid] = 0;
@@ -722,7 +714,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
         sval[slot] = val[r];
     }
     __syncthreads();
-    const int nvalid = (int)min((int64_t)RS_ITEMS, n - b0);
+    const int nvalid = sbk.n;
     for (int j = tid; j < nvalid; j += 256) {
         KT k = skey[j];
         uint32_t d = (uint32_t)((k >> shift) & 255);
@@ -732,27 +724,27 @@ __global__ __launch_bounds__(256) void k_scatter(const KT *kin, const int32_t *v
     }
 }
 
-// Sort (keys[0], vals[0]) by the low `bits` bits; result in keys[res], vals[res].
-// The first pass's histogram is already in `hist` (from the key kernel).
-template <typename KT, int RS_ITEMS>
-static int radix_sort(KT **keys, int32_t **vals, uint32_t *hist, uint32_t *part, int64_t n,
+// Sort (keys[0], vals[0]) within rows by the low `bits` bits; result in
+// keys[res], vals[res].  The first pass's histogram is already in `hist`
+// (from the key kernel).
+template <int RS_ITEMS>
+static int radix_sort(uint32_t **keys, int32_t **vals, uint32_t *hist, uint32_t *part, const SortSeg &S,
                       int bits, hipStream_t s, KernelEvents *kev) {
     int cur = 0;
-    if (n <= 1) return cur;
-    int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+    if (S.nb == 0) return cur;
+    const int nb = (int)S.nb;
     int64_t total = (int64_t)nb * 256;
     int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
     for (int shift = 0; shift < bits; shift += 8) {
         if (shift > 0)
-            hipLaunchKernelGGL((k_hist<KT, RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], n, shift, hist, nb);
+            hipLaunchKernelGGL((k_hist<RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], S, shift, hist);
         hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
         const bool inline_top = nchunk <= 256;
         if (!inline_top)
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
-        hipLaunchKernelGGL((k_scatter<KT, RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, part, nb,
-                           inline_top ? nchunk : 0);
+        hipLaunchKernelGGL((k_scatter<RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+                           keys[cur ^ 1], vals[cur ^ 1], S, shift, hist, part, inline_top ? nchunk : 0);
         if (kev) kev->end(KE_SCATTER, s);
         cur ^= 1;
     }
@@ -876,27 +868,21 @@ __global__ void k_tiles(TileJob A, TileJob B) {
     else if (t - A.NT < B.NT) tile_one<TWO>(B, t - A.NT);
 }
 
-// Both sides are sorted together (the side is the top key bit), so one
-// sequence of sort launches covers 2x the items.
-// The fewest 8-bit passes that keep at least 18 Morton bits (6 per axis),
-// then every remaining bit of those passes for the Morton prefix (at most 30).
-SortKey sort_key(int64_t G) {
+// Both sides are sorted in one sequence of launches (each row's items stay in
+// the row's range).  The fewest 8-bit passes that keep at least 18 Morton
+// bits (6 per axis), then every bit of those passes for the Morton prefix.
+SortKey sort_key() {
     SortKey K;
-    K.rowbits = 0;
-    while (((int64_t)1 << K.rowbits) < G) K.rowbits++;
-    K.passes = (1 + K.rowbits + 18 + 7) / 8;
-    K.mbits = 8 * K.passes - 1 - K.rowbits;
+    K.passes = (18 + 7) / 8;
+    K.mbits = 8 * K.passes;
     if (K.mbits > 30) K.mbits = 30;
     return K;
 }
 
-// Keys and the sort with RSI items per sort block.
+// Keys and the sort with RSI items per sort block (P.seg.rsi).
 template <int RSI>
 static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
-                      hipStream_t s,
-                      KernelEvents *kev) {
-    const int key_bits = K.rowbits + K.mbits;  // bits below the side bit
-    const int64_t n = A.nt + B.nt;
+                      hipStream_t s, KernelEvents *kev) {
     // large sorts take their keys from per-vertex codes (P.vcode is then set)
     constexpr bool VC = RSI > RS_ITEMS;
     MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode};
@@ -907,32 +893,21 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
         if (ca.nblk + cb.nblk > 0)
             hipLaunchKernelGGL(k_vcode, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
     }
-    const int nb = (int)((n + RSI - 1) / RSI);
     // at least one block: the key kernel also starts the row states
-    const int grid = nb > 0 ? nb : 1;
-    if (key_bits + 1 <= 32) {
-        // both ping-pong buffers of 32-bit keys live in keys[1]
-        uint32_t *k32[2] = {(uint32_t *)P.keys[1], (uint32_t *)P.keys[1] + n};
-        hipLaunchKernelGGL((k_morton<uint32_t, RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb,
-                           P.rowid, K.mbits, 1ull << key_bits, k32[0], P.vals[0], P.hist, nb,
-                           A.boxrep, A.G, rows);
-        return radix_sort<uint32_t, RSI>(k32, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
-    }
-    hipLaunchKernelGGL((k_morton<uint64_t, RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb, P.rowid,
-                       K.mbits, 1ull << key_bits, P.keys[0], P.vals[0], P.hist, nb, A.boxrep, A.G,
-                       rows);
-    return radix_sort<uint64_t, RSI>(P.keys, P.vals, P.hist, P.part, n, key_bits + 1, s, kev);
+    const int grid = P.seg.nb > 0 ? (int)P.seg.nb : 1;
+    hipLaunchKernelGGL((k_morton<RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb, P.seg, K.mbits,
+                       P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows);
+    return radix_sort<RSI>(P.keys, P.vals, P.hist, P.part, P.seg, K.bits(), s, kev);
 }
 
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
                  hipStream_t s, KernelEvents *kev) {
     if (A.G == 0) return;
     // smaller sort blocks shorten each block's serial ranking on small sorts;
-    // larger ones write longer contiguous runs on big sorts
-    const int64_t n = A.nt + B.nt;
-    // (the large-sort variant needs the per-vertex code buffer)
-    const int cur = n <= SMALL_SORT || !P.vcode ? sort_items<RS_ITEMS>(A, B, P, K, rows, s, kev)
-                                                : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
+    // larger ones write longer contiguous runs on big sorts (and take their
+    // keys from the per-vertex code buffer)
+    const int cur = P.seg.rsi == RS_ITEMS ? sort_items<RS_ITEMS>(A, B, P, K, rows, s, kev)
+                                          : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
