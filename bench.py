@@ -99,6 +99,9 @@ def parse():
     p.add_argument("--summarize", default=None, metavar="DIR",
                    help="summarise rocprofv3 output under DIR (see --kind) and exit")
     p.add_argument("--kind", default="stats", choices=["stats", "pmc", "sq"])
+    p.add_argument("--cmd", action="append", default=[], metavar="COMMAND",
+                   help="with --summarize: a command that produced the profiled output (recorded "
+                        "in the summary; repeatable)")
     p.add_argument("--calib", default=None, metavar="DIR",
                    help="with --kind pmc: rocprofv3 output of --copy-calibration (FETCH, WRITE dirs "
                         "as DIR_FETCH_SIZE, DIR_WRITE_SIZE)")
@@ -165,12 +168,15 @@ def roofline_for(kernel, st_list, ms, n, workload):
                 "algorithmic_bytes_per_launch": per,
                 "per_unit": f"{2 * (kb + 4)} B per key ({kb} B key + 4 B value, read + write)"}
     if kernel == "tiles":
-        # one launch builds the tiles of both sides: every sorted item
+        # one launch builds the tiles of both sides: every sorted item; the
+        # step's launches use the two queries' tile sizes
         tris = float(st_list[0]["sort_items"])
         per = tris * BYTES_TILE_TRI
         ach = per / (avg * 1e-3) / 1e9
+        tr = [measured_traffic(f"k_tiles<{x['tile']}>", workload) for x in st_list]
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("k_tiles", workload),
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None if None in tr else sum(tr) / len(tr),
                 "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per,
                 "per_unit": f"{BYTES_TILE_TRI} B per triangle"}
     raise KeyError(kernel)
@@ -547,18 +553,38 @@ def summarize(args):
             n = len(e["dispatches"])
             print(f"| `{k}` | {n} | " + " | ".join(f"{e.get(c, 0.0) / n:.3g}" for c in names) + " |")
         return
-    # pmc: FETCH_SIZE and WRITE_SIZE runs of the workload and of the copy
+    # pmc: FETCH_SIZE and WRITE_SIZE runs of the workload and of the copy.
+    # Keys: "k_scatter" (every radix pass), "k_tiles<TK>", "k_pairs<fp32|fp64,
+    # distance|intersects,TK> main pass" (dispatches above a tenth of the
+    # kernel's largest count: the seed passes, which evaluate at most one tile
+    # pair per row, fall below), other kernels by name.
+    def traffic_key(name):
+        n = _short(name).replace("sd3::", "")
+        if n.startswith("k_scatter"):
+            return "k_scatter"
+        if n.startswith("k_pairs<"):
+            p, m, t = [x.strip() for x in n[len("k_pairs<"):-1].split(",")]
+            return (f"k_pairs<{'fp32' if p == '0' else 'fp64'},{'distance' if m == '0' else 'intersects'},"
+                    f"{t}> main pass")
+        return n
+
     def per_kernel(counter, base):
         rows = _csv_rows(os.path.join(base + "_" + counter, "**", "*counter_collection.csv"))
-        acc = {}
+        disp = {}
         for r in rows:
             if r["Counter_Name"] != counter:
                 continue
-            k = _short(r["Kernel_Name"])
-            e = acc.setdefault(k, [0.0, set()])
-            e[0] += float(r["Counter_Value"])
-            e[1].add(r["Dispatch_Id"])
-        return {k: (v / len(ids), len(ids)) for k, (v, ids) in acc.items()}
+            k = traffic_key(r["Kernel_Name"])
+            e = disp.setdefault(k, {})
+            e[r["Dispatch_Id"]] = e.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        out = {}
+        for k, e in disp.items():
+            vals = list(e.values())
+            if k.endswith("main pass"):
+                top = max(vals)
+                vals = [v for v in vals if v >= 0.1 * top]
+            out[k] = (sum(vals) / len(vals), len(vals))
+        return out
 
     fetch, write = per_kernel("FETCH_SIZE", d), per_kernel("WRITE_SIZE", d)
     calib = {"copy_bytes": COPY_BYTES, "fetch_factor": 1.0, "write_factor": 1.0}
@@ -577,7 +603,7 @@ def summarize(args):
                       "bytes_per_launch": fb + wb,
                       "launches_sampled": max(fetch.get(k, (0, 0))[1], write.get(k, (0, 0))[1])}
     print(json.dumps({"kernel_source_sha256_16": kernel_source_hash(), "calibration": calib,
-                      "workload": args.workload, "kernels": kernels}, indent=1))
+                      "workload": args.workload, "commands": args.cmd, "kernels": kernels}, indent=1))
 
 
 def main():
