@@ -148,6 +148,7 @@ struct Plan {
     std::vector<int64_t> blkA, chkB;    // [G+1] A-block (64 tiles) / B-chunk (256 tiles) offsets
     std::vector<int64_t> sbA, sbB;      // [G+1] sort blocks of each row (rsi items each)
     int rsi = RS_ITEMS;                 // items per sort block
+    int64_t max_row = 0;                // most triangles in one row of either side
     int64_t potential = 0;              // sum of tilesA * tilesB
 };
 
@@ -496,9 +497,12 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         P.rsi = n <= SMALL_SORT ? RS_ITEMS : 2 * RS_ITEMS;
         P.sbA.assign(G + 1, 0);
         P.sbB.assign(G + 1, 0);
+        P.max_row = 0;
         for (int64_t g = 0; g < G; g++) {
-            P.sbA[g + 1] = P.sbA[g] + (a->t_off[g + 1] - a->t_off[g] + P.rsi - 1) / P.rsi;
-            P.sbB[g + 1] = P.sbB[g] + (b->t_off[g + 1] - b->t_off[g] + P.rsi - 1) / P.rsi;
+            const int64_t na = a->t_off[g + 1] - a->t_off[g], nb = b->t_off[g + 1] - b->t_off[g];
+            P.sbA[g + 1] = P.sbA[g] + (na + P.rsi - 1) / P.rsi;
+            P.sbB[g + 1] = P.sbB[g] + (nb + P.rsi - 1) / P.rsi;
+            P.max_row = std::max(P.max_row, std::max(na, nb));
         }
     }
     // all offsets in one pinned staging copy: [A v_off | A t_off | A tiles |
@@ -623,7 +627,7 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
     const int64_t G = C.P.G;
     const int mode = C.mode;
     const int prec = C.opts.precision == SD3_PREC_FP64 ? 1 : 0;
-    launch_prep(A, B, C.PB, sort_key(), C.rows, s, kev);
+    launch_prep(A, B, C.PB, sort_key(C.P.max_row), C.rows, s, kev);
     launch_group_boxes(A, B, Q, C.P.blkA[G], C.P.chkB[G], s);
     mark(2);
     launch_queue(A, B, Q, C.n_wi, 0, C.rows, L, mode == 0 ? Q_SEED : Q_GROUPS, s, 0);
@@ -704,7 +708,7 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->exact = (int64_t)cnt_h[C_EXACT];
     stats->logged = (int64_t)cnt_h[C_LOGGED];
     stats->sort_items = C.A.nt + C.B.nt;
-    const SortKey K = sort_key();
+    const SortKey K = sort_key(C.P.max_row);
     stats->sort_key_bytes = 4;
     stats->sort_passes = K.passes;
     stats->tile = C.P.tk;

@@ -140,7 +140,7 @@ struct SortKey {
     int mbits, passes;
     int bits() const { return mbits; }
 };
-SortKey sort_key();
+SortKey sort_key(int64_t max_row_items);
 // Morton keys of both sides (the same launch starts the row states from the
 // merged row boxes), the radix sort and the tiles.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,

@@ -44,6 +44,16 @@ __device__ __forceinline__ int64_t wave_find_row(const int64_t *off, int64_t G, 
     return lo;
 }
 
+// Workgroups are dealt to the GPU's 8 XCDs (each with its own L2) in turn:
+// block b runs on XCD b % 8.  The logical block of b gives each XCD one
+// contiguous range [x q + min(x, r), ...) of the nb blocks (q = nb / 8,
+// r = nb % 8), so that neighbouring blocks -- the same row's data -- share an
+// L2 instead of being fetched into all eight.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned x = b & 7u, k = b >> 3, q = nb >> 3, r = nb & 7u;
+    return x * q + min(x, r) + k;
+}
+
 // Vertex index of corner k of triangle t, local to its row of nvr vertices.
 // An index outside the row reads vertex 0 instead: kernels that run before the
 // validation flags are read (graph replays) never address memory outside the
@@ -77,10 +87,9 @@ __device__ __forceinline__ uint32_t coord_flags(double v) {
 
 // Every triangle index of both sides must lie inside its row.  Blocks own
 // contiguous ranges of VT_ITEMS triangles of one side (A's blocks first);
-// one binary search finds the row of a block's first triangle and each
-// thread walks forward from it.  The row of every triangle is kept for the
-// key kernel (sort item index: A's triangles, then B's).
-constexpr int VT_ITEMS = 1024;
+// one wave search finds the row of a block's first triangle and each thread
+// walks forward from it.
+constexpr int VT_ITEMS = 4096;
 
 struct TriSide {
     const int32_t *tri;
@@ -93,7 +102,11 @@ struct TriSide {
 __device__ void row_init_vals(RowState *rows, int64_t g, const unsigned long long *bA,
                               const unsigned long long *bB);
 
-// Triangle blocks of the validation launch (blk counts A's blocks, then B's).
+// Triangle blocks of the validation launch (blk counts A's blocks, then B's):
+// every index load of the block's VT_ITEMS triangles is issued before the
+// first check; each thread then walks its items' rows forward from the
+// block's first row, keeping the current row's end and vertex count, so
+// items in the same row need no further load.
 __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, unsigned blk,
                               uint32_t *flags) {
     __shared__ int64_t g0s;
@@ -101,12 +114,6 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
     const TriSide &S = sa ? A : B;
     const int64_t t0 = (int64_t)(sa ? blk : blk - A.nblk) * VT_ITEMS;
     const int64_t t1 = min(S.nt, t0 + VT_ITEMS);
-    if (threadIdx.x < 64) {
-        const int64_t g0 = wave_find_row(S.t_off, G, t0);
-        if (threadIdx.x == 0) g0s = g0;
-    }
-    __syncthreads();
-    // every index load first, at clamped positions (one memory latency)
     constexpr int PER = VT_ITEMS / 256;
     int32_t tv[PER][3];
 #pragma unroll
@@ -115,14 +122,23 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
 #pragma unroll
         for (int k = 0; k < 3; k++) tv[r][k] = S.tri[3 * t + k];
     }
+    if (threadIdx.x < 64) {
+        const int64_t g0 = wave_find_row(S.t_off, G, t0);
+        if (threadIdx.x == 0) g0s = g0;
+    }
+    __syncthreads();
     int64_t g = g0s;
+    int64_t end = S.t_off[g + 1], nvr = S.v_off[g + 1] - S.v_off[g];
     uint32_t f = 0;
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         const int64_t t = t0 + threadIdx.x + 256 * r;
         if (t >= t1) break;
-        while (S.t_off[g + 1] <= t) g++;
-        const int64_t nvr = S.v_off[g + 1] - S.v_off[g];
+        while (end <= t) {
+            g++;
+            end = S.t_off[g + 1];
+            nvr = S.v_off[g + 1] - S.v_off[g];
+        }
         for (int k = 0; k < 3; k++)
             if (tv[r][k] < 0 || tv[r][k] >= nvr) f = V_INDEX;
     }
@@ -498,7 +514,7 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         }
     }
     if ((int64_t)blockIdx.x >= S.nb) return;  // the one block of a call with no items
-    const SBlock k = sort_block(S, blockIdx.x);
+    const SBlock k = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const MortonSide &M = k.side ? B : A;
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     const int64_t vb = M.v_off[k.g];
@@ -556,7 +572,7 @@ __global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *his
     constexpr int PER = RS_ITEMS / 256;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
-    const SBlock k = sort_block(S, blockIdx.x);
+    const SBlock k = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     // every load first, at clamped indices (n >= 1 here), so that the thread
     // waits for one memory latency rather than one per item
     uint32_t kv[PER];
@@ -639,7 +655,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     __shared__ KT skey[RS_ITEMS];
     __shared__ int32_t sval[RS_ITEMS];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-    const SBlock sbk = sort_block(S, blockIdx.x);
+    const SBlock sbk = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const int64_t b0 = sbk.i0;
     const int64_t n = b0 + sbk.n;  // items of this block: [b0, n)
     if (ncraw > 0) {
@@ -863,19 +879,23 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
 // tiles, the rest B's.
 template <bool TWO>
 __global__ void k_tiles(TileJob A, TileJob B) {
-    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (t < A.NT) tile_one<TWO>(A, t);
     else if (t - A.NT < B.NT) tile_one<TWO>(B, t - A.NT);
 }
 
 // Both sides are sorted in one sequence of launches (each row's items stay in
-// the row's range).  The fewest 8-bit passes that keep at least 18 Morton
-// bits (6 per axis), then every bit of those passes for the Morton prefix.
-SortKey sort_key() {
+// the row's range).  Two 8-bit passes (16 Morton bits) while no row has more
+// than 2^18 triangles, else three (24 bits): the key only orders work, and
+// 16 bits already keep the tiles of such rows compact (the 4096-row batch
+// evaluates about 1% more tile pairs than with 24 bits and saves a pass),
+// while rows of millions of triangles need the finer cells (the 4M-triangle
+// TIN against the 1M-triangle blob evaluates 258 tile pairs instead of 2
+// with 16 bits).
+SortKey sort_key(int64_t max_row_items) {
     SortKey K;
-    K.passes = (18 + 7) / 8;
+    K.passes = max_row_items <= ((int64_t)1 << 18) ? 2 : 3;
     K.mbits = 8 * K.passes;
-    if (K.mbits > 30) K.mbits = 30;
     return K;
 }
 
@@ -1220,32 +1240,48 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
     double lim2 = lim * lim * (1.0 + 32.0 * U64);
     bool hit = R.hit != 0;
     unsigned long long best = ~0ull;  // this wave's seed candidate
-    for (int a = 0; a < w.na; a++) {
-        bool keep = false;
-        float lbf = 0.0f;
-        if (w.bvalid && !hit) {
-            double g2 = box_gap2(box[a], box[a] + 3, blo, bhi);
-            if (mode == 0) {
-                keep = g2 <= lim2;
-                if (keep) lbf = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
-            } else {
-                keep = g2 == 0.0 && box[a][0] <= bhi[0] && blo[0] <= box[a][3] &&
-                       box[a][1] <= bhi[1] && blo[1] <= box[a][4] && box[a][2] <= bhi[2] &&
-                       blo[2] <= box[a][5];
+    // groups of FG A tiles share one queue claim (their entries keep the
+    // per-tile order, a-major then lane)
+    constexpr int FG = 8;
+    for (int a0 = 0; a0 < w.na; a0 += FG) {
+        float lbf[FG];
+        unsigned long long m[FG];
+        unsigned int tot = 0;
+#pragma unroll
+        for (int j = 0; j < FG; j++) {
+            const int a = a0 + j;
+            bool keep = false;
+            lbf[j] = 0.0f;
+            if (a < w.na && w.bvalid && !hit) {
+                double g2 = box_gap2(box[a], box[a] + 3, blo, bhi);
+                if (mode == 0) {
+                    keep = g2 <= lim2;
+                    if (keep) lbf[j] = (float)(sqrt(g2) * (1.0 - 8.0 * U64) * (1.0 - 0x1p-20));
+                } else {
+                    keep = g2 == 0.0 && box[a][0] <= bhi[0] && blo[0] <= box[a][3] &&
+                           box[a][1] <= bhi[1] && blo[1] <= box[a][4] && box[a][2] <= bhi[2] &&
+                           blo[2] <= box[a][5];
+                }
             }
+            m[j] = __ballot(keep);
+            tot += (unsigned int)__popcll(m[j]);
         }
-        unsigned long long m = __ballot(keep);
-        if (m == 0) continue;
+        if (tot == 0) continue;
         unsigned int basei = 0;
-        if (lane_id() == 0) basei = atomicAdd(qcount, (unsigned int)__popcll(m));
+        if (lane_id() == 0) basei = atomicAdd(qcount, tot);
         basei = __shfl(basei, 0);
-        const unsigned int idx = basei + (unsigned int)__popcll(m & lanes_below());
-        if (keep && idx < qcap) {
-            queue[idx] = make_int2((int)(w.a0 + a), (int)w.b);
-            qlb[idx] = lbf;
+#pragma unroll
+        for (int j = 0; j < FG; j++) {
+            const bool keep = (m[j] >> lane_id()) & 1ull;
+            const unsigned int idx = basei + (unsigned int)__popcll(m[j] & lanes_below());
+            basei += (unsigned int)__popcll(m[j]);
+            if (keep && idx < qcap) {
+                queue[idx] = make_int2((int)(w.a0 + a0 + j), (int)w.b);
+                qlb[idx] = lbf[j];
+            }
+            if (RANK == 1 && keep && idx < qcap)
+                best = min(best, ((unsigned long long)float_order_bits(lbf[j]) << 32) | idx);
         }
-        if (RANK == 1 && keep && idx < qcap)
-            best = min(best, ((unsigned long long)float_order_bits(lbf) << 32) | idx);
     }
     if (RANK == 1) {
         best = wave_min(best);
@@ -2197,139 +2233,156 @@ __device__ __forceinline__ void row_scale(RowState *rows, int64_t g) {
 }
 
 
-// Ranker weights in LDS, row-major.  The first layer's rows get one padding
-// word (staging writes and the lanes' row reads fall on distinct banks); the
-// hidden layers' rows get four, so that a lane (output unit) reads its row 16
-// bytes at a time with each 16-lane group on distinct banks.
-constexpr int MLP_P1 = MLP_IN + 1, MLP_P2 = MLP_H + 4;
+// The ranker on the matrix cores: a wave scores 16 tile pairs at a time,
+// each layer a chain of FP32 MFMAs (v_mfma_f32_16x16x4_f32: D[16 x 16] +=
+// A[16 x 4] B[4 x 16]; lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[4 (l / 16) + r][l % 16], r = 0..3), so that every weight read from LDS
+// serves 16 pairs.  Rows of A are the 16 pairs, B is the layer's transposed
+// weights, one 16-column tile of the 64 hidden units per accumulator.
+typedef float mfx4 __attribute__((ext_vector_type(4)));
+
+constexpr int MLP_K1 = 12;       // first layer's inputs, padded to 3 steps of 4
+constexpr int MLP_HP = MLP_H + 4;  // padded activation rows in LDS
+// Weights in LDS in the order the B operands are read: layer L, K-step s,
+// column tile c, lane l holds W_L[16 c + l % 16][4 s + l / 16] at
+// [(s * 4 + c) * 64 + l] (one contiguous 256-byte read per MFMA).
 struct alignas(16) MlpLds {
-    alignas(16) float w1[MLP_H * MLP_P1];
-    alignas(16) float w2[MLP_H * MLP_P2];
-    alignas(16) float w3[MLP_H * MLP_P2];
-    alignas(16) float h[4][MLP_H];  // one activation row per wave
+    float w1[(MLP_K1 / 4) * 4 * 64];
+    float w2[(MLP_H / 4) * 4 * 64];
+    float w3[(MLP_H / 4) * 4 * 64];
     float bias[3 * MLP_H + MLP_H + 1];  // b1 b2 b3 w4 b4
 };
-static_assert(MLP_H == 64, "one hidden unit per lane");
-static_assert((MLP_H * MLP_H) % 256 == 0, "whole hidden matrices per 256-thread block");
+// Per wave: the 16 pairs' features and one layer's activations.
+struct MlpWave {
+    float x[16][MLP_K1];
+    float h[16][MLP_HP];
+};
+static_assert(MLP_H == 64, "four 16-column tiles per layer");
 
-// Weights into LDS by a 256-thread block: every global load is issued before
-// the first LDS write, so the block waits for one round trip, not one per row.
+// Weights into LDS by a 256-thread block (the B-operand order above).
 __device__ void mlp_stage(MlpLds &M, const float *W) {
-    constexpr int N1 = (MLP_H * MLP_IN + 255) / 256, N2 = MLP_H * MLP_H / 256;
     const int t = threadIdx.x;
-    float v1[N1], v2[N2], v3[N2], vb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int r = 0; r < N1; r++) {
-        const int i = t + 256 * r;
-        v1[r] = i < MLP_H * MLP_IN ? W[MLP_W1 + i] : 0.0f;
+    for (int i = t; i < (MLP_K1 / 4) * 4 * 64; i += 256) {
+        const int l = i & 63, c = (i >> 6) & 3, st = i >> 8;
+        const int row = 16 * c + (l & 15), k = 4 * st + (l >> 4);
+        M.w1[i] = k < MLP_IN ? W[MLP_W1 + row * MLP_IN + k] : 0.0f;
     }
-#pragma unroll
-    for (int r = 0; r < N2; r++) {
-        v2[r] = W[MLP_W2 + t + 256 * r];
-        v3[r] = W[MLP_W3 + t + 256 * r];
+    for (int i = t; i < (MLP_H / 4) * 4 * 64; i += 256) {
+        const int l = i & 63, c = (i >> 6) & 3, st = i >> 8;
+        const int row = 16 * c + (l & 15), k = 4 * st + (l >> 4);
+        M.w2[i] = W[MLP_W2 + row * MLP_H + k];
+        M.w3[i] = W[MLP_W3 + row * MLP_H + k];
     }
     if (t < MLP_H) {
-        vb[0] = W[MLP_B1 + t];
-        vb[1] = W[MLP_B2 + t];
-        vb[2] = W[MLP_B3 + t];
-        vb[3] = W[MLP_W4 + t];
+        M.bias[t] = W[MLP_B1 + t];
+        M.bias[MLP_H + t] = W[MLP_B2 + t];
+        M.bias[2 * MLP_H + t] = W[MLP_B3 + t];
+        M.bias[3 * MLP_H + t] = W[MLP_W4 + t];
     }
-    const float b4 = W[MLP_B4];
+    if (t == 0) M.bias[4 * MLP_H] = W[MLP_B4];
+}
+
+// One layer: acc[c] = A B_c over `steps` K-steps, A read from rows a[16][*]
+// (lane l takes a[l % 16][4 s + l / 16]), B from the staged weights.
+template <int STEPS, int AS>
+__device__ __forceinline__ void mlp_layer(const float *w, const float (*a)[AS], mfx4 (&acc)[4]) {
+    const int lane = lane_id();
 #pragma unroll
-    for (int r = 0; r < N1; r++) {
-        const int i = t + 256 * r;
-        if (i < MLP_H * MLP_IN) M.w1[(i / MLP_IN) * MLP_P1 + i % MLP_IN] = v1[r];
+    for (int c = 0; c < 4; c++) acc[c] = mfx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int st = 0; st < STEPS; st++) {
+        const float av = a[lane & 15][4 * st + (lane >> 4)];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w[(st * 4 + c) * 64 + lane], acc[c], 0, 0, 0);
+    }
+}
+
+// Bias, ReLU and the activations back to LDS in row order (h[pair][unit]).
+__device__ __forceinline__ void mlp_store(const mfx4 (&acc)[4], const float *bias, float (*h)[MLP_HP]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int j = 16 * c + (lane & 15);
+        const float b = bias[j];
+#pragma unroll
+        for (int r = 0; r < 4; r++) h[4 * (lane >> 4) + r][j] = fmaxf(acc[c][r] + b, 0.0f);
+    }
+}
+
+// Scores of the 16 pairs whose features are in Wv.x (rows past the batch
+// hold zeros); lane i < 16 returns pair i's score.  The whole wave takes part.
+__device__ float mlp_scores16(const MlpLds &M, MlpWave &Wv) {
+    const int lane = lane_id();
+    mfx4 acc[4];
+    wave_lds_sync();
+    mlp_layer<MLP_K1 / 4, MLP_K1>(M.w1, Wv.x, acc);
+    mlp_store(acc, M.bias, Wv.h);
+    wave_lds_sync();
+    mlp_layer<MLP_H / 4, MLP_HP>(M.w2, Wv.h, acc);
+    wave_lds_sync();  // every read of h before it is overwritten
+    mlp_store(acc, M.bias + MLP_H, Wv.h);
+    wave_lds_sync();
+    mlp_layer<MLP_H / 4, MLP_HP>(M.w3, Wv.h, acc);
+    // output: b4 + sum_j w4[j] relu(h3[i][j]); lane l holds rows 4 (l / 16) + r
+    float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int j = 16 * c + (lane & 15);
+        const float b = M.bias[2 * MLP_H + j], w = M.bias[3 * MLP_H + j];
+#pragma unroll
+        for (int r = 0; r < 4; r++) p[r] += w * fmaxf(acc[c][r] + b, 0.0f);
     }
 #pragma unroll
-    for (int r = 0; r < N2; r++) {
-        const int i = t + 256 * r;
-        M.w2[(i / MLP_H) * MLP_P2 + i % MLP_H] = v2[r];
-        M.w3[(i / MLP_H) * MLP_P2 + i % MLP_H] = v3[r];
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) p[r] += __shfl_xor(p[r], o);
+    // pair i = 4 g + r sits in lanes 16 g .. 16 g + 15, register r
+    const int src = 16 * ((lane & 15) >> 2);
+    float sc = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const float v = __shfl(p[r], src);
+        if ((lane & 3) == r) sc = v;
     }
-    if (t < MLP_H)
-        for (int k = 0; k < 4; k++) M.bias[k * MLP_H + t] = vb[k];
-    if (t == 0) M.bias[4 * MLP_H] = b4;
+    return sc + M.bias[4 * MLP_H];
 }
 
-// acc + sum_k w[k] x[k] over the 64 hidden units, in order of k, with 16-byte
-// LDS reads (w: this lane's row, x: the wave's activations, a broadcast).
-__device__ __forceinline__ float mlp_row_dot(const float *w, const float *x, float acc) {
-    const float4 *w4 = reinterpret_cast<const float4 *>(w);
-    const float4 *x4 = reinterpret_cast<const float4 *>(x);
-#pragma unroll 4
-    for (int k = 0; k < MLP_H / 4; k++) {
-        const float4 a = w4[k], b = x4[k];
-        acc += a.x * b.x;
-        acc += a.y * b.y;
-        acc += a.z * b.z;
-        acc += a.w * b.w;
-    }
-    return acc;
-}
-
-// The network's output for features f (the same in every lane); the whole
-// wave takes part, lane = hidden unit.
-__device__ float mlp_wave_score(MlpLds &M, const float *f) {
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    float h = M.bias[lane];
-    for (int k = 0; k < MLP_IN; k++) h += M.w1[lane * MLP_P1 + k] * f[k];
-    M.h[wv][lane] = fmaxf(h, 0.0f);
-    __builtin_amdgcn_wave_barrier();
-    h = mlp_row_dot(M.w2 + lane * MLP_P2, M.h[wv], M.bias[MLP_H + lane]);
-    h = fmaxf(h, 0.0f);
-    __builtin_amdgcn_wave_barrier();
-    M.h[wv][lane] = h;
-    __builtin_amdgcn_wave_barrier();
-    h = mlp_row_dot(M.w3 + lane * MLP_P2, M.h[wv], M.bias[2 * MLP_H + lane]);
-    h = fmaxf(h, 0.0f);
-    float score = wave_sum(h * M.bias[3 * MLP_H + lane]) + M.bias[4 * MLP_H];
-    __builtin_amdgcn_wave_barrier();
-    return score;
-}
-
-// Learned seed choice: each wave takes batches of `per` consecutive queued
-// tile pairs (as many as keep every wave of the grid busy, at most 64); its
-// lanes gather and compute one pair's features each, then the whole wave
-// scores the batch pair by pair (lane = hidden unit), and each pair's lane
-// keeps its row's lowest (ordered score bits << 32 | queue index) with
-// atomicMin.
+// Learned seed choice: each wave takes 16 consecutive queued tile pairs at a
+// time; lanes 0-15 gather one pair's features each, the wave scores them on
+// the matrix cores, and each pair's lane keeps its row's lowest (ordered
+// score bits << 32 | queue index) with atomicMin.
 __global__ __launch_bounds__(256) void k_rank(const TileMeta *mA, const TileMeta *mB, RowState *rows,
                                               Lists L, const float *W) {
     __shared__ MlpLds M;
-    __shared__ float fb[4][MLP_IN][64];  // per wave: features of its batch, [feature][pair]
+    __shared__ MlpWave Wv[4];
     const unsigned n = min(*L.qcount, L.qcap);
     const unsigned nw = gridDim.x * 4u;
-    const unsigned per = min(64u, max(1u, (n + nw - 1) / nw));
-    if ((unsigned)blockIdx.x * 4u * per >= n) return;  // no pair for this block: skip the weights
+    if ((unsigned)blockIdx.x * 64u >= n) return;  // no pair for this block: skip the weights
     mlp_stage(M, W);
     __syncthreads();
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    for (unsigned q0 = (blockIdx.x * 4u + wv) * per; q0 < n; q0 += nw * per) {
+    MlpWave &V = Wv[wv];
+    for (unsigned q0 = (blockIdx.x * 4u + wv) * 16u; q0 < n; q0 += nw * 16u) {
         const unsigned q = q0 + (unsigned)lane;
-        const bool mine = (unsigned)lane < per && q < n;
+        const bool mine = lane < 16 && q < n;
         int row = 0;
+        float f[MLP_IN];
+        for (int k = 0; k < MLP_IN; k++) f[k] = 0.0f;
         if (mine) {
             const int2 e = L.queue[q];
             const TileMeta &a = mA[e.x];
             row = a.row;
-            float f[MLP_IN];
             tp_features(a, mB[e.y], rows[row].scale, L.qlb[q], f);
-            for (int k = 0; k < MLP_IN; k++) fb[wv][k][lane] = f[k];
         }
-        __builtin_amdgcn_wave_barrier();
-        const unsigned cnt = min(per, n - q0);
-        float mine_score = 0.0f;
-        for (unsigned j = 0; j < cnt; j++) {
-            float f[MLP_IN];
-            for (int k = 0; k < MLP_IN; k++) f[k] = fb[wv][k][j];
-            const float sc = mlp_wave_score(M, f);
-            if ((unsigned)lane == j) mine_score = sc;
-        }
+        if (lane < 16)
+            for (int k = 0; k < MLP_K1; k++) V.x[lane][k] = k < MLP_IN ? f[k] : 0.0f;
+        const float sc = mlp_scores16(M, V);
         if (mine) {
-            const unsigned long long key = ((unsigned long long)float_order_bits(mine_score) << 32) | q;
+            const unsigned long long key = ((unsigned long long)float_order_bits(sc) << 32) | q;
             if (key < rows[row].best) atomicMin(&rows[row].best, key);
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();  // the features are read before the next batch's
     }
 }
 
@@ -2339,21 +2392,25 @@ void launch_rank(const SideBufs &A, const SideBufs &B, RowState *rows, Lists &L,
 }
 
 // The seed round's scorer on given feature rows (x: [n][MLP_IN]): the same
-// LDS weight layout and the same wave-wide evaluation as k_rank, one row per
-// wave iteration, so its outputs are exactly the scores k_rank ranks by.
+// LDS weight layout and the same 16-pair matrix-core evaluation as k_rank,
+// so its outputs are exactly the scores k_rank ranks by.
 __global__ __launch_bounds__(256) void k_rank_score(const float *W, const float *x, int64_t n,
                                                     float *y) {
     __shared__ MlpLds M;
-    if ((int64_t)blockIdx.x * 4 >= n) return;
+    __shared__ MlpWave Wv[4];
+    if ((int64_t)blockIdx.x * 64 >= n) return;
     mlp_stage(M, W);
     __syncthreads();
-    const int lane = lane_id();
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    MlpWave &V = Wv[wv];
     const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += nw) {
-        float f[MLP_IN];
-        for (int k = 0; k < MLP_IN; k++) f[k] = x[i * MLP_IN + k];
-        const float sc = mlp_wave_score(M, f);
-        if (lane == 0) y[i] = sc;
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + wv) * 16; i0 < n; i0 += nw * 16) {
+        const int64_t i = i0 + lane;
+        if (lane < 16)
+            for (int k = 0; k < MLP_K1; k++) V.x[lane][k] = (k < MLP_IN && i < n) ? x[i * MLP_IN + k] : 0.0f;
+        const float sc = mlp_scores16(M, V);
+        if (lane < 16 && i < n) y[i] = sc;
+        wave_lds_sync();
     }
 }
 

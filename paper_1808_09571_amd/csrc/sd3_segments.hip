@@ -30,6 +30,7 @@
 namespace sd3 {
 
 constexpr int MESH_TK = 64;   // triangles per mesh tile
+constexpr int SEED_PTS = 256; // mesh vertices a segment's first upper bound is taken over
 constexpr int SEG_NF = 36;    // prepared mesh triangle: F_NTRI64 fields + box
 constexpr int SEG_RING = 128;
 
@@ -163,8 +164,8 @@ __global__ __launch_bounds__(64) void k_segs(const double *seg, int64_t n, const
         const int64_t i = base + lane;
         const bool mine = i < n;
         double lo[3], hi[3];
+        double p[3], q[3];
         {
-            double p[3], q[3];
             for (int c = 0; c < 3; c++) {
                 p[c] = mine ? seg[6 * i + c] : 0.0;
                 q[c] = mine ? seg[6 * i + 3 + c] : 0.0;
@@ -185,6 +186,29 @@ __global__ __launch_bounds__(64) void k_segs(const double *seg, int64_t n, const
         const double msc = 1.4551915228366852e-11 * ext;
         best[lane] = double_to_bits(__builtin_inf());
         done[lane] = mine ? 0u : 1u;
+        // distance: a first upper bound, the distance from the nearer endpoint
+        // to the nearest of up to SEED_PTS mesh vertices (first vertices of
+        // evenly spaced triangles; wave-uniform loads), so that the cull is
+        // tight from the first tile on.  Any segment point and mesh point
+        // bound the distance from above; the returned value still comes from
+        // the pair routine alone.
+        double ub = __builtin_inf();
+        if (MODE == 0 && nt > 0) {
+            const int64_t ns = min((int64_t)SEED_PTS, nt);
+            double u2 = __builtin_inf();
+#pragma unroll 16
+            for (int64_t k = 0; k < ns; k++) {
+                const double *v = P + ((k * nt) / ns) * SEG_NF + F_V;
+                double a2 = 0.0, b2 = 0.0;
+                for (int c = 0; c < 3; c++) {
+                    const double da = p[c] - v[c], db = q[c] - v[c];
+                    a2 += da * da;
+                    b2 += db * db;
+                }
+                u2 = fmin(u2, fmin(a2, b2));
+            }
+            ub = sqrt(u2) * (1.0 + 4.0 * U64);
+        }
         unsigned rc = 0, rd = 0;
         // test ring entries rd .. rd + cnt - 1, one per lane
         auto test_batch = [&](unsigned cntb) __attribute__((always_inline)) {
@@ -231,7 +255,7 @@ __global__ __launch_bounds__(64) void k_segs(const double *seg, int64_t n, const
         for (int64_t tl = 0; tl < ntiles; tl++) {
             // this lane's cull threshold now (the best so far in LDS)
             double T2 = 0.0;
-            if (MODE == 0) T2 = seg_cull2(sqrt(bits_to_double(best[lane])), msc);
+            if (MODE == 0) T2 = seg_cull2(fmin(ub, sqrt(bits_to_double(best[lane]))), msc);
             if (MODE == 2) T2 = seg_cull2(r, msc);
             const bool live = done[lane] == 0;  // out-of-range lanes start done
             const double *tb = tbox + tl * 6;
