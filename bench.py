@@ -56,10 +56,12 @@ METRIC = "tri-pair tests/s + geometry-pairs/s, FP32+learned vs plain FP64, exact
 FLOPS_FP32_PAIR = 711   # full FP32 triangle-pair test: 9 edge/edge, 6 vertex/face, bound
 FLOPS_BOX = 12          # triangle bounding-box lower bound per boxed pair
 FLOPS_TRI_PREP = 64     # per staged triangle (edges, reciprocals, dual basis, box)
-# Algorithmic bytes of tile building per triangle on the FP32 path: sorted
-# index 4, triangle indices 12, three FP64 vertices 72 (read); FP32 copy 36,
-# slot triangle id 4 (write)
-BYTES_TILE_TRI = 4 + 12 + 72 + 36 + 4
+# Algorithmic bytes of tile building on the FP32 path: per triangle the sorted
+# index 4 and the triangle indices 12 (read), the FP32 copy 36 and the slot
+# triangle id 4 (written); per vertex its FP64 coordinates 24, read once (a
+# vertex is shared by the triangles around it)
+BYTES_TILE_TRI = 4 + 12 + 36 + 4
+BYTES_TILE_VTX = 24
 VOL_BYTES_TRI = 12 + 72  # volume: triangle indices and three FP64 vertices
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
@@ -153,9 +155,10 @@ def copy_calibration():
 # ---------------------------------------------------------------------------
 # roofline objects
 # ---------------------------------------------------------------------------
-def roofline_for(kernel, st_list, ms, n, workload):
+def roofline_for(kernel, st_list, ms, n, workload, nverts):
     """Roofline object of one instrumented HBM-bound kernel class over a
-    step.  st_list: stats of the step's calls; ms / n: summed time / launches."""
+    step.  st_list: stats of the step's calls; ms / n: summed time / launches;
+    nverts: vertices of both sides."""
     avg = ms / max(n, 1)
     if kernel == "scatter":
         items = st_list[0]["sort_items"]
@@ -171,14 +174,16 @@ def roofline_for(kernel, st_list, ms, n, workload):
         # one launch builds the tiles of both sides: every sorted item; the
         # step's launches use the two queries' tile sizes
         tris = float(st_list[0]["sort_items"])
-        per = tris * BYTES_TILE_TRI
+        per = tris * BYTES_TILE_TRI + float(nverts) * BYTES_TILE_VTX
         ach = per / (avg * 1e-3) / 1e9
-        tr = [measured_traffic(f"k_tiles<{x['tile']}>", workload) for x in st_list]
+        # (k_tiles<true>: two slots per lane, the 128-triangle tiles)
+        tr = [measured_traffic(f"k_tiles<{'true' if x['tile'] == 128 else 'false'}>", workload)
+              for x in st_list]
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": None if None in tr else sum(tr) / len(tr),
                 "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per,
-                "per_unit": f"{BYTES_TILE_TRI} B per triangle"}
+                "per_unit": f"{BYTES_TILE_TRI} B per triangle + {BYTES_TILE_VTX} B per vertex"}
     raise KeyError(kernel)
 
 
@@ -380,7 +385,8 @@ def measure(name, A, B, ctx, weights, args, headline):
         hbm_classes = [k for k in ("scatter", "tiles") if kn.get(k)]
         dom = max(kms, key=lambda k: kms[k])
         if dom in hbm_classes:
-            roof = roofline_for(dom, [sd, si], kms[dom], kn[dom], name)
+            roof = roofline_for(dom, [sd, si], kms[dom], kn[dom], name,
+                                sum(len(a[0]) for a in A) + sum(len(b[0]) for b in B))
         else:
             roof = pairs_roofline(sd, sd["ms_kernel"]["pairs"], max(sd["n_kernel"]["pairs"], 1), name)
         roof["dominant_by_time"] = dom
