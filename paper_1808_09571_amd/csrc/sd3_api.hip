@@ -103,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, small, grpA, grpB, wi_lb, wlist;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, small, grpA, grpB, wi_lb, wlist, sorttab;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -135,7 +135,7 @@ struct Workspace {
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
                         &vals0, &vals1, &hist, &part, &vcode, &small, &grpA, &grpB, &wi_lb,
-                        &wlist, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
+                        &wlist, &sorttab, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
 };
@@ -537,7 +537,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * (nb + 1) / 4096 + 2));
         C.PB.vcode = P.rsi > RS_ITEMS ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
                                       : nullptr;
-        C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi};
+        C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
+                           G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
+                                                    : nullptr};
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;
@@ -567,6 +569,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
     unsigned int *sc = (unsigned int *)ws.buf(ws.scalars, SCALAR_BYTES);
     C.sc = sc;
     C.flags = sc + 12;
+    C.PB.flags = C.flags;
     L.qcount = sc;
     L.qhead = sc + 1;
     L.rcount = sc + 2;
@@ -611,8 +614,11 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
 
 // Device validation (flags in the scalar block) fused with the row boxes: the
 // first kernels of every call (host inputs were also checked on the host).
-void enqueue_validate(Call &C, hipStream_t s) {
-    launch_validate_rowbox(C.A, C.B, C.PB, C.flags, C.L, s);
+// Without `indices` the triangle indices are checked by the key kernel: every
+// kernel clamps an index into its row before any gather, and the final kernel
+// writes no result while a flag is set.
+void enqueue_validate(Call &C, hipStream_t s, bool indices) {
+    launch_validate_rowbox(C.A, C.B, C.PB, C.flags, C.L, s, indices);
 }
 
 // Every kernel of the call after validation, in stream order, with no host
@@ -808,14 +814,10 @@ sd3_status run(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         const unsigned int *sc_h = (const unsigned int *)rb;
         const unsigned long long *cnt_h = (const unsigned long long *)(rb + 64);
         alignas(16) char rbcopy[SCALAR_BYTES];
-        enqueue_validate(C, s);
-        if (a->mem == SD3_MEM_DEVICE) {
-            // device inputs are validated before any kernel reads them
-            check(hipMemcpyAsync(rb, C.sc, 64, hipMemcpyDeviceToHost, s), "D2H flags");
-            check(hipStreamSynchronize(s), "sync");
-            st = flags_status(ctx, sc_h);
-            if (st != SD3_OK) return st;
-        }
+        // device inputs are validated by the call's kernels (coordinates
+        // first, indices by the key kernel); the flags are read with the
+        // counters at the end, and a flagged call writes no result
+        enqueue_validate(C, s, false);
         clk.mark(1);
         KernelEvents *kev = nullptr;
         if (opts.timing) {
@@ -1271,14 +1273,14 @@ sd3_status sd3_graph_create(sd3_ctx *ctx, int32_t kind, const sd3_geoms *a, cons
         check(hipHostMalloc(&g->pin, SCALAR_BYTES, hipHostMallocDefault), "hipHostMalloc");
         plan_call(ctx, g->ws, a, b, opts, mode, tk, dist, hit, g->C, g->cs);
         // validate the current contents once, before anything reads them
-        enqueue_validate(g->C, g->cs);
+        enqueue_validate(g->C, g->cs, true);
         check(hipMemcpyAsync(g->pin, g->C.sc, 64, hipMemcpyDeviceToHost, g->cs), "D2H flags");
         check(hipStreamSynchronize(g->cs), "sync");
         st = flags_status(ctx, (const unsigned int *)g->pin);
         if (st == SD3_OK) {
             check(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             capturing = true;
-            enqueue_validate(g->C, g->cs);
+            enqueue_validate(g->C, g->cs, false);
             enqueue_pipeline(ctx, g->C, g->cs, nullptr, nullptr);
             capturing = false;
             check(hipStreamEndCapture(g->cs, &g->graph), "hipStreamEndCapture");

@@ -55,12 +55,23 @@ constexpr int64_t SMALL_SORT = (int64_t)1 << 22;
 // digit, block) its place in the sorted order: the sort orders items within
 // their row and never moves them across rows, and the keys hold Morton bits
 // only.
+// One sort block: its side, row, first item (both sides' items numbered A
+// then B) and first triangle of the side, length, and where its digit counts
+// go in the histogram table (digit d at hbase + d * hstride).
+struct SBlock {
+    int64_t i0, t0, g, hbase;
+    int32_t n, hstride, side, pad;
+};
 struct SortSeg {
     const int64_t *sbA, *sbB;      // [G+1] first sort block of each row (B's counted from nbA)
     const int64_t *toffA, *toffB;  // [G+1] triangle offsets
     int64_t G, ntA, nbA, nb;       // rows, A's items, A's blocks, all blocks
     int rsi;                       // items per block
+    SBlock *tab;                   // [nb] every block's entry (calls of many rows), or nullptr:
+                                   // each block then finds its own
 };
+// Calls of at least this many rows build the sort-block table first.
+constexpr int64_t SORT_TABLE_MIN_ROWS = 64;
 
 // Sort buffers shared by both sides (device).
 struct PrepBufs {
@@ -71,6 +82,7 @@ struct PrepBufs {
     uint32_t *vcode;    // [nvA + nvB] Morton code of every vertex, or nullptr (keys
                         // then quantise each first vertex themselves)
     SortSeg seg;
+    uint32_t *flags;    // [2] validation flags of A and B (the key kernel checks indices)
 };
 
 // Counters (device, unsigned long long[16]).
@@ -126,11 +138,12 @@ __device__ __forceinline__ bool call_failed(const Lists &L, const uint32_t *vfla
 
 // Validation of both sides (flags[0] for A, flags[1] for B) fused with the
 // row bounding boxes (one read of xyz): clears the flags, boxes, work-list
-// scalars and counters, checks every coordinate and every triangle index,
-// reduces the row boxes (into A.boxrep replicas) and records each sort item's
-// row.
+// scalars and counters, checks every coordinate, reduces the row boxes (into
+// A.boxrep replicas) and, with `indices`, checks every triangle index (a
+// call's pipeline leaves that to the key kernel, which reads the indices
+// anyway).
 void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, Lists &L,
-                            hipStream_t s);
+                            hipStream_t s, bool indices);
 // Replicas of the row boxes for rows of nv vertices on the larger side: at
 // most 16, one unless a row spans at least 32 reduction blocks.
 int rowbox_replicas(int64_t nv, int64_t G);

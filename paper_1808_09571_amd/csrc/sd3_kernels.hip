@@ -326,7 +326,7 @@ int rowbox_replicas(int64_t nv, int64_t G) {
 }
 
 void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *flags, Lists &L,
-                            hipStream_t s) {
+                            hipStream_t s, bool indices) {
     const int64_t G = A.G;
     const int64_t nbox = (int64_t)A.boxrep * G * 6;
     // (one block at least: C_NCOUNTERS <= 256)
@@ -334,8 +334,9 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
                        L.qcount, flags, L.counters, A.rowbox, B.rowbox, nbox);
     XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv), A.boxrep};
     XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv), B.boxrep};
-    TriSide ta{A.tri, A.nt, A.v_off, A.t_off, grid_for(A.nt, VT_ITEMS)};
-    TriSide tb{B.tri, B.nt, B.v_off, B.t_off, grid_for(B.nt, VT_ITEMS)};
+    // (without `indices` the key kernel checks the triangle indices)
+    TriSide ta{A.tri, A.nt, A.v_off, A.t_off, indices ? grid_for(A.nt, VT_ITEMS) : 0u};
+    TriSide tb{B.tri, B.nt, B.v_off, B.t_off, indices ? grid_for(B.nt, VT_ITEMS) : 0u};
     const unsigned nblk = xa.nblk + xb.nblk + ta.nblk + tb.nblk;
     if (nblk > 0)
         hipLaunchKernelGGL(k_rowbox, dim3(nblk), dim3(256), 0, s, xa, xb, ta, tb, G, flags);
@@ -460,21 +461,16 @@ __global__ __launch_bounds__(256) void k_vcode(VcodeSide A, VcodeSide B, int64_t
     else vcode_side(B, G, rep, blockIdx.x - A.nblk);
 }
 
-// Sort block b of the row-segmented sort (every lane of the wave calls this):
-// its side, row, first item, length, and where its digit counts go in the
-// histogram table (digit d at hbase + d * hstride).
-struct SBlock {
-    int64_t i0, t0, g, hbase;
-    int n, hstride, side;
-};
-
-__device__ __forceinline__ SBlock sort_block(const SortSeg &S, int64_t b) {
+// Sort block b's entry from the side's row offsets, the row found by `find`
+// (a wave search or a thread's own binary search).
+template <typename Find>
+__device__ __forceinline__ SBlock sort_block_entry(const SortSeg &S, int64_t b, Find find) {
     SBlock k;
     k.side = b >= S.nbA ? 1 : 0;
     const int64_t bl = k.side ? b - S.nbA : b;
     const int64_t *sb = k.side ? S.sbB : S.sbA;
     const int64_t *to = k.side ? S.toffB : S.toffA;
-    k.g = wave_find_row(sb, S.G, bl);
+    k.g = find(sb, bl);
     const int64_t s0 = sb[k.g], s1 = sb[k.g + 1];
     const int64_t j = bl - s0;
     k.t0 = to[k.g] + j * S.rsi;
@@ -482,7 +478,23 @@ __device__ __forceinline__ SBlock sort_block(const SortSeg &S, int64_t b) {
     k.i0 = (k.side ? S.ntA : 0) + k.t0;
     k.hstride = (int)(s1 - s0);
     k.hbase = 256 * ((k.side ? S.nbA : 0) + s0) + j;
+    k.pad = 0;
     return k;
+}
+
+// Sort block b of the row-segmented sort (every lane of the wave calls this;
+// b wave-uniform): from the table when the call built one, else by a wave
+// search of the row offsets.
+__device__ __forceinline__ SBlock sort_block(const SortSeg &S, int64_t b) {
+    if (S.tab) return S.tab[b];
+    return sort_block_entry(S, b, [&](const int64_t *sb, int64_t bl) { return wave_find_row(sb, S.G, bl); });
+}
+
+// The table: one thread per sort block, each with its own binary search.
+__global__ __launch_bounds__(256) void k_sort_table(SortSeg S) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= S.nb) return;
+    S.tab[b] = sort_block_entry(S, b, [&](const int64_t *sb, int64_t bl) { return find_row(sb, S.G, bl); });
 }
 
 // One block of 1024 threads per sort block of RS_ITEMS keys (all in one row),
@@ -496,7 +508,7 @@ __device__ __forceinline__ SBlock sort_block(const SortSeg &S, int64_t b) {
 template <int RS_ITEMS, bool VC>
 __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, SortSeg S, int mbits,
                                                  uint32_t *keys, int32_t *vals, uint32_t *hist,
-                                                 int rep, int64_t G, RowState *rows) {
+                                                 int rep, int64_t G, RowState *rows, uint32_t *flags) {
     constexpr int PER = RS_ITEMS / 1024;
     __shared__ uint32_t h[256];
     __shared__ unsigned long long rb[16][12];   // per wave: the merged boxes of the row it starts
@@ -521,12 +533,27 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
     const int64_t nvr = M.v_off[k.g + 1] - vb;
     int64_t vi[PER];
     bool ok[PER];
+    int32_t tv[PER][3];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         const int j = r * 1024 + (int)threadIdx.x;
         ok[r] = j < k.n;
-        vi[r] = ok[r] ? vb + corner(M.tri, k.t0 + j, 0, nvr) : vb;
+        const int64_t t = k.t0 + (ok[r] ? j : 0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) tv[r][c] = M.tri[3 * t + c];
     }
+    // every triangle index must lie inside its row (the three indices share
+    // the cache lines the first one is read from); an invalid first index
+    // reads vertex 0 of the row, and the flag keeps the call from writing
+    // results
+    uint32_t bad = 0;
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) bad |= ok[r] && (tv[r][c] < 0 || (int64_t)tv[r][c] >= nvr);
+        vi[r] = vb + ((tv[r][0] >= 0 && (int64_t)tv[r][0] < nvr) ? (int64_t)tv[r][0] : 0);
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(flags + k.side, V_INDEX);
     // the key point is the triangle's first vertex (keys only order work)
     double cen[VC ? 1 : PER][3];
     uint32_t code[PER];
@@ -839,26 +866,27 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
         hi[k] = wave_max(hi[k]);
         o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
     }
-    double err = 0.0, rad = 0.0;
+    // FP32 copies of the offsets from the origin; rad = their largest
+    // magnitude over the tile
+    float rad32 = 0.0f;
 #pragma unroll
     for (int r = 0; r < 2; r++) {
         const int j = lane + 64 * r;
         if (j >= tk) continue;
-        for (int vtx = 0; vtx < 3; vtx++) {
-            double e2 = 0.0;
-            for (int k = 0; k < 3; k++) {
-                double dlt = v[r][3 * vtx + k] - o[k];
-                float f = (float)dlt;
-                J.t32[(t * 9 + 3 * vtx + k) * tk + j] = f;
-                double e = fabs((double)f - dlt) + U64 * fabs(dlt);
-                e2 += e * e;
-                rad = fmax(rad, fabs((double)f));
-            }
-            err = fmax(err, sqrt(e2));
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            const float f = (float)(v[r][c] - o[c % 3]);
+            J.t32[(t * 9 + c) * tk + j] = f;
+            rad32 = fmaxf(rad32, fabsf(f));
         }
     }
-    err = wave_max(err);
-    rad = wave_max(rad);
+    const double rad = (double)wave_max(rad32);
+    // Storage error of a coordinate: d = x - o is rounded to FP64 (relative
+    // 2^-53) and then to FP32 (relative 2^-24, or 2^-150 absolute in the
+    // subnormal range), so |f - d| <= (2^-24 + 2^-52) |d| + 2^-149 with
+    // |d| <= rad (1 + 2^-22); a vertex (three coordinates) is within sqrt(3)
+    // times that of its copy.
+    const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
     if (lane == 0) {
         TileMeta m;
         for (int k = 0; k < 3; k++) {
@@ -867,7 +895,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
             m.hi[k] = hi[k];
             m.rep[k] = v[0][k];
         }
-        m.eps = (float)(err * (1.0 + 0x1p-20) + 0x1p-1000);
+        m.eps = (float)(err * (1.0 + 0x1p-20));
         m.rad = (float)rad;
         m.row = (int32_t)g;
         m.n = n;
@@ -913,10 +941,12 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
         if (ca.nblk + cb.nblk > 0)
             hipLaunchKernelGGL(k_vcode, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
     }
+    if (P.seg.tab && P.seg.nb > 0)
+        hipLaunchKernelGGL(k_sort_table, dim3(grid_for(P.seg.nb, 256)), dim3(256), 0, s, P.seg);
     // at least one block: the key kernel also starts the row states
     const int grid = P.seg.nb > 0 ? (int)P.seg.nb : 1;
     hipLaunchKernelGGL((k_morton<RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb, P.seg, K.mbits,
-                       P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows);
+                       P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows, P.flags);
     return radix_sort<RSI>(P.keys, P.vals, P.hist, P.part, P.seg, K.bits(), s, kev);
 }
 
