@@ -162,14 +162,18 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
     avg = ms / max(n, 1)
     if kernel == "scatter":
         items = st_list[0]["sort_items"]
-        kb = st_list[0]["sort_key_bytes"]
-        per = items * (kb + 4) * 2
+        ib, npass = st_list[0]["sort_item_bytes"], st_list[0]["sort_passes"]
+        # bytes an item moves, read and written, averaged over the passes
+        # (key + value passes move 16 B, the narrowing pass and a last
+        # key + value pass 12 B, the last pass of a narrow sort 8 B)
+        per_item = ib / npass
+        what = f"{per_item:g} B per item ({ib} B over {npass} passes, read + write)"
+        per = items * per_item
         ach = per / (avg * 1e-3) / 1e9
         return {"kernel": "k_scatter (radix sort pass)", "bound": "hbm", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": measured_traffic("k_scatter", workload), "avg_launch_ms": avg,
-                "algorithmic_bytes_per_launch": per,
-                "per_unit": f"{2 * (kb + 4)} B per key ({kb} B key + 4 B value, read + write)"}
+                "algorithmic_bytes_per_launch": per, "per_unit": what}
     if kernel == "tiles":
         # one launch builds the tiles of both sides: every sorted item; the
         # step's launches use the two queries' tile sizes

@@ -164,7 +164,9 @@ typedef struct sd3_stats {
     double ms_kernel[4];
     int64_t n_kernel[4];
     int64_t sort_items;            /* keys per radix pass (both sides) */
-    int32_t sort_key_bytes;        /* 4 or 8 */
+    int32_t sort_item_bytes;       /* bytes an item moves through the radix
+                                      scatter passes (read and written,
+                                      summed over the passes) */
     int32_t sort_passes;
     int32_t tile;                  /* triangles per tile used by the call */
     int32_t queue_passes;          /* candidate-queue passes */

@@ -715,7 +715,7 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->logged = (int64_t)cnt_h[C_LOGGED];
     stats->sort_items = C.A.nt + C.B.nt;
     const SortKey K = sort_key(C.P.max_row);
-    stats->sort_key_bytes = 4;
+    stats->sort_item_bytes = K.scatter_bytes();
     stats->sort_passes = K.passes;
     stats->tile = C.P.tk;
     stats->queue_passes = C.passes;

@@ -60,7 +60,8 @@ constexpr int64_t SMALL_SORT = (int64_t)1 << 22;
 // go in the histogram table (digit d at hbase + d * hstride).
 struct SBlock {
     int64_t i0, t0, g, hbase;
-    int32_t n, hstride, side, pad;
+    int32_t n, hstride, side;
+    int32_t loc;  // index of the block's first item within its row
 };
 struct SortSeg {
     const int64_t *sbA, *sbB;      // [G+1] first sort block of each row (B's counted from nbA)
@@ -147,11 +148,21 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
 // Replicas of the row boxes for rows of nv vertices on the larger side: at
 // most 16, one unless a row spans at least 32 reduction blocks.
 int rowbox_replicas(int64_t nv, int64_t G);
-// Sort key layout: side (1 bit) | row (rowbits) | Morton prefix (mbits), in
-// `passes` 8-bit radix passes (total bits = 8 * passes at most).
+// Sort items: the Morton prefix (mbits = 8 * passes bits, one 8-bit radix
+// pass per byte) with the triangle's index.  Narrow (no row has more than
+// 2^24 triangles): the index is the triangle's within its row, and the pass
+// before the last writes each item as one 32-bit word, the last digit above
+// the 24-bit index, which the last pass moves alone (4 bytes per item instead
+// of a key and a value); else a 32-bit key and a 32-bit value, the index
+// within the side, throughout.
 struct SortKey {
     int mbits, passes;
+    bool narrow;
     int bits() const { return mbits; }
+    // bytes an item moves through the scatter passes: 16 per full pass
+    // (key and value read and written), 12 for the last full pass (no keys
+    // written) or the narrowing pass (one word written), 8 for a word pass
+    int scatter_bytes() const { return narrow ? 16 * (passes - 2) + 12 + 8 : 16 * (passes - 1) + 12; }
 };
 SortKey sort_key(int64_t max_row_items);
 // Morton keys of both sides (the same launch starts the row states from the

@@ -478,7 +478,7 @@ __device__ __forceinline__ SBlock sort_block_entry(const SortSeg &S, int64_t b, 
     k.i0 = (k.side ? S.ntA : 0) + k.t0;
     k.hstride = (int)(s1 - s0);
     k.hbase = 256 * ((k.side ? S.nbA : 0) + s0) + j;
-    k.pad = 0;
+    k.loc = (int32_t)(j * S.rsi);
     return k;
 }
 
@@ -504,8 +504,9 @@ __global__ __launch_bounds__(256) void k_sort_table(SortSeg S) {
 // codes the block's row box is merged once, by each wave, while those loads
 // are in flight.
 // The same launch starts every row's state from the merged row boxes (one
-// wave per row).
-template <int RS_ITEMS, bool VC>
+// wave per row).  LOC: values are the triangle's index within its row (else
+// within its side).
+template <int RS_ITEMS, bool VC, bool LOC>
 __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, SortSeg S, int mbits,
                                                  uint32_t *keys, int32_t *vals, uint32_t *hist,
                                                  int rep, int64_t G, RowState *rows, uint32_t *flags) {
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         if (!VC) code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
         const uint32_t key = code[r] >> (30 - mbits);
         keys[k.i0 + j] = key;
-        vals[k.i0 + j] = (int32_t)(k.t0 + j);
+        vals[k.i0 + j] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
         atomicAdd(&h[key & 255u], 1u);
     }
     __syncthreads();
@@ -669,7 +670,11 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
 // digit order and writes each digit's run to consecutive global addresses.
 // With at most 256 scan chunks the block scans the chunk totals itself
 // (ncraw > 0: part holds raw totals), which saves the top-level scan launch.
-template <int RS_ITEMS>
+// MODE 0: key and value in, key and value out (kout == nullptr: the last
+// pass's keys, which nothing reads, are not written); MODE 1: key and value
+// in, one word out (the next digit above the 24-bit value); MODE 2: words in
+// and out (the digit is the top byte).
+template <int RS_ITEMS, int MODE>
 __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout,
                                                  int32_t *vout, SortSeg S, int shift,
                                                  const uint32_t *hist, const uint32_t *part, int ncraw) {
@@ -680,7 +685,8 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     __shared__ uint32_t gbase[256];   // global position of the block's first item of each digit
     __shared__ uint32_t loff[256];    // block-local position of each digit's first item
     __shared__ KT skey[RS_ITEMS];
-    __shared__ int32_t sval[RS_ITEMS];
+    constexpr bool V = MODE < 2;  // separate values in
+    __shared__ int32_t sval[V ? RS_ITEMS : 1];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const SBlock sbk = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const int64_t b0 = sbk.i0;
@@ -713,7 +719,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     for (int r = 0; r < R; r++) {
         int64_t i = b0 + w * Q + r * 64 + lane;
         key[r] = i < n ? kin[i] : (KT)0;
-        val[r] = i < n ? vin[i] : 0;
+        if (V) val[r] = i < n ? vin[i] : 0;
     }
     for (int r = 0; r < R; r++) {
         int64_t i = b0 + w * Q + r * 64 + lane;
@@ -754,7 +760,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
         uint32_t d = (uint32_t)((key[r] >> shift) & 255);
         uint32_t slot = wc[w][d] + rk[r];
         skey[slot] = key[r];
-        sval[slot] = val[r];
+        if (V) sval[slot] = val[r];
     }
     __syncthreads();
     const int nvalid = sbk.n;
@@ -762,32 +768,47 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
         KT k = skey[j];
         uint32_t d = (uint32_t)((k >> shift) & 255);
         uint32_t pos = gbase[d] + (uint32_t)j - loff[d];
-        kout[pos] = k;
-        vout[pos] = sval[j];
+        if (MODE == 1) {
+            kout[pos] = ((k >> (shift + 8)) & 255u) << 24 | (uint32_t)sval[j];
+        } else {
+            if (MODE == 2 || kout) kout[pos] = k;
+            if (MODE == 0) vout[pos] = sval[j];
+        }
     }
 }
 
-// Sort (keys[0], vals[0]) within rows by the low `bits` bits; result in
-// keys[res], vals[res].  The first pass's histogram is already in `hist`
-// (from the key kernel).
+// Sort (keys[0], vals[0]) within rows by K's key bits; result in keys[res]
+// (narrow sorts: words) or vals[res].  The first pass's histogram is already
+// in `hist` (from the key kernel).
 template <int RS_ITEMS>
 static int radix_sort(uint32_t **keys, int32_t **vals, uint32_t *hist, uint32_t *part, const SortSeg &S,
-                      int bits, hipStream_t s, KernelEvents *kev) {
+                      const SortKey &K, hipStream_t s, KernelEvents *kev) {
     int cur = 0;
     if (S.nb == 0) return cur;
     const int nb = (int)S.nb;
     int64_t total = (int64_t)nb * 256;
     int nchunk = (int)((total + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    for (int shift = 0; shift < bits; shift += 8) {
-        if (shift > 0)
+    for (int p = 0; p < K.passes; p++) {
+        const bool last = p == K.passes - 1;
+        const int mode = !K.narrow ? 0 : last ? 2 : p == K.passes - 2 ? 1 : 0;
+        const int shift = mode == 2 ? 24 : 8 * p;
+        if (p > 0)
             hipLaunchKernelGGL((k_hist<RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], S, shift, hist);
         hipLaunchKernelGGL(k_scan_local, dim3(nchunk), dim3(1024), 0, s, hist, total, part);
         const bool inline_top = nchunk <= 256;
         if (!inline_top)
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
-        hipLaunchKernelGGL((k_scatter<RS_ITEMS>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], S, shift, hist, part, inline_top ? nchunk : 0);
+        const int ncr = inline_top ? nchunk : 0;
+        if (mode == 2)
+            hipLaunchKernelGGL((k_scatter<RS_ITEMS, 2>), dim3(nb), dim3(256), 0, s, keys[cur], nullptr,
+                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr);
+        else if (mode == 1)
+            hipLaunchKernelGGL((k_scatter<RS_ITEMS, 1>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr);
+        else
+            hipLaunchKernelGGL((k_scatter<RS_ITEMS, 0>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
+                               last ? nullptr : keys[cur ^ 1], vals[cur ^ 1], S, shift, hist, part, ncr);
         if (kev) kev->end(KE_SCATTER, s);
         cur ^= 1;
     }
@@ -802,7 +823,9 @@ struct TileJob {
     const int64_t *v_off, *t_off, *tile_off;
     int64_t G, NT;
     int tk;
-    const int32_t *sorted;
+    const int32_t *sorted;  // sorted items: triangle index within the side, or
+                            // (packed) digit << 24 | index within the row
+    int packed;
     float *t32;
     double *t64;   // FP64 copies, or nullptr: then ids
     int32_t *ids;  // triangle of each slot
@@ -833,7 +856,10 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
     int64_t tri_id[2] = {0, 0}, vi[2][3];
 #pragma unroll
     for (int r = 0; r < 2; r++)
-        if (r == 0 || two) tri_id[r] = J.sorted[J.t_off[g] + i * tk + min(lane + 64 * r, n - 1)];
+        if (r == 0 || two) {
+            const int32_t w = J.sorted[J.t_off[g] + i * tk + min(lane + 64 * r, n - 1)];
+            tri_id[r] = J.packed ? J.t_off[g] + (w & 0xffffff) : w;
+        }
 #pragma unroll
     for (int r = 0; r < 2; r++)
 #pragma unroll
@@ -924,6 +950,7 @@ SortKey sort_key(int64_t max_row_items) {
     SortKey K;
     K.passes = max_row_items <= ((int64_t)1 << 18) ? 2 : 3;
     K.mbits = 8 * K.passes;
+    K.narrow = max_row_items <= ((int64_t)1 << 24);
     return K;
 }
 
@@ -945,9 +972,13 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
         hipLaunchKernelGGL(k_sort_table, dim3(grid_for(P.seg.nb, 256)), dim3(256), 0, s, P.seg);
     // at least one block: the key kernel also starts the row states
     const int grid = P.seg.nb > 0 ? (int)P.seg.nb : 1;
-    hipLaunchKernelGGL((k_morton<RSI, VC>), dim3(grid), dim3(1024), 0, s, ma, mb, P.seg, K.mbits,
-                       P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows, P.flags);
-    return radix_sort<RSI>(P.keys, P.vals, P.hist, P.part, P.seg, K.bits(), s, kev);
+    if (K.narrow)
+        hipLaunchKernelGGL((k_morton<RSI, VC, true>), dim3(grid), dim3(1024), 0, s, ma, mb, P.seg, K.mbits,
+                           P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows, P.flags);
+    else
+        hipLaunchKernelGGL((k_morton<RSI, VC, false>), dim3(grid), dim3(1024), 0, s, ma, mb, P.seg, K.mbits,
+                           P.keys[0], P.vals[0], P.hist, A.boxrep, A.G, rows, P.flags);
+    return radix_sort<RSI>(P.keys, P.vals, P.hist, P.part, P.seg, K, s, kev);
 }
 
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
@@ -960,9 +991,11 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
                                           : sort_items<2 * RS_ITEMS>(A, B, P, K, rows, s, kev);
     if (kev) kev->begin(KE_TILES, s);
     if (A.NT + B.NT > 0) {
-        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, P.vals[cur], A.t32,
+        const int32_t *sorted = K.narrow ? (const int32_t *)P.keys[cur] : P.vals[cur];
+        const int pk = K.narrow ? 1 : 0;
+        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, sorted, pk, A.t32,
                    A.t64, A.ids, A.meta};
-        TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, P.vals[cur] + A.nt,
+        TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, sorted + A.nt, pk,
                    B.t32, B.t64, B.ids, B.meta};
         // one slot per lane below 128-triangle tiles: fewer registers, more
         // waves in flight for the gathers

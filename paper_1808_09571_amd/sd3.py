@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 7),
                 ("logged", ctypes.c_int64), ("ms_kernel", ctypes.c_double * 4),
                 ("n_kernel", ctypes.c_int64 * 4), ("sort_items", ctypes.c_int64),
-                ("sort_key_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("sort_item_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("queue_passes", ctypes.c_int32),
                 ("queue_skew", ctypes.c_int64), ("fallback", ctypes.c_int32),
                 ("reserved32", ctypes.c_int32)]
