@@ -178,6 +178,8 @@ typedef struct sd3_stats {
                                       list by the plain FP64 pass (same bits),
                                       a full exact list with a 4x longer one */
     int32_t reserved32;
+    int64_t tiles_copied;          /* tiles whose coordinate copies were written
+                                      (only tiles of queued tile pairs get them) */
 } sd3_stats;
 
 typedef struct sd3_ctx sd3_ctx;

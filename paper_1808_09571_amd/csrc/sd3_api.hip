@@ -69,7 +69,7 @@ void release(DevBuf &b) {
 }
 
 struct SideState {
-    DevBuf xyz, tri, rowbox, t32, t64, ids, meta;
+    DevBuf xyz, tri, rowbox, t32, t64, ids, meta, mat;
 };
 
 constexpr unsigned int QUEUE_BUDGET = 1u << 29;   // tile pairs per queue pass (12 B each)
@@ -130,7 +130,7 @@ struct Workspace {
     }
     void release_all() {
         for (auto &sd : side) {
-            DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta};
+            DevBuf *bs[] = {&sd.xyz, &sd.tri, &sd.rowbox, &sd.t32, &sd.t64, &sd.ids, &sd.meta, &sd.mat};
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
@@ -454,12 +454,14 @@ void setup_side(Workspace &ws, int which, const sd3_geoms *g, int64_t NT, int tk
     const int64_t rep_room = std::max<int64_t>(rowbox_replicas((int64_t)1 << 40, G), 1);
     S.rowbox = (unsigned long long *)ws.buf(st.rowbox, sizeof(unsigned long long) * 6 * rep_room *
                                                            (G > 0 ? G : 1));
-    S.t32 = (float *)ws.buf(st.t32, sizeof(float) * 9 * tk * S.NT);
-    // FP64 tile copies only for the plain FP64 pass; the FP32 path keeps the
-    // triangle id of each slot and gathers FP64 vertices for its few rescues
+    // FP32 tile copies for the FP32 path, FP64 copies for the plain FP64
+    // pass (both written only for queued tiles); the triangle id of each
+    // slot for both (the FP32 path gathers FP64 vertices for its few rescues)
+    S.t32 = fp64 ? nullptr : (float *)ws.buf(st.t32, sizeof(float) * 9 * tk * S.NT);
     S.t64 = fp64 ? (double *)ws.buf(st.t64, sizeof(double) * 9 * tk * S.NT) : nullptr;
-    S.ids = fp64 ? nullptr : (int32_t *)ws.buf(st.ids, sizeof(int32_t) * tk * S.NT);
+    S.ids = (int32_t *)ws.buf(st.ids, sizeof(int32_t) * tk * S.NT);
     S.meta = (TileMeta *)ws.buf(st.meta, sizeof(TileMeta) * S.NT);
+    S.mat = (uint32_t *)ws.buf(st.mat, sizeof(uint32_t) * S.NT);
 }
 
 // Plans a call: tiles and work items per row, buffer sizes in `ws`, offsets
@@ -656,6 +658,7 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
         if (kev) kev->begin(KE_FILTER, s);
         launch_queue(A, B, Q, nw, w0, C.rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s, rank);
         if (kev) kev->end(KE_FILTER, s);
+        launch_materialize(A, B, L, prec, ctx->cus * 16, s);
         if (learned) launch_rank(A, B, C.rows, L, C.opts.ranker, ctx->cus * 2, s);
         // at most one seed per row
         if (C.seed) launch_pairs(A, B, C.rows, LS, prec, mode, (int)std::min<int64_t>(C.grid_pairs, G), s);
@@ -720,6 +723,7 @@ void fill_counts(const Call &C, const unsigned int *sc_h, const unsigned long lo
     stats->tile = C.P.tk;
     stats->queue_passes = C.passes;
     stats->queue_skew = (int64_t)cnt_h[C_SKEW];
+    stats->tiles_copied = (int64_t)cnt_h[C_COPIED];
 }
 
 sd3_status device_error(sd3_ctx *ctx, const HipError &e) {

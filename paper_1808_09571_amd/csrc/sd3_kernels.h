@@ -20,9 +20,12 @@ struct SideBufs {
     unsigned long long *rowbox;  // [boxrep][G*6] ordered bits: lo xyz (min), hi xyz (max);
                                  // replica 0 holds the merged box after validation
     float *t32;                  // [NT*9*tk]: tile t, coordinate c, slot j at (t*9+c)*tk+j
+                                 // (FP32 path), or nullptr
     double *t64;                 // [NT*9*tk] exact copies (plain FP64 path), or nullptr
-    int32_t *ids;                // [NT*tk] triangle of each slot (FP32 path), or nullptr
+    int32_t *ids;                // [NT*tk] triangle of each slot
     TileMeta *meta;              // [NT]
+    uint32_t *mat;               // [NT] 0 until the tile's copies (t32 or t64) are written
+                                 // (large calls: only tiles of queued tile pairs get them)
 };
 
 // Optional HIP-event brackets around selected kernel launches (timing mode):
@@ -100,6 +103,7 @@ enum Counter : int {
     C_EXACT_OVF = 9,
     C_LOGGED = 10,
     C_SKEW = 11,  // waves that found the block's queue entry changed under them
+    C_COPIED = 12,  // tiles whose coordinate copies were written
     C_NCOUNTERS = 16,
 };
 
@@ -169,6 +173,11 @@ SortKey sort_key(int64_t max_row_items);
 // merged row boxes), the radix sort and the tiles.
 void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowState *rows,
                  hipStream_t s, KernelEvents *kev);
+// The FP32 (prec 0) or FP64 copies of every tile named by a queued tile pair
+// that has none yet (the tile build of a large call writes only metadata and
+// slot ids; a small call's tile build writes every copy, and this launches
+// nothing).
+void launch_materialize(SideBufs &A, SideBufs &B, const Lists &L, int prec, int grid, hipStream_t s);
 
 // Group boxes (A block of 64 tiles / B chunk of 256 tiles of one row).
 struct GroupBox {

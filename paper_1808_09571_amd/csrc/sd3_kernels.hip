@@ -815,8 +815,17 @@ static int radix_sort(uint32_t **keys, int32_t **vals, uint32_t *hist, uint32_t 
     return cur;
 }
 
-// Tiles: gather each tile's triangles in sorted order and write the FP64 and
-// FP32 SoA copies and the tile metadata.
+// Tiles: gather each tile's triangles in sorted order and write the slot
+// triangle ids and the tile metadata (box, origin, storage error bound).  The
+// coordinate copies of a large call are written later, for queued tiles only
+// (most tiles of a large call are never queued); a small call, whose time is
+// a chain of short launches, writes them here.
+constexpr int64_t LAZY_COPY_MIN_TILES = 16384;
+
+static bool lazy_copies(const SideBufs &A, const SideBufs &B) {
+    return A.NT + B.NT >= LAZY_COPY_MIN_TILES;
+}
+
 struct TileJob {
     const double *xyz;
     const int32_t *tri;
@@ -826,10 +835,11 @@ struct TileJob {
     const int32_t *sorted;  // sorted items: triangle index within the side, or
                             // (packed) digit << 24 | index within the row
     int packed;
-    float *t32;
-    double *t64;   // FP64 copies, or nullptr: then ids
     int32_t *ids;  // triangle of each slot
     TileMeta *meta;
+    uint32_t *mat;  // 0: no copies yet, 1: written here
+    float *t32;     // copies written here (small calls), else nullptr
+    double *t64;
 };
 
 // Lane l of the wave owns slots l and l + 64 (the second only for tk = 128);
@@ -877,10 +887,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
     for (int r = 0; r < 2; r++) {
         const int j = lane + 64 * r;
         if (j < tk) {
-            if (J.t64)
-                for (int c = 0; c < 9; c++) J.t64[(t * 9 + c) * tk + j] = v[r][c];
-            else
-                J.ids[t * tk + j] = (int32_t)tri_id[r];
+            J.ids[t * tk + j] = (int32_t)tri_id[r];
             for (int k = 0; k < 3; k++) {
                 lo[k] = fmin(lo[k], fmin(v[r][k], fmin(v[r][3 + k], v[r][6 + k])));
                 hi[k] = fmax(hi[k], fmax(v[r][k], fmax(v[r][3 + k], v[r][6 + k])));
@@ -892,21 +899,33 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
         hi[k] = wave_max(hi[k]);
         o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
     }
-    // FP32 copies of the offsets from the origin; rad = their largest
-    // magnitude over the tile
-    float rad32 = 0.0f;
+    // rad = the largest magnitude of the tile's FP32 offsets from the origin,
+    // (float)(x - o): rounding to FP32 is monotone and odd, so it is the
+    // largest FP64 offset magnitude rounded once
+    double dmax = 0.0;
 #pragma unroll
     for (int r = 0; r < 2; r++) {
         const int j = lane + 64 * r;
         if (j >= tk) continue;
 #pragma unroll
-        for (int c = 0; c < 9; c++) {
-            const float f = (float)(v[r][c] - o[c % 3]);
-            J.t32[(t * 9 + c) * tk + j] = f;
-            rad32 = fmaxf(rad32, fabsf(f));
+        for (int c = 0; c < 9; c++) dmax = fmax(dmax, fabs(v[r][c] - o[c % 3]));
+    }
+    const double rad = (double)(float)wave_max(dmax);
+    if (J.t32 || J.t64) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int j = lane + 64 * r;
+            if (j >= tk) continue;
+#pragma unroll
+            for (int c = 0; c < 9; c++) {
+                const int64_t at = (t * 9 + c) * tk + j;
+                if (J.t32)
+                    J.t32[at] = (float)(v[r][c] - o[c % 3]);
+                else
+                    J.t64[at] = v[r][c];
+            }
         }
     }
-    const double rad = (double)wave_max(rad32);
     // Storage error of a coordinate: d = x - o is rounded to FP64 (relative
     // 2^-53) and then to FP32 (relative 2^-24, or 2^-150 absolute in the
     // subnormal range), so |f - d| <= (2^-24 + 2^-52) |d| + 2^-149 with
@@ -926,6 +945,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
         m.row = (int32_t)g;
         m.n = n;
         J.meta[t] = m;
+        J.mat[t] = (J.t32 || J.t64) ? 1u : 0u;
     }
 }
 
@@ -993,10 +1013,11 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
     if (A.NT + B.NT > 0) {
         const int32_t *sorted = K.narrow ? (const int32_t *)P.keys[cur] : P.vals[cur];
         const int pk = K.narrow ? 1 : 0;
-        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, sorted, pk, A.t32,
-                   A.t64, A.ids, A.meta};
+        const bool lazy = lazy_copies(A, B);
+        TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, sorted, pk, A.ids,
+                   A.meta, A.mat, lazy ? nullptr : A.t32, lazy ? nullptr : A.t64};
         TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, sorted + A.nt, pk,
-                   B.t32, B.t64, B.ids, B.meta};
+                   B.ids, B.meta, B.mat, lazy ? nullptr : B.t32, lazy ? nullptr : B.t64};
         // one slot per lane below 128-triangle tiles: fewer registers, more
         // waves in flight for the gathers
         if (A.tk > 64)
@@ -1005,6 +1026,139 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
             hipLaunchKernelGGL(k_tiles<false>, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
     }
     if (kev) kev->end(KE_TILES, s);
+}
+
+// Coordinate copies of the queued tiles.  Lane l of wave w takes queue
+// entries (64 k + l) W + w (W waves), so that a short queue spreads over many
+// waves; a lane claims each of its entry's two tiles by swapping its word to
+// 1, and the wave then writes the tiles whose claim returned 0, NG at a time
+// with the loads of all NG in flight together: slot ids, corner indices and
+// FP64 vertices gathered as in the tile build, written as FP32 offsets from
+// the tile's origin (PREC 0: the same values the tile's box and error bound
+// were computed from) or as the FP64 coordinates (PREC 1).
+struct MatSide {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off;
+    const int32_t *ids;
+    const TileMeta *meta;
+    float *t32;
+    double *t64;
+    uint32_t *mat;
+};
+
+// Up to NG tiles of one side taken from the wave's claim mask m (cleared as
+// they are taken); lane l's claimed tile is tl.
+template <int PREC, int TK, int NG>
+__device__ void mat_group(const MatSide &S, unsigned long long &m, int tl) {
+    constexpr int R = TK > 64 ? 2 : 1;
+    const int lane = lane_id();
+    int t[NG];
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        t[i] = -1;
+        if (m) {
+            t[i] = __builtin_amdgcn_readlane(tl, __ffsll((long long)m) - 1);
+            m &= m - 1;
+        }
+    }
+    int64_t vb[NG], id[NG][R];
+    int32_t vi[NG][R][3];
+    double v[NG][R][9];
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        vb[i] = 0;
+        if (t[i] < 0) continue;
+#pragma unroll
+        for (int r = 0; r < R; r++) id[i][r] = S.ids[(int64_t)t[i] * TK + min(lane + 64 * r, TK - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        if (t[i] < 0) continue;
+        const int64_t g = S.meta[t[i]].row;
+        vb[i] = S.v_off[g];
+        const int64_t nvr = S.v_off[g + 1] - vb[i];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) vi[i][r][k] = (int32_t)corner(S.tri, id[i][r], k, nvr);
+    }
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        if (t[i] < 0) continue;
+        const double *X = S.xyz + 3 * vb[i];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double *p = X + 3 * (int64_t)vi[i][r][k];
+                v[i][r][3 * k] = p[0];
+                v[i][r][3 * k + 1] = p[1];
+                v[i][r][3 * k + 2] = p[2];
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        if (t[i] < 0) continue;
+        const TileMeta &mt = S.meta[t[i]];
+        const double o[3] = {mt.o[0], mt.o[1], mt.o[2]};
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int j = lane + 64 * r;
+            if (j >= TK) continue;
+#pragma unroll
+            for (int c = 0; c < 9; c++) {
+                const int64_t at = ((int64_t)t[i] * 9 + c) * TK + j;
+                if (PREC == 0)
+                    S.t32[at] = (float)(v[i][r][c] - o[c % 3]);
+                else
+                    S.t64[at] = v[i][r][c];
+            }
+        }
+    }
+}
+
+template <int PREC, int TK>
+__global__ __launch_bounds__(256) void k_materialize(MatSide A, MatSide B, Lists L) {
+    constexpr int NG = TK > 64 ? 2 : 4;
+    const int64_t n = min(*L.qcount, L.qcap);
+    const int lane = lane_id();
+    const int64_t W = (int64_t)gridDim.x * 4, w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (int64_t k = 0; k * 64 * W + w < n; k++) {
+        const int64_t e = (k * 64 + lane) * W + w;
+        int ta = -1, tb = -1;
+        if (e < n) {
+            const int2 q = L.queue[e];
+            ta = q.x;
+            tb = q.y;
+        }
+        // a plain read first: most tiles of a busy queue were claimed already
+        const bool ca = ta >= 0 && A.mat[ta] == 0u && atomicExch(&A.mat[ta], 1u) == 0u;
+        const bool cb = tb >= 0 && B.mat[tb] == 0u && atomicExch(&B.mat[tb], 1u) == 0u;
+        unsigned long long ma = __ballot(ca), mb = __ballot(cb);
+        if ((ma | mb) && lane == 0)
+            atomicAdd(&L.counters[C_COPIED], (unsigned long long)(__popcll(ma) + __popcll(mb)));
+        while (ma) mat_group<PREC, TK, NG>(A, ma, ta);
+        while (mb) mat_group<PREC, TK, NG>(B, mb, tb);
+    }
+}
+
+void launch_materialize(SideBufs &A, SideBufs &B, const Lists &L, int prec, int grid, hipStream_t s) {
+    if (A.NT == 0 || B.NT == 0 || !lazy_copies(A, B)) return;
+    const MatSide ma{A.xyz, A.tri, A.v_off, A.ids, A.meta, A.t32, A.t64, A.mat};
+    const MatSide mb{B.xyz, B.tri, B.v_off, B.ids, B.meta, B.t32, B.t64, B.mat};
+    const dim3 gr(grid), bl(256);
+#define SD3_MAT(P, T) hipLaunchKernelGGL((k_materialize<P, T>), gr, bl, 0, s, ma, mb, L)
+    if (prec == 0) {
+        if (A.tk == 128) SD3_MAT(0, 128);
+        else if (A.tk == 64) SD3_MAT(0, 64);
+        else SD3_MAT(0, 32);
+    } else {
+        if (A.tk == 128) SD3_MAT(1, 128);
+        else if (A.tk == 64) SD3_MAT(1, 64);
+        else SD3_MAT(1, 32);
+    }
+#undef SD3_MAT
 }
 
 // ---------------------------------------------------------------------------

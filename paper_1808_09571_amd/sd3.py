@@ -66,7 +66,7 @@ class Stats(ctypes.Structure):
                 ("sort_item_bytes", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("queue_passes", ctypes.c_int32),
                 ("queue_skew", ctypes.c_int64), ("fallback", ctypes.c_int32),
-                ("reserved32", ctypes.c_int32)]
+                ("reserved32", ctypes.c_int32), ("tiles_copied", ctypes.c_int64)]
 
     KERNELS = ("scatter", "tiles", "filter", "pairs")
 
