@@ -57,11 +57,16 @@ FLOPS_FP32_PAIR = 711   # full FP32 triangle-pair test: 9 edge/edge, 6 vertex/fa
 FLOPS_BOX = 12          # triangle bounding-box lower bound per boxed pair
 FLOPS_TRI_PREP = 64     # per staged triangle (edges, reciprocals, dual basis, box)
 # Algorithmic bytes of tile building on the FP32 path: per triangle the sorted
-# index 4 and the triangle indices 12 (read), the FP32 copy 36 and the slot
-# triangle id 4 (written); per vertex its FP64 coordinates 24, read once (a
-# vertex is shared by the triangles around it)
-BYTES_TILE_TRI = 4 + 12 + 36 + 4
+# item 4 and the triangle indices 12 (read) and the slot triangle id 4
+# (written), plus the FP32 copy 36 (written) in calls of fewer than
+# LAZY_COPY_MIN_TILES tiles (larger calls write the copies of queued tiles
+# only, in a later kernel); per vertex its FP64 coordinates 24, read once (a
+# vertex is shared by the triangles around it); per tile its 112-byte metadata
+BYTES_TILE_TRI = 4 + 12 + 4
+BYTES_TILE_COPY = 36
 BYTES_TILE_VTX = 24
+BYTES_TILE_META = 112
+LAZY_COPY_MIN_TILES = 16384
 VOL_BYTES_TRI = 12 + 72  # volume: triangle indices and three FP64 vertices
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
@@ -178,7 +183,9 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
         # one launch builds the tiles of both sides: every sorted item; the
         # step's launches use the two queries' tile sizes
         tris = float(st_list[0]["sort_items"])
-        per = tris * BYTES_TILE_TRI + float(nverts) * BYTES_TILE_VTX
+        ntiles = tris / st_list[0]["tile"]
+        per_tri = BYTES_TILE_TRI + (BYTES_TILE_COPY if ntiles < LAZY_COPY_MIN_TILES else 0)
+        per = tris * per_tri + float(nverts) * BYTES_TILE_VTX + ntiles * BYTES_TILE_META
         ach = per / (avg * 1e-3) / 1e9
         # (k_tiles<true>: two slots per lane, the 128-triangle tiles)
         tr = [measured_traffic(f"k_tiles<{'true' if x['tile'] == 128 else 'false'}>", workload)
@@ -187,7 +194,8 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": None if None in tr else sum(tr) / len(tr),
                 "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per,
-                "per_unit": f"{BYTES_TILE_TRI} B per triangle + {BYTES_TILE_VTX} B per vertex"}
+                "per_unit": f"{per_tri} B per triangle + {BYTES_TILE_VTX} B per vertex + "
+                            f"{BYTES_TILE_META} B per tile"}
     raise KeyError(kernel)
 
 
