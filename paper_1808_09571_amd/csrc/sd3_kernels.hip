@@ -204,17 +204,18 @@ __device__ __forceinline__ int64_t lane_row(const int64_t *off, int64_t G, int64
 }
 
 // Row bounding boxes of all vertices.  Each block owns a contiguous range of
-// vertices and keeps running per-thread min/max while its chunks stay inside
-// one row; it reduces over the block and issues one atomic per component only
-// when the row changes (rows are contiguous), so large rows cost a few atomics
-// per block instead of one per wave.
-__device__ void rowbox_flush(int64_t g, unsigned long long *lo, unsigned long long *hi,
-                             unsigned long long (*red)[6], unsigned long long *box) {
+// vertices and keeps running per-thread min/max (FP64) while its chunks stay
+// inside one row; it reduces over the block and issues one atomic per
+// component (on the order-preserving bits) only when the row changes (rows
+// are contiguous), so large rows cost a few atomics per block instead of one
+// per wave.
+__device__ void rowbox_flush(int64_t g, double *lo, double *hi, unsigned long long (*red)[6],
+                             unsigned long long *box) {
     for (int k = 0; k < 3; k++) {
-        unsigned long long a = wave_min(lo[k]), b = wave_max(hi[k]);
+        const double a = wave_min(lo[k]), b = wave_max(hi[k]);
         if (lane_id() == 0) {
-            red[threadIdx.x >> 6][k] = a;
-            red[threadIdx.x >> 6][3 + k] = b;
+            red[threadIdx.x >> 6][k] = ordered_bits(a);
+            red[threadIdx.x >> 6][3 + k] = ordered_bits(b);
         }
     }
     __syncthreads();
@@ -230,8 +231,39 @@ __device__ void rowbox_flush(int64_t g, unsigned long long *lo, unsigned long lo
     }
     __syncthreads();
     for (int k = 0; k < 3; k++) {
-        lo[k] = ~0ull;
-        hi[k] = 0ull;
+        lo[k] = __builtin_inf();
+        hi[k] = -__builtin_inf();
+    }
+}
+
+// A chunk that crosses rows: each wave reduces per row it touches (a wave's
+// lanes hold consecutive vertices, so a few rows at most) and issues one
+// atomic per row and component; a wave over more than four rows (rows of a
+// few vertices) lets every lane issue its own.
+__device__ void rowbox_split(const double (&x)[3], bool valid, int64_t g, unsigned long long *box) {
+    const int64_t gl = valid ? g : INT64_MAX, gh = valid ? g : -1;
+    const int64_t w0 = wave_min(gl), w1 = wave_max(gh);
+    if (w1 < 0) return;
+    if (w1 - w0 > 3) {
+        if (valid)
+            for (int k = 0; k < 3; k++) {
+                const unsigned long long v = ordered_bits(x[k]);
+                atomicMin(&box[g * 6 + k], v);
+                atomicMax(&box[g * 6 + 3 + k], v);
+            }
+        return;
+    }
+    for (int64_t r = w0; r <= w1; r++) {
+        const bool in = valid && g == r;
+        if (!__ballot(in)) continue;
+        for (int k = 0; k < 3; k++) {
+            const double a = wave_min(in ? x[k] : __builtin_inf());
+            const double b = wave_max(in ? x[k] : -__builtin_inf());
+            if (lane_id() == 0) {
+                atomicMin(&box[r * 6 + k], ordered_bits(a));
+                atomicMax(&box[r * 6 + 3 + k], ordered_bits(b));
+            }
+        }
     }
 }
 
@@ -251,7 +283,11 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
     const int64_t nv = S.nv;
     int64_t per = ((nv + S.nblk - 1) / S.nblk + 255) / 256 * 256;
     int64_t b0 = blk * per, b1 = min(nv, b0 + per);
-    unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; k++) {
+        lo[k] = __builtin_inf();
+        hi[k] = -__builtin_inf();
+    }
     uint32_t f = 0;
     int64_t cur = -1;
     // the rows of each chunk's first and last vertex, walked forward (rows
@@ -282,35 +318,29 @@ __device__ void rowbox_side(const XyzSide &S, int64_t G, unsigned blk, uint32_t 
             }
             if (valid)
                 for (int k = 0; k < 3; k++) {
-                    unsigned long long v = ordered_bits(x[k]);
-                    lo[k] = min(lo[k], v);
-                    hi[k] = max(hi[k], v);
+                    lo[k] = fmin(lo[k], x[k]);
+                    hi[k] = fmax(hi[k], x[k]);
                 }
         } else {
             if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
             cur = -1;
-            if (valid) {
-                const int64_t g = lane_row(S.v_off, G, g0, g1, i);
-                for (int k = 0; k < 3; k++) {
-                    unsigned long long v = ordered_bits(x[k]);
-                    atomicMin(&box[g * 6 + k], v);
-                    atomicMax(&box[g * 6 + 3 + k], v);
-                }
-            }
+            rowbox_split(x, valid, valid ? lane_row(S.v_off, G, g0, g1, i) : -1, box);
         }
     }
     if (cur >= 0) rowbox_flush(cur, lo, hi, red, box);
     if (f) atomicOr(flag, f);
 }
 
-// Blocks [0, A.nblk) take side A's vertices, then B's vertices, then the
-// triangles of both sides.
-__global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, TriSide TA, TriSide TB,
-                                                int64_t G, uint32_t *flags) {
-    const unsigned nvb = A.nblk + B.nblk;
+// Blocks [0, A.nblk) take side A's vertices, then B's vertices.
+__global__ __launch_bounds__(256) void k_rowbox(XyzSide A, XyzSide B, int64_t G, uint32_t *flags) {
     if (blockIdx.x < A.nblk) rowbox_side(A, G, blockIdx.x, flags);
-    else if (blockIdx.x < nvb) rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
-    else validate_tris(TA, TB, G, blockIdx.x - nvb, flags);
+    else rowbox_side(B, G, blockIdx.x - A.nblk, flags + 1);
+}
+
+// The triangles of both sides (A's blocks first); a launch of its own, so
+// that the vertex pass keeps its few registers.
+__global__ __launch_bounds__(256) void k_validate_tris(TriSide TA, TriSide TB, int64_t G, uint32_t *flags) {
+    validate_tris(TA, TB, G, blockIdx.x, flags);
 }
 
 static unsigned rowbox_blocks(int64_t nv) {
@@ -337,9 +367,10 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
     // (without `indices` the key kernel checks the triangle indices)
     TriSide ta{A.tri, A.nt, A.v_off, A.t_off, indices ? grid_for(A.nt, VT_ITEMS) : 0u};
     TriSide tb{B.tri, B.nt, B.v_off, B.t_off, indices ? grid_for(B.nt, VT_ITEMS) : 0u};
-    const unsigned nblk = xa.nblk + xb.nblk + ta.nblk + tb.nblk;
-    if (nblk > 0)
-        hipLaunchKernelGGL(k_rowbox, dim3(nblk), dim3(256), 0, s, xa, xb, ta, tb, G, flags);
+    if (xa.nblk + xb.nblk > 0)
+        hipLaunchKernelGGL(k_rowbox, dim3(xa.nblk + xb.nblk), dim3(256), 0, s, xa, xb, G, flags);
+    if (ta.nblk + tb.nblk > 0)
+        hipLaunchKernelGGL(k_validate_tris, dim3(ta.nblk + tb.nblk), dim3(256), 0, s, ta, tb, G, flags);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -1703,7 +1734,7 @@ __device__ __forceinline__ void global_push(bool keep, const T &item, T *arr, un
 
 constexpr int QB = 16;      // most queue entries a wave claims at once
 constexpr int RING = 128;   // LDS ring of triangle pairs awaiting their test (two batches)
-constexpr int TLCAP = 256;  // FP32 pairs awaiting the rescue decision of their tile pair
+constexpr int TLCAP = 192;  // FP32 pairs awaiting the rescue decision of their tile pair
 constexpr unsigned RCHUNK = 128;  // rescue-list slots a wave claims at once
 
 // Lane i's value in every lane (i wave-uniform): v_readlane into a scalar.
