@@ -54,6 +54,15 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
     return x * q + min(x, r) + k;
 }
 
+// LDS written by some lanes of a wave and read by others: the wave's LDS
+// operations complete in issue order, so keeping the compiler from moving
+// them across this point is all that is needed (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Vertex index of corner k of triangle t, local to its row of nvr vertices.
 // An index outside the row reads vertex 0 instead: kernels that run before the
 // validation flags are read (graph replays) never address memory outside the
@@ -989,6 +998,143 @@ __global__ void k_tiles(TileJob A, TileJob B) {
     else if (t - A.NT < B.NT) tile_one<TWO>(B, t - A.NT);
 }
 
+// The tile build of a large call (no copies): the tile's box, origin and
+// radius need each of its vertices once, and a tile's triangles share most of
+// them (about 40 distinct vertices for 64 triangles), so the wave gathers its
+// distinct vertices only.  The slots' corner indices go into a hash table in
+// the wave's LDS (linear probing, compare-and-swap from an empty key), the
+// occupied entries are numbered with ballots, and lane u loads distinct
+// vertex u: one 24-byte gather per distinct vertex instead of one per corner
+// (the address unit, which takes one cache access per cycle, bounded the
+// per-corner gathers).  R slots per lane (R = 2: 128-triangle tiles).
+constexpr uint32_t HASH_EMPTY = 0xffffffffu;
+
+template <int R>
+__device__ void tile_meta_one(const TileJob &J, int64_t t, uint32_t *hk, int32_t *uv) {
+    constexpr int HS = 256 * R;        // table entries (at most 3 * 64 R keys)
+    constexpr int NU = 3 * R;          // rounds of 64 distinct vertices at most
+    const int lane = lane_id(), tk = J.tk;
+    const int64_t g = wave_find_row(J.tile_off, J.G, t);
+    const int64_t i = t - J.tile_off[g];
+    const int64_t ntr = J.t_off[g + 1] - J.t_off[g];
+    const int n = (int)min((int64_t)tk, ntr - i * tk);
+    const double *X = J.xyz + 3 * J.v_off[g];
+    const int64_t nvr = J.v_off[g + 1] - J.v_off[g];
+    int64_t tri_id[R];
+    uint32_t c[R][3];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int32_t w = J.sorted[J.t_off[g] + i * tk + min(lane + 64 * r, n - 1)];
+        tri_id[r] = J.packed ? J.t_off[g] + (w & 0xffffff) : w;
+    }
+#pragma unroll
+    for (int q = 0; q < HS / 64; q++) hk[q * 64 + lane] = HASH_EMPTY;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) c[r][k] = (uint32_t)corner(J.tri, tri_id[r], k, nvr);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = lane + 64 * r;
+        if (j < tk) J.ids[t * tk + j] = (int32_t)tri_id[r];
+    }
+    wave_lds_sync();
+    // insert every slot's corners (slots past tk are left out); the table
+    // holds at most 3/4 of its size in keys, so every probe ends
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (lane + 64 * r >= tk) continue;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint32_t key = c[r][k];
+            uint32_t h = (key * 2654435761u) >> (32 - (R == 2 ? 9 : 8));
+            for (;;) {
+                const uint32_t old = atomicCAS(&hk[h], HASH_EMPTY, key);
+                if (old == HASH_EMPTY || old == key) break;
+                h = (h + 1) & (HS - 1);
+            }
+        }
+    }
+    wave_lds_sync();
+    // number the distinct vertices in table order
+    int nu = 0;
+#pragma unroll
+    for (int q = 0; q < HS / 64; q++) {
+        const uint32_t key = hk[q * 64 + lane];
+        const bool occ = key != HASH_EMPTY;
+        const unsigned long long m = __ballot(occ);
+        if (occ) uv[nu + __popcll(m & lanes_below())] = (int32_t)key;
+        nu += __popcll(m);
+    }
+    wave_lds_sync();
+    // gather them: lane u of round q holds distinct vertex 64 q + u
+    double p[NU][3];
+    double lo[3], hi[3], o[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        lo[k] = __builtin_inf();
+        hi[k] = -__builtin_inf();
+    }
+#pragma unroll
+    for (int q = 0; q < NU; q++) {
+        if (q * 64 >= nu) break;  // (wave-uniform)
+        const int u = q * 64 + lane;
+        const bool on = u < nu;
+        const double *pv = X + 3 * (int64_t)(on ? uv[u] : uv[0]);
+#pragma unroll
+        for (int k = 0; k < 3; k++) p[q][k] = pv[k];
+        if (on)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                lo[k] = fmin(lo[k], p[q][k]);
+                hi[k] = fmax(hi[k], p[q][k]);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        lo[k] = wave_min(lo[k]);
+        hi[k] = wave_max(hi[k]);
+        o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
+    }
+    // rad as in the copying build: the largest FP64 offset magnitude rounded
+    // once to FP32 (the same set of coordinates)
+    double dmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < NU; q++)
+        if (q * 64 + lane < nu)
+#pragma unroll
+            for (int k = 0; k < 3; k++) dmax = fmax(dmax, fabs(p[q][k] - o[k]));
+    const double rad = (double)(float)wave_max(dmax);
+    const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
+    // the representative vertex: corner 0 of slot 0, as in the copying build
+    const double *rv = X + 3 * (int64_t)__builtin_amdgcn_readfirstlane((int)c[0][0]);
+    if (lane == 0) {
+        TileMeta m;
+        for (int k = 0; k < 3; k++) {
+            m.o[k] = o[k];
+            m.lo[k] = lo[k];
+            m.hi[k] = hi[k];
+            m.rep[k] = rv[k];
+        }
+        m.eps = (float)(err * (1.0 + 0x1p-20));
+        m.rad = (float)rad;
+        m.row = (int32_t)g;
+        m.n = n;
+        J.meta[t] = m;
+        J.mat[t] = 0u;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_tiles_meta(TileJob A, TileJob B) {
+    __shared__ uint32_t hk[4][256 * R];
+    __shared__ int32_t uv[4][3 * 64 * R];
+    const int w = threadIdx.x >> 6;
+    int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (t < A.NT) tile_meta_one<R>(A, t, hk[w], uv[w]);
+    else if (t - A.NT < B.NT) tile_meta_one<R>(B, t - A.NT, hk[w], uv[w]);
+}
+
 // Both sides are sorted in one sequence of launches (each row's items stay in
 // the row's range).  Two 8-bit passes (16 Morton bits) while no row has more
 // than 2^18 triangles, else three (24 bits): the key only orders work, and
@@ -1051,10 +1197,17 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
                    B.ids, B.meta, B.mat, lazy ? nullptr : B.t32, lazy ? nullptr : B.t64};
         // one slot per lane below 128-triangle tiles: fewer registers, more
         // waves in flight for the gathers
-        if (A.tk > 64)
-            hipLaunchKernelGGL(k_tiles<true>, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
-        else
-            hipLaunchKernelGGL(k_tiles<false>, dim3(grid_for(A.NT + B.NT, 4)), dim3(256), 0, s, ja, jb);
+        const dim3 grid(grid_for(A.NT + B.NT, 4));
+        if (lazy) {
+            if (A.tk > 64)
+                hipLaunchKernelGGL(k_tiles_meta<2>, grid, dim3(256), 0, s, ja, jb);
+            else
+                hipLaunchKernelGGL(k_tiles_meta<1>, grid, dim3(256), 0, s, ja, jb);
+        } else if (A.tk > 64) {
+            hipLaunchKernelGGL(k_tiles<true>, grid, dim3(256), 0, s, ja, jb);
+        } else {
+            hipLaunchKernelGGL(k_tiles<false>, grid, dim3(256), 0, s, ja, jb);
+        }
     }
     if (kev) kev->end(KE_TILES, s);
 }
@@ -1751,14 +1904,6 @@ __device__ __forceinline__ double rl_d(double v, int i) {
     return __longlong_as_double((long long)rl_u64((unsigned long long)__double_as_longlong(v), i));
 }
 
-// LDS written by some lanes of a wave and read by others: the wave's LDS
-// operations complete in issue order, so keeping the compiler from moving
-// them across this point is all that is needed (no workgroup barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // A wave's share of the rescue list: it claims RCHUNK slots with one atomic
 // and fills them in order, so that most appends need no global atomic (and no
