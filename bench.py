@@ -187,9 +187,14 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
         per_tri = BYTES_TILE_TRI + (BYTES_TILE_COPY if ntiles < LAZY_COPY_MIN_TILES else 0)
         per = tris * per_tri + float(nverts) * BYTES_TILE_VTX + ntiles * BYTES_TILE_META
         ach = per / (avg * 1e-3) / 1e9
-        # (k_tiles<true>: two slots per lane, the 128-triangle tiles)
-        tr = [measured_traffic(f"k_tiles<{'true' if x['tile'] == 128 else 'false'}>", workload)
-              for x in st_list]
+        # kernel names: two slots per lane at 128-triangle tiles; large calls
+        # build metadata only (k_tiles_meta), small ones copies too (k_tiles)
+        def tile_kernel(x):
+            two = x["tile"] == 128
+            if x["sort_items"] / x["tile"] >= LAZY_COPY_MIN_TILES:
+                return f"k_tiles_meta<{2 if two else 1}>"
+            return f"k_tiles<{'true' if two else 'false'}>"
+        tr = [measured_traffic(tile_kernel(x), workload) for x in st_list]
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": None if None in tr else sum(tr) / len(tr),
