@@ -1742,8 +1742,11 @@ void launch_queue(const SideBufs &A, const SideBufs &B, const QueueGeo &Q, int64
 // ---------------------------------------------------------------------------
 // a4-a7: triangle-pair passes over the queue (persistent workgroups)
 // ---------------------------------------------------------------------------
-// Per-tile-pair constants of the FP32 pass (see sd3_pair32.h for the model):
-// the A tile is shifted into the B tile's frame; eps_c bounds how far the real
+// Per-tile-pair constants of the FP32 pass (see sd3_pair32.h for the model)
+// for tile a shifted into tile b's frame (the pair pass calls it with its B
+// tile as a, so that its A tile's staged copy is kept across consecutive
+// entries of the same A tile; the model is symmetric in the two tiles
+// otherwise); eps_c bounds how far the real
 // triangles are from their FP32 copies; eu / elb bound the evaluation error of
 // the upper / lower bounds; eo bounds the error of FP32 orientation values.
 struct TP32 {
@@ -1991,7 +1994,9 @@ __device__ __forceinline__ int wave_gather(Entry &E, const Lists &L, unsigned qc
             E.ub = bits_to_double(R.ub);
             E.msc = R.margin_scale;
             if (PREC == 0) {
-                const TP32 c = tp32_consts(a, b);
+                // B is shifted into A's frame, so that A's staged copy serves
+                // every consecutive entry of the same A tile
+                const TP32 c = tp32_consts(b, a);
                 E.sh0 = c.sh[0];
                 E.sh1 = c.sh[1];
                 E.sh2 = c.sh[2];
@@ -2020,8 +2025,9 @@ __device__ __forceinline__ double fp32_upper(float dm, float eu) {
 // one by one.  The global loads of the next live entry's two tiles (and of
 // its row's current upper bound) are issued as soon as the current entry is
 // staged, so they travel while the current entry is culled and tested.  Per
-// entry: both tiles staged into the wave's own LDS (FP32 copies shifted into
-// the B tile's frame, or FP64), a cull of 8 x 8 slot-group boxes, then of
+// entry: both tiles staged into the wave's own LDS (FP32 copies, the B tile
+// shifted into the A tile's frame, or FP64; the A tile is kept when the
+// previous entry staged the same one), a cull of 8 x 8 slot-group boxes, then of
 // triangle boxes, with the surviving triangle pairs compacted by ballots into
 // an LDS ring and tested 64 at a time, one pair per lane.  Distance: the wave
 // lowers the row bound with one atomic whose result it does not wait for,
@@ -2057,6 +2063,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
     const unsigned qb = max(1u, min((unsigned)QB, qcount / (nwave * 4u)));
     unsigned long long n_eval = 0, n_boxed = 0, n_tested = 0, n_resc = 0, n_exact = 0, n_bad = 0;
     RescueChunk rch;
+    int staged_a = -1;  // the A tile whose copy is in sA (wave-uniform)
     unsigned claim = blockIdx.x;
     for (;;) {
         const unsigned q0 = claim * qb;
@@ -2078,16 +2085,20 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
             }
             return true;
         };
-        // raw tile data of the entry staged next, and its row's upper bound
+        // raw tile data of the entry staged next (its A tile only when that
+        // is not the one staged already), and its row's upper bound
         Tt raw[NS][9];
         unsigned long long raw_ub = ~0ull;
         int pf = -1;
+        bool raw_keepA = false;
         auto load_raw = [&](int j) __attribute__((always_inline)) {
             const int ja = rl_i(E.ta, j), jb = rl_i(E.tb, j);
+            raw_keepA = ja == staged_a;
 #pragma unroll
             for (int s = 0; s < NS; s++) {
                 const int sl = s * 64 + lane;
                 const bool onB = sl >= TK;
+                if (!onB && raw_keepA) continue;
                 const int jj = onB ? sl - TK : sl;
                 const Tt *src = PREC == 0 ? (const Tt *)(onB ? t32B + (int64_t)jb * 9 * TK : t32A + (int64_t)ja * 9 * TK)
                                           : (const Tt *)(onB ? t64B + (int64_t)jb * 9 * TK : t64A + (int64_t)ja * 9 * TK);
@@ -2120,15 +2131,20 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
             }
             // stage both tiles from the raw registers: slot s of [A slots |
             // B slots], 64 at a time; each group of 8 consecutive slots (8
-            // lanes) reduces its box
+            // lanes) reduces its box.  An A tile that is already staged (the
+            // previous entry's) is kept: A stays in its own frame and B is
+            // shifted into it
+            const bool keepA = raw_keepA;
+            staged_a = ta;
 #pragma unroll
             for (int s = 0; s < NS; s++) {
                 const int sl = s * 64 + lane;
                 const bool onB = sl >= TK;
+                if (!onB && keepA) continue;
                 const int j = onB ? sl - TK : sl;
                 Tt *dst = onB ? sB : sA;
                 if (PREC == 0) {
-                    const float sx = onB ? 0.0f : sh[0], sy = onB ? 0.0f : sh[1], sz = onB ? 0.0f : sh[2];
+                    const float sx = onB ? sh[0] : 0.0f, sy = onB ? sh[1] : 0.0f, sz = onB ? sh[2] : 0.0f;
 #pragma unroll
                     for (int c = 0; c < 9; c++)
                         dst[c * TK + j] = (Tt)raw[s][c] + (Tt)(c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);

@@ -1,7 +1,8 @@
 // FP32 triangle-pair test with forward error bounds.
 //
-// The two triangles are FP32 copies expressed in the B tile's frame: every
-// real vertex lies within eps_c (a per-tile-pair bound) of its FP32 copy, so
+// The two triangles are FP32 copies expressed in one tile's frame (the other
+// tile shifted into it): every real vertex lies within eps_c (a per-tile-pair
+// bound) of its FP32 copy, so
 // distances between the real triangles and between the copies differ by at
 // most eps_c.  On the copies, every candidate is the vector between two
 // feasible points (clamped edge parameters, or a face foot whose barycentric
