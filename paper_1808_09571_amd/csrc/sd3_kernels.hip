@@ -724,9 +724,12 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     __shared__ uint32_t wc[4][256];   // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t gbase[256];   // global position of the block's first item of each digit
     __shared__ uint32_t loff[256];    // block-local position of each digit's first item
+    // staged items in digit order: MODE 0 keys and values, MODE 1 the output
+    // words and each item's digit (a byte), MODE 2 words
     __shared__ KT skey[RS_ITEMS];
     constexpr bool V = MODE < 2;  // separate values in
-    __shared__ int32_t sval[V ? RS_ITEMS : 1];
+    __shared__ int32_t sval[MODE == 0 ? RS_ITEMS : 1];
+    __shared__ uint8_t sdig[MODE == 1 ? RS_ITEMS : 1];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const SBlock sbk = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const int64_t b0 = sbk.i0;
@@ -799,20 +802,25 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
         if (rk[r] == 0xffffffffu) continue;
         uint32_t d = (uint32_t)((key[r] >> shift) & 255);
         uint32_t slot = wc[w][d] + rk[r];
-        skey[slot] = key[r];
-        if (V) sval[slot] = val[r];
+        if (MODE == 1) {
+            skey[slot] = ((key[r] >> (shift + 8)) & 255u) << 24 | (uint32_t)val[r];
+            sdig[slot] = (uint8_t)d;
+        } else {
+            skey[slot] = key[r];
+            if (MODE == 0) sval[slot] = val[r];
+        }
     }
     __syncthreads();
     const int nvalid = sbk.n;
     for (int j = tid; j < nvalid; j += 256) {
-        KT k = skey[j];
-        uint32_t d = (uint32_t)((k >> shift) & 255);
-        uint32_t pos = gbase[d] + (uint32_t)j - loff[d];
-        if (MODE == 1) {
-            kout[pos] = ((k >> (shift + 8)) & 255u) << 24 | (uint32_t)sval[j];
+        const KT k = skey[j];
+        const uint32_t d = MODE == 1 ? (uint32_t)sdig[j] : (uint32_t)((k >> shift) & 255);
+        const uint32_t pos = gbase[d] + (uint32_t)j - loff[d];
+        if (MODE == 0) {
+            if (kout) kout[pos] = k;
+            vout[pos] = sval[j];
         } else {
-            if (MODE == 2 || kout) kout[pos] = k;
-            if (MODE == 0) vout[pos] = sval[j];
+            kout[pos] = k;
         }
     }
 }
