@@ -134,6 +134,8 @@ def cpu_model():
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from committed PMC counters of this workload, or
     None when the kernel source changed since they were taken."""
+    if workload not in TRAFFIC_FILES:
+        return None
     try:
         with open(os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])) as f:
             t = json.load(f)
