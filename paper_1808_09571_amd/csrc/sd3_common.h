@@ -107,32 +107,96 @@ __device__ __forceinline__ T wave_max(T v) {
     }
     return v;
 }
-// Floating-point specialisations: the min / max instructions themselves
-// (one v_min_f64 instead of a compare and two selects per step); the values
+// Floating-point specialisations on DPP lane moves (no LDS crossbar): swaps
+// within quads (lanes 1,0,3,2 and 2,3,0,1), mirrors within half rows and
+// rows, then the broadcasts of lane 15 to the next row and of lane 31 to the
+// upper half, which leave the wave's extremum in lane 63; it is read back
+// into a scalar.  Lanes a row mask leaves out keep the identity.  Every lane
+// of the wave must be active (all callers are convergent); the values
 // reduced here are never NaN for valid input.
+namespace dpp {
+constexpr int QUAD_1032 = 0xB1, QUAD_2301 = 0x4E, ROW_HALF_MIRROR = 0x141, ROW_MIRROR = 0x140,
+              ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float movf(float v, float ident) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(ident), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double movd(double v, double ident) {
+    const long long b = __double_as_longlong(v), i = __double_as_longlong(ident);
+    const int lo = __builtin_amdgcn_update_dpp((int)i, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(i >> 32), (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+}  // namespace dpp
+
 template <>
 __device__ __forceinline__ double wave_min<double>(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+    const double I = __builtin_inf();
+    v = fmin(v, dpp::movd<dpp::QUAD_1032>(v, I));
+    v = fmin(v, dpp::movd<dpp::QUAD_2301>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_MIRROR>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_BCAST15, 0xa>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_BCAST31, 0xc>(v, I));
+    return dpp::lane63(v);
 }
 template <>
 __device__ __forceinline__ double wave_max<double>(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    const double I = -__builtin_inf();
+    v = fmax(v, dpp::movd<dpp::QUAD_1032>(v, I));
+    v = fmax(v, dpp::movd<dpp::QUAD_2301>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_MIRROR>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_BCAST15, 0xa>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_BCAST31, 0xc>(v, I));
+    return dpp::lane63(v);
 }
 template <>
 __device__ __forceinline__ float wave_min<float>(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
+    const float I = __builtin_inff();
+    v = fminf(v, dpp::movf<dpp::QUAD_1032>(v, I));
+    v = fminf(v, dpp::movf<dpp::QUAD_2301>(v, I));
+    v = fminf(v, dpp::movf<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fminf(v, dpp::movf<dpp::ROW_MIRROR>(v, I));
+    v = fminf(v, dpp::movf<dpp::ROW_BCAST15, 0xa>(v, I));
+    v = fminf(v, dpp::movf<dpp::ROW_BCAST31, 0xc>(v, I));
+    return dpp::lane63(v);
 }
 template <>
 __device__ __forceinline__ float wave_max<float>(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    const float I = -__builtin_inff();
+    v = fmaxf(v, dpp::movf<dpp::QUAD_1032>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::QUAD_2301>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::ROW_MIRROR>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::ROW_BCAST15, 0xa>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::ROW_BCAST31, 0xc>(v, I));
+    return dpp::lane63(v);
+}
+// Minimum / maximum over each aligned group of 8 lanes, in every lane of the
+// group (quad swaps, then the half-row mirror joins the two quads).
+__device__ __forceinline__ float group8_min(float v) {
+    const float I = __builtin_inff();
+    v = fminf(v, dpp::movf<dpp::QUAD_1032>(v, I));
+    v = fminf(v, dpp::movf<dpp::QUAD_2301>(v, I));
+    return fminf(v, dpp::movf<dpp::ROW_HALF_MIRROR>(v, I));
+}
+__device__ __forceinline__ float group8_max(float v) {
+    const float I = -__builtin_inff();
+    v = fmaxf(v, dpp::movf<dpp::QUAD_1032>(v, I));
+    v = fmaxf(v, dpp::movf<dpp::QUAD_2301>(v, I));
+    return fmaxf(v, dpp::movf<dpp::ROW_HALF_MIRROR>(v, I));
 }
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

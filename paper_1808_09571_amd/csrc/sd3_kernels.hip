@@ -2174,13 +2174,21 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                     bx[k] = dst[(F_LO + k) * TK + j];
                     bx[3 + k] = dst[(F_HI + k) * TK + j];
                 }
-#pragma unroll
-                for (int o = 1; o < 8; o <<= 1)
+                if constexpr (PREC == 0) {
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        bx[k] = fmin(bx[k], __shfl_xor(bx[k], o));
-                        bx[3 + k] = fmax(bx[3 + k], __shfl_xor(bx[3 + k], o));
+                        bx[k] = group8_min(bx[k]);
+                        bx[3 + k] = group8_max(bx[3 + k]);
                     }
+                } else {
+#pragma unroll
+                    for (int o = 1; o < 8; o <<= 1)
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            bx[k] = fmin(bx[k], __shfl_xor(bx[k], o));
+                            bx[3 + k] = fmax(bx[3 + k], __shfl_xor(bx[3 + k], o));
+                        }
+                }
                 if ((j & 7) == 0)
 #pragma unroll
                     for (int k = 0; k < 6; k++) gbox[onB ? 1 : 0][j >> 3][k] = bx[k];
