@@ -2151,28 +2151,34 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 if (!onB && keepA) continue;
                 const int j = onB ? sl - TK : sl;
                 Tt *dst = onB ? sB : sA;
+                // the vertices in registers: stored, and every derived field
+                // and the triangle box computed from them (no LDS read back)
+                Tt v[9];
                 if (PREC == 0) {
                     const float sx = onB ? sh[0] : 0.0f, sy = onB ? sh[1] : 0.0f, sz = onB ? sh[2] : 0.0f;
 #pragma unroll
-                    for (int c = 0; c < 9; c++)
-                        dst[c * TK + j] = (Tt)raw[s][c] + (Tt)(c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);
-                    tri_prep32(TriRef<float>{(float *)dst + j, TK});
+                    for (int c = 0; c < 9; c++) v[c] = (Tt)raw[s][c] + (Tt)(c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 9; c++) dst[c * TK + j] = raw[s][c];
-                    tri_prep64(TriRef<double>{(double *)dst + j, TK});
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        const Tt x0 = raw[s][k], x1 = raw[s][3 + k], x2 = raw[s][6 + k];
-                        dst[(F_LO + k) * TK + j] = fmin(x0, fmin(x1, x2));
-                        dst[(F_HI + k) * TK + j] = fmax(x0, fmax(x1, x2));
-                    }
+                    for (int c = 0; c < 9; c++) v[c] = raw[s][c];
                 }
+#pragma unroll
+                for (int c = 0; c < 9; c++) dst[c * TK + j] = v[c];
                 Tt bx[6];
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
-                    bx[k] = dst[(F_LO + k) * TK + j];
-                    bx[3 + k] = dst[(F_HI + k) * TK + j];
+                    bx[k] = fmin(v[k], fmin(v[3 + k], v[6 + k]));
+                    bx[3 + k] = fmax(v[k], fmax(v[3 + k], v[6 + k]));
+                }
+                if constexpr (PREC == 0) {
+                    tri_derive32(TriRef<float>{(float *)dst + j, TK}, v);
+                } else {
+                    tri_derive64(TriRef<double>{(double *)dst + j, TK}, v);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        dst[(F_LO + k) * TK + j] = bx[k];
+                        dst[(F_HI + k) * TK + j] = bx[3 + k];
+                    }
                 }
                 if constexpr (PREC == 0) {
 #pragma unroll

@@ -19,11 +19,9 @@ namespace sd3 {
 __device__ __forceinline__ float clamp01f(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 
 // Fill the derived fields (edges, squared lengths and their reciprocals, face
-// dual basis, bounding box) of an FP32 triangle from fields 0..8.
-__device__ __forceinline__ void tri_prep32(TriRef<float> t) {
-    float v[9];
-#pragma unroll
-    for (int i = 0; i < 9; i++) v[i] = t[F_V + i];
+// dual basis, bounding box) of an FP32 triangle from its vertices v (the
+// values of fields 0..8, held in registers).
+__device__ __forceinline__ void tri_derive32(TriRef<float> t, const float (&v)[9]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         int n = (k + 1) % 3;
@@ -54,6 +52,14 @@ __device__ __forceinline__ void tri_prep32(TriRef<float> t) {
         t.at(F_LO + k) = fminf(v[k], fminf(v[3 + k], v[6 + k]));
         t.at(F_HI + k) = fmaxf(v[k], fmaxf(v[3 + k], v[6 + k]));
     }
+}
+
+// The same from fields 0..8 as stored.
+__device__ __forceinline__ void tri_prep32(TriRef<float> t) {
+    float v[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) v[i] = t[F_V + i];
+    tri_derive32(t, v);
 }
 
 struct Pair32 {

@@ -40,11 +40,9 @@ __device__ __forceinline__ double dot3d(double ax, double ay, double az, double 
 
 __device__ __forceinline__ double clamp01d(double x) { return fmin(fmax(x, 0.0), 1.0); }
 
-// Fill the derived fields from v0 v1 v2 (already in fields 0..8).
-__device__ __forceinline__ void tri_prep64(TriRef<double> t) {
-    double v[9];
-#pragma unroll
-    for (int i = 0; i < 9; i++) v[i] = t[F_V + i];
+// Fill the derived fields from the vertices v (the values of fields 0..8,
+// held in registers).
+__device__ __forceinline__ void tri_derive64(TriRef<double> t, const double (&v)[9]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         int n = (k + 1) % 3;
@@ -72,6 +70,14 @@ __device__ __forceinline__ void tri_prep64(TriRef<double> t) {
     t.at(F_G2 + 0) = (a * E1x - b * E0x) * inn;
     t.at(F_G2 + 1) = (a * E1y - b * E0y) * inn;
     t.at(F_G2 + 2) = (a * E1z - b * E0z) * inn;
+}
+
+// The same from v0 v1 v2 as stored in fields 0..8.
+__device__ __forceinline__ void tri_prep64(TriRef<double> t) {
+    double v[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) v[i] = t[F_V + i];
+    tri_derive64(t, v);
 }
 
 // Filtered orient3d: sign of ((b-a) x (c-a)) . (d-a), or 2 when the FP64
