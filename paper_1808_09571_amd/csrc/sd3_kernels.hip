@@ -659,12 +659,17 @@ __global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *his
 // scans the chunk totals; the scatter adds both parts.
 constexpr int SCAN_CHUNK = 4096;
 
+// Inclusive prefix sum over the wave on DPP lane moves (every lane active):
+// shifts by 1, 2, 4 and 8 lanes within each row of 16 (lanes with no source
+// add 0), then the broadcasts of lane 15 to the next row and of lane 31 to
+// the upper half.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, o);
-        if (lane_id() >= o) v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
@@ -1678,7 +1683,7 @@ __global__ __launch_bounds__(256) void k_filter(const TileMeta *mA, const TileMe
         if (tot == 0) continue;
         unsigned int basei = 0;
         if (lane_id() == 0) basei = atomicAdd(qcount, tot);
-        basei = __shfl(basei, 0);
+        basei = __builtin_amdgcn_readfirstlane(basei);
 #pragma unroll
         for (int j = 0; j < FG; j++) {
             const bool keep = (m[j] >> lane_id()) & 1ull;
@@ -1847,29 +1852,6 @@ __device__ __forceinline__ bool overlap_boxes(const T (&alo)[3], const T (&ahi)[
 #pragma unroll
     for (int k = 0; k < 3; k++) keep = keep && blo[k] - ahi[k] <= tol && alo[k] - bhi[k] <= tol;
     return keep;
-}
-
-// Stage slot j of one tile into LDS: FP32 copies shifted by sh, or FP64.
-template <int TK>
-__device__ __forceinline__ void stage32(float *dst, const float *src_tile, float sx, float sy,
-                                        float sz, int j) {
-#pragma unroll
-    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j] + (c % 3 == 0 ? sx : c % 3 == 1 ? sy : sz);
-    tri_prep32(TriRef<float>{dst + j, TK});
-}
-
-template <int TK>
-__device__ __forceinline__ void stage64(double *dst, const double *src_tile, int j) {
-#pragma unroll
-    for (int c = 0; c < 9; c++) dst[c * TK + j] = src_tile[c * TK + j];
-    tri_prep64(TriRef<double>{dst + j, TK});
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        double x0 = dst[(F_V + k) * TK + j], x1 = dst[(F_V + 3 + k) * TK + j],
-               x2 = dst[(F_V + 6 + k) * TK + j];
-        dst[(F_LO + k) * TK + j] = fmin(x0, fmin(x1, x2));
-        dst[(F_HI + k) * TK + j] = fmax(x0, fmax(x1, x2));
-    }
 }
 
 // A lower bound rounded down to its upper 16 bits (negative bounds become 0:
@@ -2056,8 +2038,10 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
     constexpr int NS = 2 * TK / 64;  // staging slots per lane: [A slots | B slots]
     constexpr bool TESTED_LIST = PREC == 0 && MODE == 0;
     using Tt = typename std::conditional<PREC == 0, float, double>::type;
-    __shared__ Tt sA[NF * TK];
-    __shared__ Tt sB[NF * TK];
+    // the staged tiles, slot-major: a slot's NF fields are contiguous, so a
+    // triangle's fields are read with 16-byte LDS loads
+    __shared__ __attribute__((aligned(16))) Tt sA[NF * TK];
+    __shared__ __attribute__((aligned(16))) Tt sB[NF * TK];
     __shared__ Tt gbox[2][NG][6];  // [side][group][lo xyz, hi xyz]
     __shared__ uint32_t glist[NGP];
     __shared__ uint32_t ring[RING];
@@ -2163,7 +2147,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                     for (int c = 0; c < 9; c++) v[c] = raw[s][c];
                 }
 #pragma unroll
-                for (int c = 0; c < 9; c++) dst[c * TK + j] = v[c];
+                for (int c = 0; c < 9; c++) dst[j * NF + c] = v[c];
                 Tt bx[6];
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
@@ -2171,13 +2155,13 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                     bx[3 + k] = fmax(v[k], fmax(v[3 + k], v[6 + k]));
                 }
                 if constexpr (PREC == 0) {
-                    tri_derive32(TriRef<float>{(float *)dst + j, TK}, v);
+                    tri_derive32(TriRef<float>{(float *)dst + j * NF, 1}, v);
                 } else {
-                    tri_derive64(TriRef<double>{(double *)dst + j, TK}, v);
+                    tri_derive64(TriRef<double>{(double *)dst + j * NF, 1}, v);
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        dst[(F_LO + k) * TK + j] = bx[k];
-                        dst[(F_HI + k) * TK + j] = bx[3 + k];
+                        dst[j * NF + F_LO + k] = bx[k];
+                        dst[j * NF + F_HI + k] = bx[3 + k];
                     }
                 }
                 if constexpr (PREC == 0) {
@@ -2266,7 +2250,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 uint32_t e = on ? ring[(rd + lane) & (RING - 1)] : 0u;
                 const int a = e & 255, b = (e >> 8) & 255;
                 if (PREC == 0) {
-                    TriRef<float> TA{(float *)sA + a, TK}, TB{(float *)sB + b, TK};
+                    TriRef<float> TA{(float *)sA + a * NF, 1}, TB{(float *)sB + b * NF, 1};
                     if (MODE == 0) {
                         uint32_t te = 0;
                         if (on) {
@@ -2303,7 +2287,7 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                         n_resc += c == 2;
                     }
                 } else {
-                    TriRef<double> TA{(double *)sA + a, TK}, TB{(double *)sB + b, TK};
+                    TriRef<double> TA{(double *)sA + a * NF, 1}, TB{(double *)sB + b * NF, 1};
                     // distance and intersects both use the full FP64 pair test:
                     // its separating-plane certificate settles the disjoint
                     // pairs whose orientation signs are exact zeros
@@ -2327,10 +2311,11 @@ __global__ __launch_bounds__(64) void k_pairs(const float *t32A, const double *t
                 const int a = (int)(ge & 255) * 8 + (lane >> 3);
                 const int b = (int)((ge >> 8) & 255) * 8 + (lane & 7);
                 bool keep = a < na && b < nb;
-                const Tt alo[3] = {sA[F_LO * TK + a], sA[(F_LO + 1) * TK + a], sA[(F_LO + 2) * TK + a]};
-                const Tt ahi[3] = {sA[F_HI * TK + a], sA[(F_HI + 1) * TK + a], sA[(F_HI + 2) * TK + a]};
-                const Tt blo[3] = {sB[F_LO * TK + b], sB[(F_LO + 1) * TK + b], sB[(F_LO + 2) * TK + b]};
-                const Tt bhi[3] = {sB[F_HI * TK + b], sB[(F_HI + 1) * TK + b], sB[(F_HI + 2) * TK + b]};
+                const Tt *pa = sA + a * NF, *pb = sB + b * NF;
+                const Tt alo[3] = {pa[F_LO], pa[F_LO + 1], pa[F_LO + 2]};
+                const Tt ahi[3] = {pa[F_HI], pa[F_HI + 1], pa[F_HI + 2]};
+                const Tt blo[3] = {pb[F_LO], pb[F_LO + 1], pb[F_LO + 2]};
+                const Tt bhi[3] = {pb[F_HI], pb[F_HI + 1], pb[F_HI + 2]};
                 if (MODE == 0) {
                     const Tt g2 = gap2_boxes(alo, ahi, blo, bhi);
                     keep = keep && (PREC == 0 ? (float)g2 <= T2f : (double)g2 <= T2d);
