@@ -118,16 +118,23 @@ namespace dpp {
 constexpr int QUAD_1032 = 0xB1, QUAD_2301 = 0x4E, ROW_HALF_MIRROR = 0x141, ROW_MIRROR = 0x140,
               ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
 
+// A DPP move of each lane's value; lanes outside the row mask keep ident.
+// Moves over all rows (quad swaps, mirrors: every lane has a source) need no
+// old value, which saves setting it.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int mov32(int v, int ident) {
+    if constexpr (ROWS == 0xf) return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+    else return __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xf, false);
+}
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ float movf(float v, float ident) {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(ident), __float_as_int(v), CTRL, ROWS, 0xf, false));
+    return __int_as_float(mov32<CTRL, ROWS>(__float_as_int(v), __float_as_int(ident)));
 }
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ double movd(double v, double ident) {
     const long long b = __double_as_longlong(v), i = __double_as_longlong(ident);
-    const int lo = __builtin_amdgcn_update_dpp((int)i, (int)b, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(i >> 32), (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    const int lo = mov32<CTRL, ROWS>((int)b, (int)i);
+    const int hi = mov32<CTRL, ROWS>((int)(b >> 32), (int)(i >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane63(double v) {

@@ -868,6 +868,18 @@ static int radix_sort(uint32_t **keys, int32_t **vals, uint32_t *hist, uint32_t 
     return cur;
 }
 
+// The largest |x - o| (rounded to FP64) over a tile's coordinates x, from
+// its box: rounding is monotone, so along each axis the largest offset is
+// attained at the box's low or high end, and the value equals the maximum
+// over the vertices themselves.
+__device__ __forceinline__ double box_offset_max(const double (&lo)[3], const double (&hi)[3],
+                                                 const double (&o)[3]) {
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) m = fmax(m, fmax(hi[k] - o[k], o[k] - lo[k]));
+    return m;
+}
+
 // Tiles: gather each tile's triangles in sorted order and write the slot
 // triangle ids and the tile metadata (box, origin, storage error bound).  The
 // coordinate copies of a large call are written later, for queued tiles only
@@ -955,15 +967,7 @@ __device__ void tile_one(const TileJob &J, int64_t t) {
     // rad = the largest magnitude of the tile's FP32 offsets from the origin,
     // (float)(x - o): rounding to FP32 is monotone and odd, so it is the
     // largest FP64 offset magnitude rounded once
-    double dmax = 0.0;
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-        const int j = lane + 64 * r;
-        if (j >= tk) continue;
-#pragma unroll
-        for (int c = 0; c < 9; c++) dmax = fmax(dmax, fabs(v[r][c] - o[c % 3]));
-    }
-    const double rad = (double)(float)wave_max(dmax);
+    const double rad = (double)(float)box_offset_max(lo, hi, o);
     if (J.t32 || J.t64) {
 #pragma unroll
         for (int r = 0; r < 2; r++) {
@@ -1111,13 +1115,7 @@ __device__ void tile_meta_one(const TileJob &J, int64_t t, uint32_t *hk, int32_t
     }
     // rad as in the copying build: the largest FP64 offset magnitude rounded
     // once to FP32 (the same set of coordinates)
-    double dmax = 0.0;
-#pragma unroll
-    for (int q = 0; q < NU; q++)
-        if (q * 64 + lane < nu)
-#pragma unroll
-            for (int k = 0; k < 3; k++) dmax = fmax(dmax, fabs(p[q][k] - o[k]));
-    const double rad = (double)(float)wave_max(dmax);
+    const double rad = (double)(float)box_offset_max(lo, hi, o);
     const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
     // the representative vertex: corner 0 of slot 0, as in the copying build
     const double *rv = X + 3 * (int64_t)__builtin_amdgcn_readfirstlane((int)c[0][0]);
