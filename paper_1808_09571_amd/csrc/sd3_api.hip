@@ -168,6 +168,11 @@ struct sd3_ctx {
     std::map<uint64_t, int> tuned;        // workload key -> tile size (sd3_autotune)
     hipEvent_t ev[8] = {};
     KernelEvents *kev = nullptr;  // created on the first timed call
+    // a second stream (default priority) and two events that fork the
+    // learned ranking off a call's stream beside the tile copies and join it
+    // back (graph capture records the fork as two parallel branches)
+    hipStream_t side = nullptr;
+    hipEvent_t fork[2] = {};
 };
 
 namespace {
@@ -658,8 +663,21 @@ void enqueue_pipeline(sd3_ctx *ctx, Call &C, hipStream_t s, PhaseClock *clk, Ker
         if (kev) kev->begin(KE_FILTER, s);
         launch_queue(A, B, Q, nw, w0, C.rows, L, mode == 0 ? Q_FILTER_DIST : Q_FILTER_HIT, s, rank);
         if (kev) kev->end(KE_FILTER, s);
-        launch_materialize(A, B, L, prec, ctx->cus * 16, s);
-        if (learned) launch_rank(A, B, C.rows, L, C.opts.ranker, ctx->cus * 2, s);
+        if (learned && G > RESOLVE_MAX_ROWS) {
+            // the ranking and the tile copies read the queue and write disjoint
+            // state: in calls of many rows the ranking runs on the side stream
+            // beside the copies (a call of a few rows, a short chain of
+            // launches, gains nothing from the join)
+            check(hipEventRecord(ctx->fork[0], s), "hipEventRecord");
+            check(hipStreamWaitEvent(ctx->side, ctx->fork[0], 0), "hipStreamWaitEvent");
+            launch_rank(A, B, C.rows, L, C.opts.ranker, ctx->cus * 2, ctx->side);
+            check(hipEventRecord(ctx->fork[1], ctx->side), "hipEventRecord");
+            launch_materialize(A, B, L, prec, ctx->cus * 16, s);
+            check(hipStreamWaitEvent(s, ctx->fork[1], 0), "hipStreamWaitEvent");
+        } else {
+            launch_materialize(A, B, L, prec, ctx->cus * 16, s);
+            if (learned) launch_rank(A, B, C.rows, L, C.opts.ranker, ctx->cus * 2, s);
+        }
         // at most one seed per row
         if (C.seed) launch_pairs(A, B, C.rows, LS, prec, mode, (int)std::min<int64_t>(C.grid_pairs, G), s);
         if (w0 == 0) mark(3);
@@ -1000,8 +1018,14 @@ sd3_status sd3_create(sd3_ctx **out, int device) {
     c->sws.exact_cap = NOALLOC_EXACT;
     try {
         ensure_pinned(c, NOALLOC_HOST_BYTES);
+        check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "hipStreamCreate");
+        for (hipEvent_t &e : c->fork) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     } catch (const HipError &) {
         (void)hipGetLastError();
+        for (hipEvent_t &e : c->fork)
+            if (e) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->pin) (void)hipHostFree(c->pin);
         delete c;
         return SD3_E_NOMEM;
     }
@@ -1016,6 +1040,9 @@ sd3_status sd3_destroy(sd3_ctx *ctx) {
     release(ctx->mlp);
     for (hipEvent_t &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t &e : ctx->fork)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     if (ctx->kev) {
         for (auto &row : ctx->kev->ev)
