@@ -16,10 +16,10 @@ sd3_distance (validation, Morton sort + tiling, tile-pair bounds and queue,
 learned seed round, FP32 triangle-pair pass with error bounds, FP64 rescue,
 exact fallback, final reduction) and sd3_intersects (same stages, any-hit),
 each replayed from a HIP graph with the tile size the autotuner chose; the
-two queries are independent and run on two streams (the one-stream time is
-reported beside).  The plain-FP64 path (box-bound seed order, its own graphs
-and tuned tiles) runs the same step for comparison, and the line records
-whether the bits match.
+two queries are independent and run on two streams, each on a hardware queue
+of its own (the one-stream time is reported beside).  The plain-FP64 path
+(box-bound seed order, its own graphs and tuned tiles) runs the same step for
+comparison, and the line records whether the bits match.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--workload batch4096|scale|tin512] [--extras scale,tin512]
@@ -271,6 +271,41 @@ def time_orders(ctx, ba, bb, weights, args, precisions=("fp32",)):
     return out
 
 
+class QueueStreams:
+    """Streams that each own a hardware queue.  HIP maps ordinary streams onto
+    a few hardware queues (four by default), shared in turn, so two ordinary
+    streams can land on one queue and run one after the other; whether they
+    do depends on how many streams the process created before.  A stream made
+    with a CU mask (here every CU) gets a queue of its own.  Such a stream
+    orders itself against the null stream, so the timed steps launch on these
+    streams only.  The handles come from torch's own HIP runtime (loaded
+    under the same name)."""
+
+    def __init__(self, n):
+        import ctypes
+        import torch
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        ncu = torch.cuda.get_device_properties(0).multi_processor_count
+        words = (ncu + 31) // 32
+        mask = (ctypes.c_uint32 * words)(*([0xFFFFFFFF] * words))
+        self._raw, self.streams = [], []
+        for _ in range(n):
+            h = ctypes.c_void_p()
+            st = self._hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), ctypes.c_uint32(words), mask)
+            if st != 0:
+                self.close()
+                raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({st})")
+            self._raw.append(h)
+            self.streams.append(torch.cuda.ExternalStream(h.value))
+
+    def close(self):
+        import torch
+        torch.cuda.synchronize()
+        for h in self._raw:
+            self._hip.hipStreamDestroy(h)
+        self._raw, self.streams = [], []
+
+
 def measure(name, A, B, ctx, weights, args, headline):
     """Time one workload: the method (FP32 + rescue, learned seed round) and
     the plain FP64 path, graph-replayed, both queries per step.  The headline
@@ -302,20 +337,19 @@ def measure(name, A, B, ctx, weights, args, headline):
                 ctx.graph("intersects", ba, bb, precision=prec))
 
     # the step's two queries are independent and each graph has its own
-    # workspace: distance replays on the current stream, intersects on a
-    # second one (default priority), so the two overlap; replays of one graph
-    # stay in order on its own stream
-    side = torch.cuda.Stream()
+    # workspace: distance replays on one stream, intersects on a second one
+    # (default priority, each stream on a hardware queue of its own), so the
+    # two overlap; replays of one graph stay in order on its own stream
+    qs = QueueStreams(2)
+    main, side = qs.streams
 
     def timed_graphs(gd, gi):
         """K steps of (distance replay, intersects replay): concurrent on two
         streams (the step time) and serial on one stream (reported beside)."""
         def step(concurrent):
-            gd.launch()
-            if concurrent:
-                with torch.cuda.stream(side):
-                    gi.launch()
-            else:
+            with torch.cuda.stream(main):
+                gd.launch()
+            with torch.cuda.stream(side if concurrent else main):
                 gi.launch()
 
         out = {}
@@ -354,8 +388,9 @@ def measure(name, A, B, ctx, weights, args, headline):
                 "exact_match_fp32_vs_fp64": bool(exact), "speedup_fp32_over_fp64": t64 / t32}
         gd64.close()
         gi64.close()
+    qs.close()
 
-    fp32_tests = sd32["tri_pairs_fp32"] + si32["tri_pairs_fp32"]
+    fp32_tests =sd32["tri_pairs_fp32"] + si32["tri_pairs_fp32"]
     fp64_tests = sd32["tri_pairs_fp64"] + si32["tri_pairs_fp64"]
     res = {
         "workload": WORKLOADS[name], "rows": G, "triangles_a": na, "triangles_b": nb,
@@ -677,7 +712,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "rows": head["rows"],
                    "triangles_a": head["triangles_a"], "triangles_b": head["triangles_b"],
                    "order": "learned", "ranker": "ranker_weights.npy",
-                   "launch": "HIP graph per operator; distance and intersects on two streams",
+                   "launch": "HIP graph per operator; distance and intersects on two streams with hardware queues of their own",
                    "tiles": head["tiles"]},
     }
     for k in ("tri_pairs_executed_per_step", "tri_pairs_executed_per_s", "all_pairs_equivalent_per_s",
