@@ -190,11 +190,12 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
         per = tris * per_tri + float(nverts) * BYTES_TILE_VTX + ntiles * BYTES_TILE_META
         ach = per / (avg * 1e-3) / 1e9
         # kernel names: two slots per lane at 128-triangle tiles; large calls
-        # build metadata only (k_tiles_meta), small ones copies too (k_tiles)
+        # build metadata only (k_tiles_meta<slots per lane and tile, tiles
+        # per wave>), small ones copies too (k_tiles)
         def tile_kernel(x):
             two = x["tile"] == 128
             if x["sort_items"] / x["tile"] >= LAZY_COPY_MIN_TILES:
-                return f"k_tiles_meta<{2 if two else 1}>"
+                return "k_tiles_meta<2, 1>" if two else "k_tiles_meta<1, 2>"
             return f"k_tiles<{'true' if two else 'false'}>"
         tr = [measured_traffic(tile_kernel(x), workload) for x in st_list]
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,

@@ -1023,127 +1023,182 @@ __global__ void k_tiles(TileJob A, TileJob B) {
 // occupied entries are numbered with ballots, and lane u loads distinct
 // vertex u: one 24-byte gather per distinct vertex instead of one per corner
 // (the address unit, which takes one cache access per cycle, bounded the
-// per-corner gathers).  R slots per lane (R = 2: 128-triangle tiles).
+// per-corner gathers).  A tile is a chain of dependent loads (row search, row
+// offsets, sorted items, corner indices, distinct vertices), so a wave builds
+// M consecutive tiles of one side at once, each step's loads for all of them
+// issued together: M round trips' latency is paid once.  RT slots per lane
+// and tile (RT = 2: 128-triangle tiles); tile m has its own table and list.
 constexpr uint32_t HASH_EMPTY = 0xffffffffu;
+constexpr int TILE_META_PER_WAVE = 2;  // tiles per wave of the metadata build up to 64 triangles
 
-template <int R>
-__device__ void tile_meta_one(const TileJob &J, int64_t t, uint32_t *hk, int32_t *uv) {
-    constexpr int HS = 256 * R;        // table entries (at most 3 * 64 R keys)
-    constexpr int NU = 3 * R;          // rounds of 64 distinct vertices at most
+template <int RT, int M>
+__device__ void tile_meta_wave(const TileJob &J, int64_t t0, uint32_t *hk, int32_t *uv) {
+    constexpr int HS = 256 * RT;       // table entries per tile (at most 3 * 64 RT keys)
+    constexpr int US = 3 * 64 * RT;    // distinct-vertex list per tile
+    constexpr int NU = 3 * RT;         // rounds of 64 distinct vertices at most
     const int lane = lane_id(), tk = J.tk;
-    const int64_t g = wave_find_row(J.tile_off, J.G, t);
-    const int64_t i = t - J.tile_off[g];
-    const int64_t ntr = J.t_off[g + 1] - J.t_off[g];
-    const int n = (int)min((int64_t)tk, ntr - i * tk);
-    const double *X = J.xyz + 3 * J.v_off[g];
-    const int64_t nvr = J.v_off[g + 1] - J.v_off[g];
-    int64_t tri_id[R];
-    uint32_t c[R][3];
+    // rows: consecutive tiles mostly share one; search again only past its end
+    int64_t g[M];
+    g[0] = wave_find_row(J.tile_off, J.G, t0);
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int32_t w = J.sorted[J.t_off[g] + i * tk + min(lane + 64 * r, n - 1)];
-        tri_id[r] = J.packed ? J.t_off[g] + (w & 0xffffff) : w;
+    for (int m = 1; m < M; m++) {
+        g[m] = g[m - 1];
+        if (t0 + m < J.NT && t0 + m >= J.tile_off[g[m] + 1]) g[m] = wave_find_row(J.tile_off, J.G, t0 + m);
     }
+    // a tile past the side's end (the last wave of a side) repeats tile t0's
+    // loads, so that every step's loads go out together without branches,
+    // and writes nothing
+    bool on[M];
+    int n[M];
+    int64_t tlo[M], pos[M], nvr[M];
+    const double *X[M];
 #pragma unroll
-    for (int q = 0; q < HS / 64; q++) hk[q * 64 + lane] = HASH_EMPTY;
-#pragma unroll
-    for (int r = 0; r < R; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) c[r][k] = (uint32_t)corner(J.tri, tri_id[r], k, nvr);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int j = lane + 64 * r;
-        if (j < tk) J.ids[t * tk + j] = (int32_t)tri_id[r];
+    for (int m = 0; m < M; m++) {
+        on[m] = t0 + m < J.NT;  // (wave-uniform)
+        const int64_t t = on[m] ? t0 + m : t0, gm = on[m] ? g[m] : g[0];
+        const int64_t i = t - J.tile_off[gm];
+        tlo[m] = J.t_off[gm];
+        n[m] = (int)min((int64_t)tk, J.t_off[gm + 1] - tlo[m] - i * tk);
+        pos[m] = tlo[m] + i * tk;
+        X[m] = J.xyz + 3 * J.v_off[gm];
+        nvr[m] = J.v_off[gm + 1] - J.v_off[gm];
     }
-    wave_lds_sync();
-    // insert every slot's corners (slots past tk are left out); the table
-    // holds at most 3/4 of its size in keys, so every probe ends
+    int64_t tri_id[M][RT];
+    uint32_t c[M][RT][3];
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        if (lane + 64 * r >= tk) continue;
+    for (int m = 0; m < M; m++)
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const uint32_t key = c[r][k];
-            uint32_t h = (key * 2654435761u) >> (32 - (R == 2 ? 9 : 8));
-            for (;;) {
-                const uint32_t old = atomicCAS(&hk[h], HASH_EMPTY, key);
-                if (old == HASH_EMPTY || old == key) break;
-                h = (h + 1) & (HS - 1);
-            }
+        for (int r = 0; r < RT; r++) {
+            const int32_t w = J.sorted[pos[m] + min(lane + 64 * r, n[m] - 1)];
+            tri_id[m][r] = J.packed ? tlo[m] + (w & 0xffffff) : w;
         }
-    }
+#pragma unroll
+    for (int q = 0; q < M * HS / 64; q++) hk[q * 64 + lane] = HASH_EMPTY;
+#pragma unroll
+    for (int m = 0; m < M; m++)
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) c[m][r][k] = (uint32_t)corner(J.tri, tri_id[m][r], k, nvr[m]);
+#pragma unroll
+    for (int m = 0; m < M; m++)
+#pragma unroll
+        for (int r = 0; r < RT; r++) {
+            const int j = lane + 64 * r;
+            if (on[m] && j < tk) J.ids[(t0 + m) * tk + j] = (int32_t)tri_id[m][r];
+        }
     wave_lds_sync();
-    // number the distinct vertices in table order
-    int nu = 0;
+    // insert every slot's corners into its tile's table (slots past tk are
+    // left out); a table holds at most 3/4 of its size in keys, so every
+    // probe ends
 #pragma unroll
-    for (int q = 0; q < HS / 64; q++) {
-        const uint32_t key = hk[q * 64 + lane];
-        const bool occ = key != HASH_EMPTY;
-        const unsigned long long m = __ballot(occ);
-        if (occ) uv[nu + __popcll(m & lanes_below())] = (int32_t)key;
-        nu += __popcll(m);
-    }
-    wave_lds_sync();
-    // gather them: lane u of round q holds distinct vertex 64 q + u
-    double p[NU][3];
-    double lo[3], hi[3], o[3];
+    for (int m = 0; m < M; m++) {
+        uint32_t *ht = hk + m * HS;
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        lo[k] = __builtin_inf();
-        hi[k] = -__builtin_inf();
-    }
-#pragma unroll
-    for (int q = 0; q < NU; q++) {
-        if (q * 64 >= nu) break;  // (wave-uniform)
-        const int u = q * 64 + lane;
-        const bool on = u < nu;
-        const double *pv = X + 3 * (int64_t)(on ? uv[u] : uv[0]);
-#pragma unroll
-        for (int k = 0; k < 3; k++) p[q][k] = pv[k];
-        if (on)
+        for (int r = 0; r < RT; r++) {
+            if (lane + 64 * r >= tk) continue;
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                lo[k] = fmin(lo[k], p[q][k]);
-                hi[k] = fmax(hi[k], p[q][k]);
+                const uint32_t key = c[m][r][k];
+                uint32_t h = (key * 2654435761u) >> (32 - (RT == 2 ? 9 : 8));
+                for (;;) {
+                    const uint32_t old = atomicCAS(&ht[h], HASH_EMPTY, key);
+                    if (old == HASH_EMPTY || old == key) break;
+                    h = (h + 1) & (HS - 1);
+                }
             }
+        }
+    }
+    wave_lds_sync();
+    // number each tile's distinct vertices in table order (at least one)
+    int nu[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        nu[m] = 0;
+#pragma unroll
+        for (int q = 0; q < HS / 64; q++) {
+            const uint32_t key = hk[m * HS + q * 64 + lane];
+            const bool occ = key != HASH_EMPTY;
+            const unsigned long long b = __ballot(occ);
+            if (occ) uv[m * US + nu[m] + __popcll(b & lanes_below())] = (int32_t)key;
+            nu[m] += __popcll(b);
+        }
+    }
+    wave_lds_sync();
+    // gather them: lane u of round q holds distinct vertex 64 q + u of its
+    // tile; the first round of every tile is issued at once
+    double lo[M][3], hi[M][3];
+#pragma unroll
+    for (int m = 0; m < M; m++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            lo[m][k] = __builtin_inf();
+            hi[m][k] = -__builtin_inf();
+        }
+    auto take = [&](int m, int q) __attribute__((always_inline)) {
+        const int u = q * 64 + lane;
+        const bool in = u < nu[m];
+        const double *pv = X[m] + 3 * (int64_t)uv[m * US + (in ? u : 0)];
+        const double p0 = pv[0], p1 = pv[1], p2 = pv[2];
+        lo[m][0] = in ? fmin(lo[m][0], p0) : lo[m][0];
+        lo[m][1] = in ? fmin(lo[m][1], p1) : lo[m][1];
+        lo[m][2] = in ? fmin(lo[m][2], p2) : lo[m][2];
+        hi[m][0] = in ? fmax(hi[m][0], p0) : hi[m][0];
+        hi[m][1] = in ? fmax(hi[m][1], p1) : hi[m][1];
+        hi[m][2] = in ? fmax(hi[m][2], p2) : hi[m][2];
+    };
+#pragma unroll
+    for (int m = 0; m < M; m++) take(m, 0);
+#pragma unroll
+    for (int m = 0; m < M; m++)
+        for (int q = 1; q < NU && q * 64 < nu[m]; q++) take(m, q);  // (wave-uniform)
+    // the representative vertex: corner 0 of slot 0, as in the copying build
+    double rep[M][3];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const double *rv = X[m] + 3 * (int64_t)__builtin_amdgcn_readfirstlane((int)c[m][0][0]);
+        for (int k = 0; k < 3; k++) rep[m][k] = rv[k];
     }
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        lo[k] = wave_min(lo[k]);
-        hi[k] = wave_max(hi[k]);
-        o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
-    }
-    // rad as in the copying build: the largest FP64 offset magnitude rounded
-    // once to FP32 (the same set of coordinates)
-    const double rad = (double)(float)box_offset_max(lo, hi, o);
-    const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
-    // the representative vertex: corner 0 of slot 0, as in the copying build
-    const double *rv = X + 3 * (int64_t)__builtin_amdgcn_readfirstlane((int)c[0][0]);
-    if (lane == 0) {
-        TileMeta m;
+    for (int m = 0; m < M; m++) {
+        double o[3];
         for (int k = 0; k < 3; k++) {
-            m.o[k] = o[k];
-            m.lo[k] = lo[k];
-            m.hi[k] = hi[k];
-            m.rep[k] = rv[k];
+            lo[m][k] = wave_min(lo[m][k]);
+            hi[m][k] = wave_max(hi[m][k]);
+            o[k] = (double)(float)(0.5 * lo[m][k] + 0.5 * hi[m][k]);
         }
-        m.eps = (float)(err * (1.0 + 0x1p-20));
-        m.rad = (float)rad;
-        m.row = (int32_t)g;
-        m.n = n;
-        J.meta[t] = m;
-        J.mat[t] = 0u;
+        // rad as in the copying build: the largest FP64 offset magnitude
+        // rounded once to FP32 (the same set of coordinates)
+        const double rad = (double)(float)box_offset_max(lo[m], hi[m], o);
+        const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
+        if (on[m] && lane == m) {
+            TileMeta mt;
+            for (int k = 0; k < 3; k++) {
+                mt.o[k] = o[k];
+                mt.lo[k] = lo[m][k];
+                mt.hi[k] = hi[m][k];
+                mt.rep[k] = rep[m][k];
+            }
+            mt.eps = (float)(err * (1.0 + 0x1p-20));
+            mt.rad = (float)rad;
+            mt.row = (int32_t)g[m];
+            mt.n = n[m];
+            J.meta[t0 + m] = mt;
+            J.mat[t0 + m] = 0u;
+        }
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(256) void k_tiles_meta(TileJob A, TileJob B) {
-    __shared__ uint32_t hk[4][256 * R];
-    __shared__ int32_t uv[4][3 * 64 * R];
+// One wave per M tiles: waves [0, ceil(NT_A / M)) build A's tiles, the rest B's.
+template <int RT, int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tiles_meta(TileJob A, TileJob B) {
+    __shared__ uint32_t hk[4][256 * RT * M];
+    __shared__ int32_t uv[4][3 * 64 * RT * M];
     const int w = threadIdx.x >> 6;
-    int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (t < A.NT) tile_meta_one<R>(A, t, hk[w], uv[w]);
-    else if (t - A.NT < B.NT) tile_meta_one<R>(B, t - A.NT, hk[w], uv[w]);
+    const int64_t v = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    const int64_t wa = (A.NT + M - 1) / M;
+    if (v < wa) tile_meta_wave<RT, M>(A, v * M, hk[w], uv[w]);
+    else if ((v - wa) * M < B.NT) tile_meta_wave<RT, M>(B, (v - wa) * M, hk[w], uv[w]);
 }
 
 // Both sides are sorted in one sequence of launches (each row's items stay in
@@ -1210,10 +1265,13 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
         // waves in flight for the gathers
         const dim3 grid(grid_for(A.NT + B.NT, 4));
         if (lazy) {
+            // the metadata build takes two tiles per wave up to 64 triangles
+            constexpr int64_t MT = TILE_META_PER_WAVE;
+            const dim3 gm(grid_for((A.NT + MT - 1) / MT + (B.NT + MT - 1) / MT, 4));
             if (A.tk > 64)
-                hipLaunchKernelGGL(k_tiles_meta<2>, grid, dim3(256), 0, s, ja, jb);
+                hipLaunchKernelGGL((k_tiles_meta<2, 1>), grid, dim3(256), 0, s, ja, jb);
             else
-                hipLaunchKernelGGL(k_tiles_meta<1>, grid, dim3(256), 0, s, ja, jb);
+                hipLaunchKernelGGL((k_tiles_meta<1, MT>), gm, dim3(256), 0, s, ja, jb);
         } else if (A.tk > 64) {
             hipLaunchKernelGGL(k_tiles<true>, grid, dim3(256), 0, s, ja, jb);
         } else {
