@@ -67,6 +67,7 @@ BYTES_TILE_COPY = 36
 BYTES_TILE_VTX = 24
 BYTES_TILE_META = 112
 LAZY_COPY_MIN_TILES = 16384
+TILE_META_PER_WAVE = {32: 4, 64: 4, 128: 2}  # metadata-only build: tiles per wave
 VOL_BYTES_TRI = 12 + 72  # volume: triangle indices and three FP64 vertices
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
@@ -189,14 +190,14 @@ def roofline_for(kernel, st_list, ms, n, workload, nverts):
         per_tri = BYTES_TILE_TRI + (BYTES_TILE_COPY if ntiles < LAZY_COPY_MIN_TILES else 0)
         per = tris * per_tri + float(nverts) * BYTES_TILE_VTX + ntiles * BYTES_TILE_META
         ach = per / (avg * 1e-3) / 1e9
-        # kernel names: two slots per lane at 128-triangle tiles; large calls
-        # build metadata only (k_tiles_meta<slots per lane and tile, tiles
-        # per wave>), small ones copies too (k_tiles)
+        # kernel names: large calls build metadata only (k_tiles_meta<tile
+        # size, tiles per wave>), small ones copies too (k_tiles<two slots
+        # per lane>)
         def tile_kernel(x):
-            two = x["tile"] == 128
-            if x["sort_items"] / x["tile"] >= LAZY_COPY_MIN_TILES:
-                return "k_tiles_meta<2, 1>" if two else "k_tiles_meta<1, 2>"
-            return f"k_tiles<{'true' if two else 'false'}>"
+            tk = x["tile"]
+            if x["sort_items"] / tk >= LAZY_COPY_MIN_TILES:
+                return f"k_tiles_meta<{tk}, {TILE_META_PER_WAVE[tk]}>"
+            return f"k_tiles<{'true' if tk == 128 else 'false'}>"
         tr = [measured_traffic(tile_kernel(x), workload) for x in st_list]
         return {"kernel": "k_tiles", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,

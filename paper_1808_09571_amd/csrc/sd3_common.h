@@ -205,6 +205,33 @@ __device__ __forceinline__ float group8_max(float v) {
     v = fmaxf(v, dpp::movf<dpp::QUAD_2301>(v, I));
     return fmaxf(v, dpp::movf<dpp::ROW_HALF_MIRROR>(v, I));
 }
+// Minimum / maximum over each aligned group of S lanes (S = 16, 32 or 64),
+// left in the group's last lane (and, for S = 16, in every lane of it): the
+// steps of the wave reduction that stay inside the group.
+template <int S>
+__device__ __forceinline__ double group_min(double v) {
+    static_assert(S == 16 || S == 32 || S == 64, "group of 16, 32 or 64 lanes");
+    const double I = __builtin_inf();
+    v = fmin(v, dpp::movd<dpp::QUAD_1032>(v, I));
+    v = fmin(v, dpp::movd<dpp::QUAD_2301>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fmin(v, dpp::movd<dpp::ROW_MIRROR>(v, I));
+    if constexpr (S >= 32) v = fmin(v, dpp::movd<dpp::ROW_BCAST15, 0xa>(v, I));
+    if constexpr (S == 64) v = fmin(v, dpp::movd<dpp::ROW_BCAST31, 0xc>(v, I));
+    return v;
+}
+template <int S>
+__device__ __forceinline__ double group_max(double v) {
+    static_assert(S == 16 || S == 32 || S == 64, "group of 16, 32 or 64 lanes");
+    const double I = -__builtin_inf();
+    v = fmax(v, dpp::movd<dpp::QUAD_1032>(v, I));
+    v = fmax(v, dpp::movd<dpp::QUAD_2301>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_HALF_MIRROR>(v, I));
+    v = fmax(v, dpp::movd<dpp::ROW_MIRROR>(v, I));
+    if constexpr (S >= 32) v = fmax(v, dpp::movd<dpp::ROW_BCAST15, 0xa>(v, I));
+    if constexpr (S == 64) v = fmax(v, dpp::movd<dpp::ROW_BCAST31, 0xc>(v, I));
+    return v;
+}
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

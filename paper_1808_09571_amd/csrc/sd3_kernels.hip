@@ -1017,188 +1017,175 @@ __global__ void k_tiles(TileJob A, TileJob B) {
 
 // The tile build of a large call (no copies): the tile's box, origin and
 // radius need each of its vertices once, and a tile's triangles share most of
-// them (about 40 distinct vertices for 64 triangles), so the wave gathers its
-// distinct vertices only.  The slots' corner indices go into a hash table in
-// the wave's LDS (linear probing, compare-and-swap from an empty key), the
-// occupied entries are numbered with ballots, and lane u loads distinct
-// vertex u: one 24-byte gather per distinct vertex instead of one per corner
-// (the address unit, which takes one cache access per cycle, bounded the
-// per-corner gathers).  A tile is a chain of dependent loads (row search, row
-// offsets, sorted items, corner indices, distinct vertices), so a wave builds
-// M consecutive tiles of one side at once, each step's loads for all of them
-// issued together: M round trips' latency is paid once.  RT slots per lane
-// and tile (RT = 2: 128-triangle tiles); tile m has its own table and list.
+// them (about 40 distinct vertices for 64 triangles), so only the distinct
+// vertices are gathered.  The slots' corner indices go into a hash table in
+// LDS (linear probing, compare-and-swap from an empty key), the occupied
+// entries are numbered with ballots, and each lane loads some of the distinct
+// vertices: one 24-byte gather per distinct vertex instead of one per corner.
+// The build is bound by vector instructions, most of them in the FP64
+// min/max reductions of the box, so a wave builds M consecutive tiles of one
+// side at once, lanes [m S, (m + 1) S) (S = 64 / M) working on tile m with
+// TK / S slots each: one reduction over groups of S lanes serves all M tiles
+// (a wave-wide reduction per tile cost twice the instructions).
 constexpr uint32_t HASH_EMPTY = 0xffffffffu;
-constexpr int TILE_META_PER_WAVE = 2;  // tiles per wave of the metadata build up to 64 triangles
+constexpr int TILE_META_M64 = 4;   // tiles per wave of the metadata build, 64-triangle tiles
+constexpr int TILE_META_M128 = 2;  // and 128-triangle tiles
 
-template <int RT, int M>
-__device__ void tile_meta_wave(const TileJob &J, int64_t t0, uint32_t *hk, int32_t *uv) {
-    constexpr int HS = 256 * RT;       // table entries per tile (at most 3 * 64 RT keys)
-    constexpr int US = 3 * 64 * RT;    // distinct-vertex list per tile
-    constexpr int NU = 3 * RT;         // rounds of 64 distinct vertices at most
-    const int lane = lane_id(), tk = J.tk;
+template <int TK, int M>
+__device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int32_t *uv) {
+    constexpr int S = 64 / M;         // lanes per tile
+    constexpr int SL = TK / S;        // slots per lane
+    constexpr int HS = 4 * TK;        // table entries per tile (at most 3 TK keys)
+    constexpr int HB = TK == 32 ? 7 : (TK == 64 ? 8 : 9);  // log2(HS)
+    constexpr int US = 3 * TK;        // distinct-vertex list per tile
+    static_assert(M * S == 64 && SL * S == TK, "tile groups fill the wave");
+    const int lane = lane_id();
+    const int m = lane / S, sl = lane % S;
+    // lanes of this lane's tile (contiguous), and those of them below it
+    const unsigned long long gm = (S == 64 ? ~0ull : ((1ull << S) - 1ull)) << (m * S);
+    const unsigned long long gbelow = gm & lanes_below();
     // rows: consecutive tiles mostly share one; search again only past its end
     int64_t g[M];
     g[0] = wave_find_row(J.tile_off, J.G, t0);
 #pragma unroll
-    for (int m = 1; m < M; m++) {
-        g[m] = g[m - 1];
-        if (t0 + m < J.NT && t0 + m >= J.tile_off[g[m] + 1]) g[m] = wave_find_row(J.tile_off, J.G, t0 + m);
+    for (int q = 1; q < M; q++) {
+        g[q] = g[q - 1];
+        if (t0 + q < J.NT && t0 + q >= J.tile_off[g[q] + 1]) g[q] = wave_find_row(J.tile_off, J.G, t0 + q);
     }
-    // a tile past the side's end (the last wave of a side) repeats tile t0's
-    // loads, so that every step's loads go out together without branches,
-    // and writes nothing
-    bool on[M];
-    int n[M];
-    int64_t tlo[M], pos[M], nvr[M];
-    const double *X[M];
+    // this lane's tile; one past the side's end (the last wave of a side)
+    // repeats tile t0's loads and writes nothing
+    const bool on = t0 + m < J.NT;
+    int64_t gl = g[0];
 #pragma unroll
-    for (int m = 0; m < M; m++) {
-        on[m] = t0 + m < J.NT;  // (wave-uniform)
-        const int64_t t = on[m] ? t0 + m : t0, gm = on[m] ? g[m] : g[0];
-        const int64_t i = t - J.tile_off[gm];
-        tlo[m] = J.t_off[gm];
-        n[m] = (int)min((int64_t)tk, J.t_off[gm + 1] - tlo[m] - i * tk);
-        pos[m] = tlo[m] + i * tk;
-        X[m] = J.xyz + 3 * J.v_off[gm];
-        nvr[m] = J.v_off[gm + 1] - J.v_off[gm];
+    for (int q = 1; q < M; q++) gl = m == q ? g[q] : gl;
+    if (!on) gl = g[0];
+    const int64_t tl = on ? t0 + m : t0;
+    const int64_t i = tl - J.tile_off[gl];
+    const int64_t tlo = J.t_off[gl];
+    const int n = (int)min((int64_t)TK, J.t_off[gl + 1] - tlo - i * TK);
+    const int64_t pos = tlo + i * TK;
+    const int64_t vb = J.v_off[gl];
+    const int64_t nvr = J.v_off[gl + 1] - vb;
+    const double *X = J.xyz + 3 * vb;
+    int64_t tri_id[SL];
+    uint32_t c[SL][3];
+#pragma unroll
+    for (int r = 0; r < SL; r++) {
+        const int32_t w = J.sorted[pos + min(sl + S * r, n - 1)];
+        tri_id[r] = J.packed ? tlo + (w & 0xffffff) : w;
     }
-    int64_t tri_id[M][RT];
-    uint32_t c[M][RT][3];
-#pragma unroll
-    for (int m = 0; m < M; m++)
-#pragma unroll
-        for (int r = 0; r < RT; r++) {
-            const int32_t w = J.sorted[pos[m] + min(lane + 64 * r, n[m] - 1)];
-            tri_id[m][r] = J.packed ? tlo[m] + (w & 0xffffff) : w;
-        }
 #pragma unroll
     for (int q = 0; q < M * HS / 64; q++) hk[q * 64 + lane] = HASH_EMPTY;
 #pragma unroll
-    for (int m = 0; m < M; m++)
+    for (int r = 0; r < SL; r++)
 #pragma unroll
-        for (int r = 0; r < RT; r++)
+        for (int k = 0; k < 3; k++) c[r][k] = (uint32_t)corner(J.tri, tri_id[r], k, nvr);
+    if (on)
 #pragma unroll
-            for (int k = 0; k < 3; k++) c[m][r][k] = (uint32_t)corner(J.tri, tri_id[m][r], k, nvr[m]);
-#pragma unroll
-    for (int m = 0; m < M; m++)
-#pragma unroll
-        for (int r = 0; r < RT; r++) {
-            const int j = lane + 64 * r;
-            if (on[m] && j < tk) J.ids[(t0 + m) * tk + j] = (int32_t)tri_id[m][r];
-        }
+        for (int r = 0; r < SL; r++) J.ids[tl * TK + sl + S * r] = (int32_t)tri_id[r];
     wave_lds_sync();
-    // insert every slot's corners into its tile's table (slots past tk are
-    // left out); a table holds at most 3/4 of its size in keys, so every
-    // probe ends
+    // insert every slot's corners into the tile's table; a table holds at
+    // most 3/4 of its size in keys, so every probe ends
+    uint32_t *ht = hk + m * HS;
+    if (on)
 #pragma unroll
-    for (int m = 0; m < M; m++) {
-        uint32_t *ht = hk + m * HS;
-#pragma unroll
-        for (int r = 0; r < RT; r++) {
-            if (lane + 64 * r >= tk) continue;
+        for (int r = 0; r < SL; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const uint32_t key = c[m][r][k];
-                uint32_t h = (key * 2654435761u) >> (32 - (RT == 2 ? 9 : 8));
+                const uint32_t key = c[r][k];
+                uint32_t h = (key * 2654435761u) >> (32 - HB);
                 for (;;) {
                     const uint32_t old = atomicCAS(&ht[h], HASH_EMPTY, key);
                     if (old == HASH_EMPTY || old == key) break;
                     h = (h + 1) & (HS - 1);
                 }
             }
-        }
+    wave_lds_sync();
+    // number the tile's distinct vertices in table order (at least one for a
+    // tile that exists, none for one past the end)
+    int32_t *ul = uv + m * US;
+    int nu = 0;
+#pragma unroll
+    for (int q = 0; q < HS / S; q++) {
+        const uint32_t key = ht[q * S + sl];
+        const bool occ = key != HASH_EMPTY;
+        const unsigned long long b = __ballot(occ);
+        if (occ) ul[nu + __popcll(b & gbelow)] = (int32_t)key;
+        nu += __popcll(b & gm);
     }
     wave_lds_sync();
-    // number each tile's distinct vertices in table order (at least one)
-    int nu[M];
+    // gather them: lane sl of round q holds distinct vertex S q + sl of its
+    // tile (rounds up to the largest count among the wave's tiles)
+    int nmax = 0;
 #pragma unroll
-    for (int m = 0; m < M; m++) {
-        nu[m] = 0;
+    for (int q = 0; q < M; q++) nmax = max(nmax, __builtin_amdgcn_readlane(nu, q * S));
+    double lo[3], hi[3];
 #pragma unroll
-        for (int q = 0; q < HS / 64; q++) {
-            const uint32_t key = hk[m * HS + q * 64 + lane];
-            const bool occ = key != HASH_EMPTY;
-            const unsigned long long b = __ballot(occ);
-            if (occ) uv[m * US + nu[m] + __popcll(b & lanes_below())] = (int32_t)key;
-            nu[m] += __popcll(b);
-        }
+    for (int k = 0; k < 3; k++) {
+        lo[k] = __builtin_inf();
+        hi[k] = -__builtin_inf();
     }
-    wave_lds_sync();
-    // gather them: lane u of round q holds distinct vertex 64 q + u of its
-    // tile; the first round of every tile is issued at once
-    double lo[M][3], hi[M][3];
-#pragma unroll
-    for (int m = 0; m < M; m++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            lo[m][k] = __builtin_inf();
-            hi[m][k] = -__builtin_inf();
-        }
-    auto take = [&](int m, int q) __attribute__((always_inline)) {
-        const int u = q * 64 + lane;
-        const bool in = u < nu[m];
-        const double *pv = X[m] + 3 * (int64_t)uv[m * US + (in ? u : 0)];
+    for (int q = 0; q * S < nmax; q++) {  // (wave-uniform)
+        const int u = q * S + sl;
+        const bool in = u < nu;
+        const double *pv = X + 3 * (int64_t)(in ? (uint32_t)ul[u] : c[0][0]);
         const double p0 = pv[0], p1 = pv[1], p2 = pv[2];
-        lo[m][0] = in ? fmin(lo[m][0], p0) : lo[m][0];
-        lo[m][1] = in ? fmin(lo[m][1], p1) : lo[m][1];
-        lo[m][2] = in ? fmin(lo[m][2], p2) : lo[m][2];
-        hi[m][0] = in ? fmax(hi[m][0], p0) : hi[m][0];
-        hi[m][1] = in ? fmax(hi[m][1], p1) : hi[m][1];
-        hi[m][2] = in ? fmax(hi[m][2], p2) : hi[m][2];
-    };
-#pragma unroll
-    for (int m = 0; m < M; m++) take(m, 0);
-#pragma unroll
-    for (int m = 0; m < M; m++)
-        for (int q = 1; q < NU && q * 64 < nu[m]; q++) take(m, q);  // (wave-uniform)
-    // the representative vertex: corner 0 of slot 0, as in the copying build
-    double rep[M][3];
-#pragma unroll
-    for (int m = 0; m < M; m++) {
-        const double *rv = X[m] + 3 * (int64_t)__builtin_amdgcn_readfirstlane((int)c[m][0][0]);
-        for (int k = 0; k < 3; k++) rep[m][k] = rv[k];
+        lo[0] = in ? fmin(lo[0], p0) : lo[0];
+        lo[1] = in ? fmin(lo[1], p1) : lo[1];
+        lo[2] = in ? fmin(lo[2], p2) : lo[2];
+        hi[0] = in ? fmax(hi[0], p0) : hi[0];
+        hi[1] = in ? fmax(hi[1], p1) : hi[1];
+        hi[2] = in ? fmax(hi[2], p2) : hi[2];
     }
+    // the representative vertex: corner 0 of slot 0 (the tile's first lane),
+    // as in the copying build
+    const uint32_t c0 = (uint32_t)__shfl((int)c[0][0], m * S);
 #pragma unroll
-    for (int m = 0; m < M; m++) {
+    for (int k = 0; k < 3; k++) {
+        lo[k] = group_min<S>(lo[k]);
+        hi[k] = group_max<S>(hi[k]);
+    }
+    // the tile's last lane holds its box and writes its metadata
+    if (on && sl == S - 1) {
         double o[3];
-        for (int k = 0; k < 3; k++) {
-            lo[m][k] = wave_min(lo[m][k]);
-            hi[m][k] = wave_max(hi[m][k]);
-            o[k] = (double)(float)(0.5 * lo[m][k] + 0.5 * hi[m][k]);
-        }
+        for (int k = 0; k < 3; k++) o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
         // rad as in the copying build: the largest FP64 offset magnitude
         // rounded once to FP32 (the same set of coordinates)
-        const double rad = (double)(float)box_offset_max(lo[m], hi[m], o);
+        const double rad = (double)(float)box_offset_max(lo, hi, o);
         const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
-        if (on[m] && lane == m) {
-            TileMeta mt;
-            for (int k = 0; k < 3; k++) {
-                mt.o[k] = o[k];
-                mt.lo[k] = lo[m][k];
-                mt.hi[k] = hi[m][k];
-                mt.rep[k] = rep[m][k];
-            }
-            mt.eps = (float)(err * (1.0 + 0x1p-20));
-            mt.rad = (float)rad;
-            mt.row = (int32_t)g[m];
-            mt.n = n[m];
-            J.meta[t0 + m] = mt;
-            J.mat[t0 + m] = 0u;
+        const double *rv = X + 3 * (int64_t)c0;
+        TileMeta mt;
+        for (int k = 0; k < 3; k++) {
+            mt.o[k] = o[k];
+            mt.lo[k] = lo[k];
+            mt.hi[k] = hi[k];
+            mt.rep[k] = rv[k];
         }
+        mt.eps = (float)(err * (1.0 + 0x1p-20));
+        mt.rad = (float)rad;
+        mt.row = (int32_t)gl;
+        mt.n = n;
+        J.meta[tl] = mt;
+        J.mat[tl] = 0u;
     }
 }
 
 // One wave per M tiles: waves [0, ceil(NT_A / M)) build A's tiles, the rest B's.
-template <int RT, int M>
+template <int TK, int M>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tiles_meta(TileJob A, TileJob B) {
-    __shared__ uint32_t hk[4][256 * RT * M];
-    __shared__ int32_t uv[4][3 * 64 * RT * M];
+    __shared__ uint32_t hk[4][M * 4 * TK];
+    __shared__ int32_t uv[4][M * 3 * TK];
     const int w = threadIdx.x >> 6;
     const int64_t v = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     const int64_t wa = (A.NT + M - 1) / M;
-    if (v < wa) tile_meta_wave<RT, M>(A, v * M, hk[w], uv[w]);
-    else if ((v - wa) * M < B.NT) tile_meta_wave<RT, M>(B, (v - wa) * M, hk[w], uv[w]);
+    if (v < wa) tile_meta_group<TK, M>(A, v * M, hk[w], uv[w]);
+    else if ((v - wa) * M < B.NT) tile_meta_group<TK, M>(B, (v - wa) * M, hk[w], uv[w]);
+}
+
+template <int TK, int M>
+static void launch_tiles_meta(const TileJob &ja, const TileJob &jb, hipStream_t s) {
+    const int64_t waves = (ja.NT + M - 1) / M + (jb.NT + M - 1) / M;
+    hipLaunchKernelGGL((k_tiles_meta<TK, M>), dim3(grid_for(waves, 4)), dim3(256), 0, s, ja, jb);
 }
 
 // Both sides are sorted in one sequence of launches (each row's items stay in
@@ -1265,13 +1252,10 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
         // waves in flight for the gathers
         const dim3 grid(grid_for(A.NT + B.NT, 4));
         if (lazy) {
-            // the metadata build takes two tiles per wave up to 64 triangles
-            constexpr int64_t MT = TILE_META_PER_WAVE;
-            const dim3 gm(grid_for((A.NT + MT - 1) / MT + (B.NT + MT - 1) / MT, 4));
-            if (A.tk > 64)
-                hipLaunchKernelGGL((k_tiles_meta<2, 1>), grid, dim3(256), 0, s, ja, jb);
-            else
-                hipLaunchKernelGGL((k_tiles_meta<1, MT>), gm, dim3(256), 0, s, ja, jb);
+            // the metadata build: tiles per wave by tile size
+            if (A.tk == 128) launch_tiles_meta<128, TILE_META_M128>(ja, jb, s);
+            else if (A.tk == 64) launch_tiles_meta<64, TILE_META_M64>(ja, jb, s);
+            else launch_tiles_meta<32, 4>(ja, jb, s);
         } else if (A.tk > 64) {
             hipLaunchKernelGGL(k_tiles<true>, grid, dim3(256), 0, s, ja, jb);
         } else {
