@@ -103,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, small, grpA, grpB, wi_lb, wlist, sorttab;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, small, grpA, grpB, wi_lb, wlist, sorttab;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -134,7 +134,7 @@ struct Workspace {
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &vcode, &small, &grpA, &grpB, &wi_lb,
+                        &vals0, &vals1, &hist, &part, &vcode, &kc, &small, &grpA, &grpB, &wi_lb,
                         &wlist, &sorttab, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
@@ -544,6 +544,9 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * (nb + 1) / 4096 + 2));
         C.PB.vcode = P.rsi > RS_ITEMS ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
                                       : nullptr;
+        // intersects on a large sort builds tiles of the triangles whose boxes
+        // meet the other side's row box only
+        C.PB.kc = (mode == 1 && C.PB.vcode) ? (int32_t *)ws.buf(ws.kc, sizeof(int32_t) * 2 * G) : nullptr;
         C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
                            G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
                                                     : nullptr};

@@ -85,6 +85,9 @@ struct PrepBufs {
     uint32_t *part;     // [chunks]
     uint32_t *vcode;    // [nvA + nvB] Morton code of every vertex, or nullptr (keys
                         // then quantise each first vertex themselves)
+    int32_t *kc;        // [2G] triangles kept per row (A rows, then B rows) when an
+                        // intersects call culls by the other side's row box
+                        // (large sorts only), else nullptr
     SortSeg seg;
     uint32_t *flags;    // [2] validation flags of A and B (the key kernel checks indices)
 };

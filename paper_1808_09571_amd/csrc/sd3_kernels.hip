@@ -159,9 +159,11 @@ __device__ void validate_tris(const TriSide &A, const TriSide &B, int64_t G, uns
 // ---------------------------------------------------------------------------
 // The first kernel of a call: clears the device scalars 0-11 (queue, rescue,
 // exact, seed, work items, exact blocks done), the validation flags of both
-// sides, the counters and the row boxes of both sides.
+// sides, the counters, the row boxes of both sides and the kept-triangle
+// counts of a culling call.
 __global__ void k_prep_init(unsigned int *sc, uint32_t *flags, unsigned long long *counters,
-                            unsigned long long *boxA, unsigned long long *boxB, int64_t nbox) {
+                            unsigned long long *boxA, unsigned long long *boxB, int64_t nbox,
+                            int32_t *kc, int64_t nkc) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < 12) sc[i] = 0u;
     if (i < 2) flags[i] = 0u;
@@ -171,6 +173,7 @@ __global__ void k_prep_init(unsigned int *sc, uint32_t *flags, unsigned long lon
         boxA[i] = v;
         boxB[i] = v;
     }
+    if (i < nkc) kc[i] = 0;
 }
 
 // Rows of the vertex chunks of a block's contiguous range: the row of vertex
@@ -368,9 +371,11 @@ void launch_validate_rowbox(SideBufs &A, SideBufs &B, PrepBufs &P, uint32_t *fla
                             hipStream_t s, bool indices) {
     const int64_t G = A.G;
     const int64_t nbox = (int64_t)A.boxrep * G * 6;
+    const int64_t nkc = P.kc ? 2 * G : 0;
     // (one block at least: C_NCOUNTERS <= 256)
-    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(nbox > 256 ? nbox : 256, 256)), dim3(256), 0, s,
-                       L.qcount, flags, L.counters, A.rowbox, B.rowbox, nbox);
+    const int64_t nz = std::max<int64_t>(256, std::max(nbox, nkc));
+    hipLaunchKernelGGL(k_prep_init, dim3(grid_for(nz, 256)), dim3(256), 0, s, L.qcount, flags, L.counters,
+                       A.rowbox, B.rowbox, nbox, P.kc, nkc);
     XyzSide xa{A.xyz, A.nv, A.v_off, A.rowbox, rowbox_blocks(A.nv), A.boxrep};
     XyzSide xb{B.xyz, B.nv, B.v_off, B.rowbox, rowbox_blocks(B.nv), B.boxrep};
     // (without `indices` the key kernel checks the triangle indices)
@@ -437,6 +442,7 @@ struct MortonSide {
     const int64_t *v_off, *t_off;
     const unsigned long long *box;
     const uint32_t *vcode;  // per-vertex codes (VC keys)
+    int32_t *kc;            // kept triangles per row (culling VC keys), else nullptr
 };
 
 // Per-vertex Morton codes for large sorts: the key kernel then gathers a
@@ -451,8 +457,24 @@ struct VcodeSide {
     const unsigned long long *box;
     uint32_t *code;
     unsigned nblk;
+    const unsigned long long *obox;  // the other side's row boxes (culling), else nullptr
 };
 
+// Outcode of point p against a box given as six ordered-bit components: bit
+// 2k set when coordinate k lies below the box, bit 2k + 1 when above.  A
+// triangle whose three vertices share a set bit lies entirely on the far
+// side of one of the box's planes, so its box misses that box (exact: the
+// comparisons are of the stored coordinates).
+__device__ __forceinline__ uint32_t outcode(const double *p, const unsigned long long *ob) {
+    uint32_t oc = 0;
+    for (int k = 0; k < 3; k++) {
+        oc |= (p[k] < from_ordered_bits(ob[k]) ? 1u : 0u) << (2 * k);
+        oc |= (p[k] > from_ordered_bits(ob[3 + k]) ? 1u : 0u) << (2 * k + 1);
+    }
+    return oc;
+}
+
+template <bool CULL>
 __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk) {
     const int lane = lane_id();
     const int64_t nv = S.nv;
@@ -460,6 +482,7 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
     const int64_t b0 = blk * per, b1 = min(nv, b0 + per);
     int64_t cg = -1;  // row whose cells are held (wave-uniform)
     double clo[3] = {0.0, 0.0, 0.0}, csc = 0.0;
+    unsigned long long cob[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};  // the other side's box (culling)
     RowCursor rc{0, 0};
     double pn[3] = {0.0, 0.0, 0.0};  // the next chunk's coordinates, in flight
     if (b0 < b1) {
@@ -476,29 +499,42 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
         const double p[3] = {pn[0], pn[1], pn[2]};
         if (i + 256 < b1)
             for (int k = 0; k < 3; k++) pn[k] = S.xyz[3 * (i + 256) + k];
+        // a culling call keeps the vertex's outcode against the other side's
+        // row box in the code's low 6 bits (keys use its top 24 bits at most)
         if (g0 == g1) {
             if (g0 != cg) {
-                const unsigned long long m = lane < 6 ? merged_box(S.box, rep, G, g0, lane) : 0ull;
+                const unsigned long long m = lane < 6 ? merged_box(S.box, rep, G, g0, lane)
+                                                      : (CULL && lane < 12 ? merged_box(S.obox, rep, G, g0, lane - 6) : 0ull);
                 unsigned long long b[6];
                 for (int k = 0; k < 6; k++) b[k] = __shfl(m, k);
+                if (CULL)
+                    for (int k = 0; k < 6; k++) cob[k] = __shfl(m, 6 + k);
                 csc = row_cells(b, clo);
                 cg = g0;
             }
-            if (valid) S.code[i] = morton_code(p, clo, csc);
+            if (valid) S.code[i] = CULL ? (morton_code(p, clo, csc) & ~63u) | outcode(p, cob) : morton_code(p, clo, csc);
         } else if (valid) {
             const int64_t g = lane_row(S.v_off, G, g0, g1, i);
             unsigned long long b[6];
             for (int k = 0; k < 6; k++) b[k] = merged_box(S.box, rep, G, g, k);
             double lo[3];
             const double sc = row_cells(b, lo);
-            S.code[i] = morton_code(p, lo, sc);
+            uint32_t code = morton_code(p, lo, sc);
+            if (CULL) {
+                unsigned long long ob[6];
+                for (int k = 0; k < 6; k++) ob[k] = merged_box(S.obox, rep, G, g, k);
+                code = (code & ~63u) | outcode(p, ob);
+            }
+            S.code[i] = code;
         }
     }
 }
 
+// CULL: a culling call (the sides' other-box pointers are set).
+template <bool CULL>
 __global__ __launch_bounds__(256) void k_vcode(VcodeSide A, VcodeSide B, int64_t G, int rep) {
-    if (blockIdx.x < A.nblk) vcode_side(A, G, rep, blockIdx.x);
-    else vcode_side(B, G, rep, blockIdx.x - A.nblk);
+    if (blockIdx.x < A.nblk) vcode_side<CULL>(A, G, rep, blockIdx.x);
+    else vcode_side<CULL>(B, G, rep, blockIdx.x - A.nblk);
 }
 
 // Sort block b's entry from the side's row offsets, the row found by `find`
@@ -569,7 +605,9 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
     if ((int64_t)blockIdx.x >= S.nb) return;  // the one block of a call with no items
     const SBlock k = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const MortonSide &M = k.side ? B : A;
+    __shared__ uint32_t nkeep;  // the block's kept triangles (culling)
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    if (threadIdx.x == 0) nkeep = 0;
     const int64_t vb = M.v_off[k.g];
     const int64_t nvr = M.v_off[k.g + 1] - vb;
     int64_t vi[PER];
@@ -595,13 +633,25 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         vi[r] = vb + ((tv[r][0] >= 0 && (int64_t)tv[r][0] < nvr) ? (int64_t)tv[r][0] : 0);
     }
     if (__ballot(bad) && lane == 0) atomicOr(flags + k.side, V_INDEX);
-    // the key point is the triangle's first vertex (keys only order work)
+    // the key point is the triangle's first vertex (keys only order work).
+    // A culling call also reads the other two vertices' outcodes: a triangle
+    // whose box misses the other side's row box cannot meet that side, gets
+    // the largest key (kept ones are held below it) and is not counted, so
+    // the row's kept triangles come first in its sorted range.
     double cen[VC ? 1 : PER][3];
     uint32_t code[PER];
+    bool cut[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
+        cut[r] = false;
         if (VC) {
             code[r] = ok[r] ? M.vcode[vi[r]] : 0u;
+            if (M.kc && ok[r]) {
+                const int32_t v1 = tv[r][1], v2 = tv[r][2];
+                const uint32_t o1 = M.vcode[vb + ((v1 >= 0 && (int64_t)v1 < nvr) ? (int64_t)v1 : 0)];
+                const uint32_t o2 = M.vcode[vb + ((v2 >= 0 && (int64_t)v2 < nvr) ? (int64_t)v2 : 0)];
+                cut[r] = (code[r] & o1 & o2 & 63u) != 0u;
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? M.xyz[3 * vi[r] + c] : 0.0;
@@ -620,13 +670,25 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         if (!ok[r]) continue;
         const int j = r * 1024 + (int)threadIdx.x;
         if (!VC) code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
-        const uint32_t key = code[r] >> (30 - mbits);
+        uint32_t key = code[r] >> (30 - mbits);
+        if (VC && M.kc) {
+            const uint32_t kmax = (1u << mbits) - 1u;
+            key = cut[r] ? kmax : min(key, kmax - 1u);
+        }
         keys[k.i0 + j] = key;
         vals[k.i0 + j] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
         atomicAdd(&h[key & 255u], 1u);
     }
+    if (VC && M.kc) {
+        uint32_t kept = 0;
+#pragma unroll
+        for (int r = 0; r < PER; r++) kept += (ok[r] && !cut[r]) ? 1u : 0u;
+        kept = wave_sum(kept);
+        if (lane == 0 && kept) atomicAdd(&nkeep, kept);
+    }
     __syncthreads();
     if (threadIdx.x < 256) hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
+    if (VC && M.kc && threadIdx.x == 0 && nkeep) atomicAdd(M.kc + k.g, (int32_t)nkeep);
 }
 
 // Stable LSD radix sort, 8-bit digits, within rows.  Blocks of 256 threads
@@ -905,6 +967,8 @@ struct TileJob {
     uint32_t *mat;  // 0: no copies yet, 1: written here
     float *t32;     // copies written here (small calls), else nullptr
     double *t64;
+    const int32_t *kc;  // triangles kept per row (a culling call: the first kc[g] of the
+                        // row's sorted range; the metadata build only), else nullptr
 };
 
 // Lane l of the wave owns slots l and l + 64 (the second only for tk = 128);
@@ -1062,7 +1126,13 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     const int64_t tl = on ? t0 + m : t0;
     const int64_t i = tl - J.tile_off[gl];
     const int64_t tlo = J.t_off[gl];
-    const int n = (int)min((int64_t)TK, J.t_off[gl + 1] - tlo - i * TK);
+    // a culling call's tiles hold the row's kept triangles only; a tile past
+    // them is empty (n = 0: it loads the first slot of its range, a real
+    // triangle, builds an empty box and is never a candidate)
+    const int64_t nrow = J.kc ? (int64_t)J.kc[gl] : J.t_off[gl + 1] - tlo;
+    const int n = (int)max((int64_t)0, min((int64_t)TK, nrow - i * TK));
+    const bool live = on && n > 0;
+    const int nl = max(n, 1);
     const int64_t pos = tlo + i * TK;
     const int64_t vb = J.v_off[gl];
     const int64_t nvr = J.v_off[gl + 1] - vb;
@@ -1071,7 +1141,7 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     uint32_t c[SL][3];
 #pragma unroll
     for (int r = 0; r < SL; r++) {
-        const int32_t w = J.sorted[pos + min(sl + S * r, n - 1)];
+        const int32_t w = J.sorted[pos + min(sl + S * r, nl - 1)];
         tri_id[r] = J.packed ? tlo + (w & 0xffffff) : w;
     }
 #pragma unroll
@@ -1087,7 +1157,7 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     // insert every slot's corners into the tile's table; a table holds at
     // most 3/4 of its size in keys, so every probe ends
     uint32_t *ht = hk + m * HS;
-    if (on)
+    if (live)
 #pragma unroll
         for (int r = 0; r < SL; r++)
 #pragma unroll
@@ -1145,14 +1215,16 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
         lo[k] = group_min<S>(lo[k]);
         hi[k] = group_max<S>(hi[k]);
     }
-    // the tile's last lane holds its box and writes its metadata
+    // the tile's last lane holds its box and writes its metadata (an empty
+    // tile: the empty box, origin 0, radius and error 0)
     if (on && sl == S - 1) {
-        double o[3];
-        for (int k = 0; k < 3; k++) o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
+        double o[3] = {0.0, 0.0, 0.0};
+        if (live)
+            for (int k = 0; k < 3; k++) o[k] = (double)(float)(0.5 * lo[k] + 0.5 * hi[k]);
         // rad as in the copying build: the largest FP64 offset magnitude
         // rounded once to FP32 (the same set of coordinates)
-        const double rad = (double)(float)box_offset_max(lo, hi, o);
-        const double err = 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149);
+        const double rad = live ? (double)(float)box_offset_max(lo, hi, o) : 0.0;
+        const double err = live ? 1.7321 * ((0x1p-24 + 0x1p-52) * rad * (1.0 + 0x1p-22) + 0x1p-149) : 0.0;
         const double *rv = X + 3 * (int64_t)c0;
         TileMeta mt;
         for (int k = 0; k < 3; k++) {
@@ -1172,7 +1244,7 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
 
 // One wave per M tiles: waves [0, ceil(NT_A / M)) build A's tiles, the rest B's.
 template <int TK, int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tiles_meta(TileJob A, TileJob B) {
+__global__ __launch_bounds__(256) void k_tiles_meta(TileJob A, TileJob B) {
     __shared__ uint32_t hk[4][M * 4 * TK];
     __shared__ int32_t uv[4][M * 3 * TK];
     const int w = threadIdx.x >> 6;
@@ -1210,13 +1282,18 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
                       hipStream_t s, KernelEvents *kev) {
     // large sorts take their keys from per-vertex codes (P.vcode is then set)
     constexpr bool VC = RSI > RS_ITEMS;
-    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode};
-    MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox, VC ? P.vcode + A.nv : nullptr};
+    // culling (P.kc) comes with per-vertex codes only
+    int32_t *kc = VC ? P.kc : nullptr;
+    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode, kc};
+    MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox, VC ? P.vcode + A.nv : nullptr,
+                  kc ? kc + A.G : nullptr};
     if (VC) {
-        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv)};
-        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv)};
-        if (ca.nblk + cb.nblk > 0)
-            hipLaunchKernelGGL(k_vcode, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
+        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv), kc ? B.rowbox : nullptr};
+        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv), kc ? A.rowbox : nullptr};
+        if (ca.nblk + cb.nblk > 0 && kc)
+            hipLaunchKernelGGL(k_vcode<true>, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
+        else if (ca.nblk + cb.nblk > 0)
+            hipLaunchKernelGGL(k_vcode<false>, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
     }
     if (P.seg.tab && P.seg.nb > 0)
         hipLaunchKernelGGL(k_sort_table, dim3(grid_for(P.seg.nb, 256)), dim3(256), 0, s, P.seg);
@@ -1244,10 +1321,12 @@ void launch_prep(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, RowSta
         const int32_t *sorted = K.narrow ? (const int32_t *)P.keys[cur] : P.vals[cur];
         const int pk = K.narrow ? 1 : 0;
         const bool lazy = lazy_copies(A, B);
+        // (a culling call is a large sort, so its copies are lazy)
         TileJob ja{A.xyz, A.tri, A.v_off, A.t_off, A.tile_off, A.G, A.NT, A.tk, sorted, pk, A.ids,
-                   A.meta, A.mat, lazy ? nullptr : A.t32, lazy ? nullptr : A.t64};
+                   A.meta, A.mat, lazy ? nullptr : A.t32, lazy ? nullptr : A.t64, P.kc};
         TileJob jb{B.xyz, B.tri, B.v_off, B.t_off, B.tile_off, B.G, B.NT, B.tk, sorted + A.nt, pk,
-                   B.ids, B.meta, B.mat, lazy ? nullptr : B.t32, lazy ? nullptr : B.t64};
+                   B.ids, B.meta, B.mat, lazy ? nullptr : B.t32, lazy ? nullptr : B.t64,
+                   P.kc ? P.kc + A.G : nullptr};
         // one slot per lane below 128-triangle tiles: fewer registers, more
         // waves in flight for the gathers
         const dim3 grid(grid_for(A.NT + B.NT, 4));
