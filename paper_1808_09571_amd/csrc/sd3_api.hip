@@ -103,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, small, grpA, grpB, wi_lb, wlist, sorttab;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, cub, small, grpA, grpB, wi_lb, wlist, sorttab;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -134,7 +134,7 @@ struct Workspace {
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &vcode, &kc, &small, &grpA, &grpB, &wi_lb,
+                        &vals0, &vals1, &hist, &part, &vcode, &kc, &cub, &small, &grpA, &grpB, &wi_lb,
                         &wlist, &sorttab, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
@@ -178,6 +178,7 @@ struct sd3_ctx {
 namespace {
 
 constexpr int64_t RESOLVE_MAX_ROWS = 64;           // FP64 rescue inside the exact launch
+constexpr int64_t CULL_MIN_ROWS = 64;              // pre-cull of large sorts above this many rows
 constexpr int64_t COMPACT_MIN_ROWS = 64;           // compacted work lists above this
 // device scalars: [0] queue count [1] queue head [2] rescue count [3] rescue
 // head [4] exact count [7] seed pass head [8] [9] work-item counts [11] exact
@@ -544,9 +545,16 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.part = (uint32_t *)ws.buf(ws.part, sizeof(uint32_t) * (256 * (nb + 1) / 4096 + 2));
         C.PB.vcode = P.rsi > RS_ITEMS ? (uint32_t *)ws.buf(ws.vcode, sizeof(uint32_t) * (C.A.nv + C.B.nv))
                                       : nullptr;
-        // intersects on a large sort builds tiles of the triangles whose boxes
-        // meet the other side's row box only
-        C.PB.kc = (mode == 1 && C.PB.vcode) ? (int32_t *)ws.buf(ws.kc, sizeof(int32_t) * 2 * G) : nullptr;
+        // a large sort of many rows builds tiles of the triangles whose boxes
+        // meet the other side's row box only (intersects), or come within the
+        // row's cull distance of it (distance; not in allocation-free calls,
+        // whose static scratch keeps its size).  A call of a few rows is a
+        // short chain of launches whose tile build is small: the cull's extra
+        // loads cost it more than they save (the 4M-triangle TIN against the
+        // 1M-triangle blob: 0.435 -> 0.509 ms per distance call)
+        const bool cull = C.PB.vcode && G > CULL_MIN_ROWS && (mode == 1 || (mode == 0 && !ws.arena));
+        C.PB.kc = cull ? (int32_t *)ws.buf(ws.kc, sizeof(int32_t) * 2 * G) : nullptr;
+        C.PB.cub = cull && mode == 0 ? (double *)ws.buf(ws.cub, sizeof(double) * G) : nullptr;
         C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
                            G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
                                                     : nullptr};

@@ -85,9 +85,12 @@ struct PrepBufs {
     uint32_t *part;     // [chunks]
     uint32_t *vcode;    // [nvA + nvB] Morton code of every vertex, or nullptr (keys
                         // then quantise each first vertex themselves)
-    int32_t *kc;        // [2G] triangles kept per row (A rows, then B rows) when an
-                        // intersects call culls by the other side's row box
-                        // (large sorts only), else nullptr
+    int32_t *kc;        // [2G] triangles kept per row (A rows, then B rows) when a
+                        // call culls by the other side's row box (large sorts
+                        // only), else nullptr
+    double *cub;        // [G] a distance call's cull distance per row (an upper
+                        // bound of the row distance plus a margin), else nullptr
+                        // (intersects culls by the box itself)
     SortSeg seg;
     uint32_t *flags;    // [2] validation flags of A and B (the key kernel checks indices)
 };

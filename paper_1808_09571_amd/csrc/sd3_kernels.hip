@@ -458,20 +458,82 @@ struct VcodeSide {
     uint32_t *code;
     unsigned nblk;
     const unsigned long long *obox;  // the other side's row boxes (culling), else nullptr
+    const double *cub;               // per row: how far beyond that box a triangle is
+                                     // still kept (distance calls), else nullptr (0)
 };
 
-// Outcode of point p against a box given as six ordered-bit components: bit
-// 2k set when coordinate k lies below the box, bit 2k + 1 when above.  A
-// triangle whose three vertices share a set bit lies entirely on the far
-// side of one of the box's planes, so its box misses that box (exact: the
-// comparisons are of the stored coordinates).
-__device__ __forceinline__ uint32_t outcode(const double *p, const unsigned long long *ob) {
+// The other side's row box (six ordered-bit components) widened by e >= 0 on
+// every side and then by 2^-50 (|bound| + e), far more than the rounding of
+// the two operations (2^-53 of that each), so that a point outside it is
+// farther than e from the box along that axis.
+__device__ __forceinline__ void cull_box(const unsigned long long *ob, double e, double lo[3], double hi[3]) {
+    for (int k = 0; k < 3; k++) {
+        lo[k] = from_ordered_bits(ob[k]);
+        hi[k] = from_ordered_bits(ob[3 + k]);
+        if (e > 0.0) {
+            lo[k] = (lo[k] - e) - 0x1p-50 * (fabs(lo[k]) + e);
+            hi[k] = (hi[k] + e) + 0x1p-50 * (fabs(hi[k]) + e);
+        }
+    }
+}
+
+// Outcode of point p against that box: bit 2k set when coordinate k lies
+// below it, bit 2k + 1 when above.  A triangle whose three vertices share a
+// set bit lies entirely beyond one of the box's planes (exact comparisons of
+// the stored coordinates), so it is farther than e from every point of the
+// other side.
+__device__ __forceinline__ uint32_t outcode(const double *p, const double *lo, const double *hi) {
     uint32_t oc = 0;
     for (int k = 0; k < 3; k++) {
-        oc |= (p[k] < from_ordered_bits(ob[k]) ? 1u : 0u) << (2 * k);
-        oc |= (p[k] > from_ordered_bits(ob[3 + k]) ? 1u : 0u) << (2 * k + 1);
+        oc |= (p[k] < lo[k] ? 1u : 0u) << (2 * k);
+        oc |= (p[k] > hi[k] ? 1u : 0u) << (2 * k + 1);
     }
     return oc;
+}
+
+// Cull distance of each row for a distance call: the smallest distance
+// between corners of 64 evenly spaced triangles of each side (two surface
+// points bound the row distance from above), rounded up, plus a margin far
+// above the FP64 rounding of any pair distance in the row (2^-30 of the row
+// extent and of the bound; the pruning margin is 2^-36 of both), so that a
+// triangle culled by it could not hold the FP64 minimum.  One wave per row.
+struct UbSide {
+    const double *xyz;
+    const int32_t *tri;
+    const int64_t *v_off, *t_off;
+    const unsigned long long *box;
+};
+
+__global__ __launch_bounds__(256) void k_row_ub(UbSide A, UbSide B, int64_t G, int rep, double *cub) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= G) return;  // (wave-uniform)
+    const int lane = lane_id();
+    const int64_t ta = A.t_off[g], na = A.t_off[g + 1] - ta, tb = B.t_off[g], nb = B.t_off[g + 1] - tb;
+    if (na == 0 || nb == 0) {
+        if (lane == 0) cub[g] = __builtin_inf();
+        return;
+    }
+    const int64_t va = A.v_off[g], vb = B.v_off[g];
+    const double *pa = A.xyz + 3 * (va + corner(A.tri, ta + (lane * na) / 64, 0, A.v_off[g + 1] - va));
+    const double *pb = B.xyz + 3 * (vb + corner(B.tri, tb + (lane * nb) / 64, 0, B.v_off[g + 1] - vb));
+    const double p0 = pa[0], p1 = pa[1], p2 = pa[2];
+    const double q0 = pb[0], q1 = pb[1], q2 = pb[2];
+    double m = __builtin_inf();
+    for (int j = 0; j < 64; j++) {
+        const double d0 = p0 - __shfl(q0, j), d1 = p1 - __shfl(q1, j), d2 = p2 - __shfl(q2, j);
+        m = fmin(m, d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    m = wave_min(m);
+    double ext2 = 0.0;
+    for (int k = 0; k < 3; k++) {
+        const double lo = fmin(from_ordered_bits(merged_box(A.box, rep, G, g, k)),
+                               from_ordered_bits(merged_box(B.box, rep, G, g, k)));
+        const double hi = fmax(from_ordered_bits(merged_box(A.box, rep, G, g, 3 + k)),
+                               from_ordered_bits(merged_box(B.box, rep, G, g, 3 + k)));
+        ext2 += (hi - lo) * (hi - lo);
+    }
+    const double ub = sqrt(m) * (1.0 + 8.0 * U64);
+    if (lane == 0) cub[g] = ub + 0x1p-30 * (sqrt(ext2) * 1.01 + ub);
 }
 
 template <bool CULL>
@@ -482,7 +544,7 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
     const int64_t b0 = blk * per, b1 = min(nv, b0 + per);
     int64_t cg = -1;  // row whose cells are held (wave-uniform)
     double clo[3] = {0.0, 0.0, 0.0}, csc = 0.0;
-    unsigned long long cob[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};  // the other side's box (culling)
+    double olo[3] = {0.0, 0.0, 0.0}, ohi[3] = {0.0, 0.0, 0.0};  // the row's cull box
     RowCursor rc{0, 0};
     double pn[3] = {0.0, 0.0, 0.0};  // the next chunk's coordinates, in flight
     if (b0 < b1) {
@@ -507,12 +569,15 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
                                                       : (CULL && lane < 12 ? merged_box(S.obox, rep, G, g0, lane - 6) : 0ull);
                 unsigned long long b[6];
                 for (int k = 0; k < 6; k++) b[k] = __shfl(m, k);
-                if (CULL)
-                    for (int k = 0; k < 6; k++) cob[k] = __shfl(m, 6 + k);
+                if (CULL) {
+                    unsigned long long ob[6];
+                    for (int k = 0; k < 6; k++) ob[k] = __shfl(m, 6 + k);
+                    cull_box(ob, S.cub ? S.cub[g0] : 0.0, olo, ohi);
+                }
                 csc = row_cells(b, clo);
                 cg = g0;
             }
-            if (valid) S.code[i] = CULL ? (morton_code(p, clo, csc) & ~63u) | outcode(p, cob) : morton_code(p, clo, csc);
+            if (valid) S.code[i] = CULL ? (morton_code(p, clo, csc) & ~63u) | outcode(p, olo, ohi) : morton_code(p, clo, csc);
         } else if (valid) {
             const int64_t g = lane_row(S.v_off, G, g0, g1, i);
             unsigned long long b[6];
@@ -523,7 +588,9 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
             if (CULL) {
                 unsigned long long ob[6];
                 for (int k = 0; k < 6; k++) ob[k] = merged_box(S.obox, rep, G, g, k);
-                code = (code & ~63u) | outcode(p, ob);
+                double bl[3], bh[3];
+                cull_box(ob, S.cub ? S.cub[g] : 0.0, bl, bh);
+                code = (code & ~63u) | outcode(p, bl, bh);
             }
             S.code[i] = code;
         }
@@ -1288,8 +1355,13 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
     MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox, VC ? P.vcode + A.nv : nullptr,
                   kc ? kc + A.G : nullptr};
     if (VC) {
-        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv), kc ? B.rowbox : nullptr};
-        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv), kc ? A.rowbox : nullptr};
+        const double *cub = kc ? P.cub : nullptr;
+        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv), kc ? B.rowbox : nullptr, cub};
+        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv), kc ? A.rowbox : nullptr, cub};
+        if (cub && A.G > 0)
+            hipLaunchKernelGGL(k_row_ub, dim3(grid_for(A.G, 4)), dim3(256), 0, s,
+                               UbSide{A.xyz, A.tri, A.v_off, A.t_off, A.rowbox},
+                               UbSide{B.xyz, B.tri, B.v_off, B.t_off, B.rowbox}, A.G, A.boxrep, P.cub);
         if (ca.nblk + cb.nblk > 0 && kc)
             hipLaunchKernelGGL(k_vcode<true>, dim3(ca.nblk + cb.nblk), dim3(256), 0, s, ca, cb, A.G, A.boxrep);
         else if (ca.nblk + cb.nblk > 0)
