@@ -744,14 +744,19 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         }
         keys[k.i0 + j] = key;
         vals[k.i0 + j] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
-        atomicAdd(&h[key & 255u], 1u);
+        // culled items all fall in the last digit: counted per wave below
+        // (one LDS atomic instead of one per item on a single address)
+        if (!cut[r]) atomicAdd(&h[key & 255u], 1u);
     }
     if (VC && M.kc) {
-        uint32_t kept = 0;
+        uint32_t kept = 0, ncut = 0;
 #pragma unroll
-        for (int r = 0; r < PER; r++) kept += (ok[r] && !cut[r]) ? 1u : 0u;
-        kept = wave_sum(kept);
+        for (int r = 0; r < PER; r++) {
+            kept += (uint32_t)__popcll(__ballot(ok[r] && !cut[r]));
+            ncut += (uint32_t)__popcll(__ballot(ok[r] && cut[r]));
+        }
         if (lane == 0 && kept) atomicAdd(&nkeep, kept);
+        if (lane == 0 && ncut) atomicAdd(&h[((1u << mbits) - 1u) & 255u], ncut);
     }
     __syncthreads();
     if (threadIdx.x < 256) hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
@@ -776,9 +781,18 @@ __global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *his
 #pragma unroll
     for (int r = 0; r < PER; r++) kv[r] = keys[k.i0 + min(r * 256 + (int)threadIdx.x, k.n - 1)];
     __syncthreads();
+    // items of digit 255 (the culled items of a culling call, all in one
+    // digit) are counted per wave: one LDS atomic instead of one per item on
+    // a single address
+    uint32_t n255 = 0;
 #pragma unroll
-    for (int r = 0; r < PER; r++)
-        if (r * 256 + (int)threadIdx.x < k.n) atomicAdd(&h[(kv[r] >> shift) & 255], 1u);
+    for (int r = 0; r < PER; r++) {
+        const bool in = r * 256 + (int)threadIdx.x < k.n;
+        const uint32_t dg = (kv[r] >> shift) & 255;
+        n255 += (uint32_t)__popcll(__ballot(in && dg == 255u));
+        if (in && dg != 255u) atomicAdd(&h[dg], 1u);
+    }
+    if (lane_id() == 0 && n255) atomicAdd(&h[255], n255);
     __syncthreads();
     hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
 }
