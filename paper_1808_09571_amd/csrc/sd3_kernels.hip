@@ -713,15 +713,22 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         cut[r] = false;
         if (VC) {
             code[r] = ok[r] ? M.vcode[vi[r]] : 0u;
-            if (M.kc && ok[r]) {
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? M.xyz[3 * vi[r] + c] : 0.0;
+        }
+    }
+    // (the other two codes only where the first vertex lies outside: a zero
+    // outcode keeps the triangle whatever the others are)
+    if (VC && M.kc) {
+#pragma unroll
+        for (int r = 0; r < PER; r++) {
+            if (ok[r] && (code[r] & 63u) != 0u) {
                 const int32_t v1 = tv[r][1], v2 = tv[r][2];
                 const uint32_t o1 = M.vcode[vb + ((v1 >= 0 && (int64_t)v1 < nvr) ? (int64_t)v1 : 0)];
                 const uint32_t o2 = M.vcode[vb + ((v2 >= 0 && (int64_t)v2 < nvr) ? (int64_t)v2 : 0)];
                 cut[r] = (code[r] & o1 & o2 & 63u) != 0u;
             }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; c++) cen[VC ? 0 : r][c] = ok[r] ? M.xyz[3 * vi[r] + c] : 0.0;
         }
     }
     double lo[3] = {0.0, 0.0, 0.0}, sc = 0.0;
