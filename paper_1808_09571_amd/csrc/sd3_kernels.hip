@@ -1225,6 +1225,30 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     const int64_t vb = J.v_off[gl];
     const int64_t nvr = J.v_off[gl + 1] - vb;
     const double *X = J.xyz + 3 * vb;
+    // a wave whose tiles are all empty (the kept triangles lead each row, so
+    // most waves past them hold no live tile) writes their metadata only:
+    // the empty box and, as the representative, corner 0 of the first slot
+    if (!__any(live)) {
+        if (on && sl == S - 1) {
+            const int32_t w = J.sorted[pos];
+            const int64_t t = J.packed ? tlo + (w & 0xffffff) : w;
+            const double *rv = X + 3 * corner(J.tri, t, 0, nvr);
+            TileMeta mt;
+            for (int k = 0; k < 3; k++) {
+                mt.o[k] = 0.0;
+                mt.lo[k] = __builtin_inf();
+                mt.hi[k] = -__builtin_inf();
+                mt.rep[k] = rv[k];
+            }
+            mt.eps = 0.0f;
+            mt.rad = 0.0f;
+            mt.row = (int32_t)gl;
+            mt.n = 0;
+            J.meta[tl] = mt;
+            J.mat[tl] = 0u;
+        }
+        return;
+    }
     int64_t tri_id[SL];
     uint32_t c[SL][3];
 #pragma unroll
@@ -1238,7 +1262,8 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     for (int r = 0; r < SL; r++)
 #pragma unroll
         for (int k = 0; k < 3; k++) c[r][k] = (uint32_t)corner(J.tri, tri_id[r], k, nvr);
-    if (on)
+    // (an empty tile's slots are never read)
+    if (live)
 #pragma unroll
         for (int r = 0; r < SL; r++) J.ids[tl * TK + sl + S * r] = (int32_t)tri_id[r];
     wave_lds_sync();
