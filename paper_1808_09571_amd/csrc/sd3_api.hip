@@ -103,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, cub, small, grpA, grpB, wi_lb, wlist, sorttab;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, cub, oc, small, grpA, grpB, wi_lb, wlist, sorttab;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -134,7 +134,7 @@ struct Workspace {
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &vcode, &kc, &cub, &small, &grpA, &grpB, &wi_lb,
+                        &vals0, &vals1, &hist, &part, &vcode, &kc, &cub, &oc, &small, &grpA, &grpB, &wi_lb,
                         &wlist, &sorttab, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
@@ -555,6 +555,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         const bool cull = C.PB.vcode && G > CULL_MIN_ROWS && (mode == 1 || (mode == 0 && !ws.arena));
         C.PB.kc = cull ? (int32_t *)ws.buf(ws.kc, sizeof(int32_t) * 2 * G) : nullptr;
         C.PB.cub = cull && mode == 0 ? (double *)ws.buf(ws.cub, sizeof(double) * G) : nullptr;
+        C.PB.oc = cull ? (uint8_t *)ws.buf(ws.oc, (size_t)(C.A.nv + C.B.nv)) : nullptr;
         C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
                            G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
                                                     : nullptr};

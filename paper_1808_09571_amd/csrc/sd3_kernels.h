@@ -88,6 +88,7 @@ struct PrepBufs {
     int32_t *kc;        // [2G] triangles kept per row (A rows, then B rows) when a
                         // call culls by the other side's row box (large sorts
                         // only), else nullptr
+    uint8_t *oc;        // [nvA + nvB] every vertex's outcode (culling calls), else nullptr
     double *cub;        // [G] a distance call's cull distance per row (an upper
                         // bound of the row distance plus a margin), else nullptr
                         // (intersects culls by the box itself)

@@ -443,6 +443,7 @@ struct MortonSide {
     const unsigned long long *box;
     const uint32_t *vcode;  // per-vertex codes (VC keys)
     int32_t *kc;            // kept triangles per row (culling VC keys), else nullptr
+    const uint8_t *oc;      // per-vertex outcodes (culling), else nullptr
 };
 
 // Per-vertex Morton codes for large sorts: the key kernel then gathers a
@@ -460,6 +461,9 @@ struct VcodeSide {
     const unsigned long long *obox;  // the other side's row boxes (culling), else nullptr
     const double *cub;               // per row: how far beyond that box a triangle is
                                      // still kept (distance calls), else nullptr (0)
+    uint8_t *oc;                     // the outcodes again, one byte per vertex (culling):
+                                     // the key kernel gathers two per triangle from this
+                                     // array, a quarter of the codes' footprint
 };
 
 // The other side's row box (six ordered-bit components) widened by e >= 0 on
@@ -577,7 +581,13 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
                 csc = row_cells(b, clo);
                 cg = g0;
             }
-            if (valid) S.code[i] = CULL ? (morton_code(p, clo, csc) & ~63u) | outcode(p, olo, ohi) : morton_code(p, clo, csc);
+            if (valid && CULL) {
+                const uint32_t oc = outcode(p, olo, ohi);
+                S.code[i] = (morton_code(p, clo, csc) & ~63u) | oc;
+                S.oc[i] = (uint8_t)oc;
+            } else if (valid) {
+                S.code[i] = morton_code(p, clo, csc);
+            }
         } else if (valid) {
             const int64_t g = lane_row(S.v_off, G, g0, g1, i);
             unsigned long long b[6];
@@ -590,7 +600,9 @@ __device__ void vcode_side(const VcodeSide &S, int64_t G, int rep, unsigned blk)
                 for (int k = 0; k < 6; k++) ob[k] = merged_box(S.obox, rep, G, g, k);
                 double bl[3], bh[3];
                 cull_box(ob, S.cub ? S.cub[g] : 0.0, bl, bh);
-                code = (code & ~63u) | outcode(p, bl, bh);
+                const uint32_t oc = outcode(p, bl, bh);
+                code = (code & ~63u) | oc;
+                S.oc[i] = (uint8_t)oc;
             }
             S.code[i] = code;
         }
@@ -725,8 +737,8 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         for (int r = 0; r < PER; r++) {
             if (ok[r] && (code[r] & 63u) != 0u) {
                 const int32_t v1 = tv[r][1], v2 = tv[r][2];
-                const uint32_t o1 = M.vcode[vb + ((v1 >= 0 && (int64_t)v1 < nvr) ? (int64_t)v1 : 0)];
-                const uint32_t o2 = M.vcode[vb + ((v2 >= 0 && (int64_t)v2 < nvr) ? (int64_t)v2 : 0)];
+                const uint32_t o1 = M.oc[vb + ((v1 >= 0 && (int64_t)v1 < nvr) ? (int64_t)v1 : 0)];
+                const uint32_t o2 = M.oc[vb + ((v2 >= 0 && (int64_t)v2 < nvr) ? (int64_t)v2 : 0)];
                 cut[r] = (code[r] & o1 & o2 & 63u) != 0u;
             }
         }
@@ -1397,13 +1409,15 @@ static int sort_items(SideBufs &A, SideBufs &B, PrepBufs &P, const SortKey &K, R
     constexpr bool VC = RSI > RS_ITEMS;
     // culling (P.kc) comes with per-vertex codes only
     int32_t *kc = VC ? P.kc : nullptr;
-    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode, kc};
+    MortonSide ma{A.xyz, A.tri, A.nt, A.v_off, A.t_off, A.rowbox, P.vcode, kc, kc ? P.oc : nullptr};
     MortonSide mb{B.xyz, B.tri, B.nt, B.v_off, B.t_off, B.rowbox, VC ? P.vcode + A.nv : nullptr,
-                  kc ? kc + A.G : nullptr};
+                  kc ? kc + A.G : nullptr, kc ? P.oc + A.nv : nullptr};
     if (VC) {
         const double *cub = kc ? P.cub : nullptr;
-        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv), kc ? B.rowbox : nullptr, cub};
-        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv), kc ? A.rowbox : nullptr, cub};
+        VcodeSide ca{A.xyz, A.nv, A.v_off, A.rowbox, P.vcode, rowbox_blocks(A.nv), kc ? B.rowbox : nullptr, cub,
+                     kc ? P.oc : nullptr};
+        VcodeSide cb{B.xyz, B.nv, B.v_off, B.rowbox, P.vcode + A.nv, rowbox_blocks(B.nv), kc ? A.rowbox : nullptr, cub,
+                     kc ? P.oc + A.nv : nullptr};
         if (cub && A.G > 0)
             hipLaunchKernelGGL(k_row_ub, dim3(grid_for(A.G, 4)), dim3(256), 0, s,
                                UbSide{A.xyz, A.tri, A.v_off, A.t_off, A.rowbox},
