@@ -558,7 +558,8 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.oc = cull ? (uint8_t *)ws.buf(ws.oc, (size_t)(C.A.nv + C.B.nv)) : nullptr;
         C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
                            G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
-                                                    : nullptr};
+                                                    : nullptr,
+                           C.PB.kc};
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;

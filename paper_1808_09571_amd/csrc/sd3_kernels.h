@@ -73,6 +73,9 @@ struct SortSeg {
     int rsi;                       // items per block
     SBlock *tab;                   // [nb] every block's entry (calls of many rows), or nullptr:
                                    // each block then finds its own
+    const int32_t *kc;             // [2G] kept items per row of a culling call, else nullptr:
+                                   // after the first pass they lead each row's range and
+                                   // later passes read and place only them
 };
 // Calls of at least this many rows build the sort-block table first.
 constexpr int64_t SORT_TABLE_MIN_ROWS = 64;

@@ -758,8 +758,13 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         if (!VC) code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
         uint32_t key = code[r] >> (30 - mbits);
         if (VC && M.kc) {
+            // kept keys hold no 255 digit (each byte capped at 254), so that
+            // every pass places the culled items, all 255 digits, at the end
+            // of the row
             const uint32_t kmax = (1u << mbits) - 1u;
-            key = cut[r] ? kmax : min(key, kmax - 1u);
+            uint32_t kk = 0;
+            for (int sh = 0; sh < mbits; sh += 8) kk |= min((key >> sh) & 255u, 254u) << sh;
+            key = cut[r] ? kmax : kk;
         }
         keys[k.i0 + j] = key;
         vals[k.i0 + j] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
@@ -788,6 +793,16 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
 // exclusive scan over (row, digit, block), and a stable scatter that ranks
 // equal digits inside a wave with ballots.
 
+// Items of sort block k that a pass after the first reads: all of them, or
+// in a culling call the part of the block inside its row's kept prefix (the
+// first pass put the kept items first, the culled ones, all digits 255, at
+// the row's end, where no later pass reads or writes them).
+__device__ __forceinline__ int kept_in_block(const SortSeg &S, const SBlock &k) {
+    if (!S.kc) return k.n;
+    const int64_t kept = (int64_t)S.kc[(k.side ? S.G : 0) + k.g] - (int64_t)k.loc;
+    return (int)max((int64_t)0, min((int64_t)k.n, kept));
+}
+
 template <int RS_ITEMS>
 __global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *hist) {
     constexpr int PER = RS_ITEMS / 256;
@@ -796,17 +811,21 @@ __global__ void k_hist(const uint32_t *keys, SortSeg S, int shift, uint32_t *his
     const SBlock k = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     // every load first, at clamped indices (n >= 1 here), so that the thread
     // waits for one memory latency rather than one per item
+    // (a culling call: this pass reads the row's kept prefix only; the
+    // block's other items, culled, all have digit 255 and are counted there
+    // without being read)
+    const int nv = kept_in_block(S, k);
     uint32_t kv[PER];
 #pragma unroll
-    for (int r = 0; r < PER; r++) kv[r] = keys[k.i0 + min(r * 256 + (int)threadIdx.x, k.n - 1)];
+    for (int r = 0; r < PER; r++) kv[r] = keys[k.i0 + max(0, min(r * 256 + (int)threadIdx.x, nv - 1))];
     __syncthreads();
     // items of digit 255 (the culled items of a culling call, all in one
     // digit) are counted per wave: one LDS atomic instead of one per item on
     // a single address
-    uint32_t n255 = 0;
+    uint32_t n255 = threadIdx.x == 0 ? (uint32_t)(k.n - nv) : 0u;
 #pragma unroll
     for (int r = 0; r < PER; r++) {
-        const bool in = r * 256 + (int)threadIdx.x < k.n;
+        const bool in = r * 256 + (int)threadIdx.x < nv;
         const uint32_t dg = (kv[r] >> shift) & 255;
         n255 += (uint32_t)__popcll(__ballot(in && dg == 255u));
         if (in && dg != 255u) atomicAdd(&h[dg], 1u);
@@ -884,7 +903,8 @@ __global__ __launch_bounds__(64) void k_scan_top(uint32_t *part, int64_t n) {
 template <int RS_ITEMS, int MODE>
 __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout,
                                                  int32_t *vout, SortSeg S, int shift,
-                                                 const uint32_t *hist, const uint32_t *part, int ncraw) {
+                                                 const uint32_t *hist, const uint32_t *part, int ncraw,
+                                                 int later) {
     using KT = uint32_t;
     constexpr int Q = RS_ITEMS / 4;   // items per wave
     constexpr int R = Q / 64;         // rounds per wave
@@ -900,7 +920,11 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const SBlock sbk = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
     const int64_t b0 = sbk.i0;
-    const int64_t n = b0 + sbk.n;  // items of this block: [b0, n)
+    // items of this block: [b0, n); after the first pass of a culling call
+    // the kept ones only (the culled ones keep their reserved places, digit
+    // 255 at the row's end, unwritten)
+    const int nvalid = later ? kept_in_block(S, sbk) : sbk.n;
+    const int64_t n = b0 + nvalid;
     if (ncraw > 0) {
         // exclusive scan of the raw chunk totals (one per thread) into loff
         __shared__ uint32_t csum[4];
@@ -978,7 +1002,6 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
         }
     }
     __syncthreads();
-    const int nvalid = sbk.n;
     for (int j = tid; j < nvalid; j += 256) {
         const KT k = skey[j];
         const uint32_t d = MODE == 1 ? (uint32_t)sdig[j] : (uint32_t)((k >> shift) & 255);
@@ -1015,15 +1038,16 @@ static int radix_sort(uint32_t **keys, int32_t **vals, uint32_t *hist, uint32_t 
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, part, (int64_t)nchunk);
         if (kev) kev->begin(KE_SCATTER, s);
         const int ncr = inline_top ? nchunk : 0;
+        const int later = p > 0 ? 1 : 0;
         if (mode == 2)
             hipLaunchKernelGGL((k_scatter<RS_ITEMS, 2>), dim3(nb), dim3(256), 0, s, keys[cur], nullptr,
-                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr);
+                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr, later);
         else if (mode == 1)
             hipLaunchKernelGGL((k_scatter<RS_ITEMS, 1>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr);
+                               keys[cur ^ 1], nullptr, S, shift, hist, part, ncr, later);
         else
             hipLaunchKernelGGL((k_scatter<RS_ITEMS, 0>), dim3(nb), dim3(256), 0, s, keys[cur], vals[cur],
-                               last ? nullptr : keys[cur ^ 1], vals[cur ^ 1], S, shift, hist, part, ncr);
+                               last ? nullptr : keys[cur ^ 1], vals[cur ^ 1], S, shift, hist, part, ncr, later);
         if (kev) kev->end(KE_SCATTER, s);
         cur ^= 1;
     }
@@ -1227,12 +1251,12 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     const int64_t i = tl - J.tile_off[gl];
     const int64_t tlo = J.t_off[gl];
     // a culling call's tiles hold the row's kept triangles only; a tile past
-    // them is empty (n = 0: it loads the first slot of its range, a real
-    // triangle, builds an empty box and is never a candidate)
+    // them is empty (n = 0: it takes the row's first triangle, a real one,
+    // builds an empty box and is never a candidate; the sorted range past
+    // the kept items is not written)
     const int64_t nrow = J.kc ? (int64_t)J.kc[gl] : J.t_off[gl + 1] - tlo;
     const int n = (int)max((int64_t)0, min((int64_t)TK, nrow - i * TK));
     const bool live = on && n > 0;
-    const int nl = max(n, 1);
     const int64_t pos = tlo + i * TK;
     const int64_t vb = J.v_off[gl];
     const int64_t nvr = J.v_off[gl + 1] - vb;
@@ -1242,9 +1266,7 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     // the empty box and, as the representative, corner 0 of the first slot
     if (!__any(live)) {
         if (on && sl == S - 1) {
-            const int32_t w = J.sorted[pos];
-            const int64_t t = J.packed ? tlo + (w & 0xffffff) : w;
-            const double *rv = X + 3 * corner(J.tri, t, 0, nvr);
+            const double *rv = X + 3 * corner(J.tri, tlo, 0, nvr);
             TileMeta mt;
             for (int k = 0; k < 3; k++) {
                 mt.o[k] = 0.0;
@@ -1265,8 +1287,11 @@ __device__ void tile_meta_group(const TileJob &J, int64_t t0, uint32_t *hk, int3
     uint32_t c[SL][3];
 #pragma unroll
     for (int r = 0; r < SL; r++) {
-        const int32_t w = J.sorted[pos + min(sl + S * r, nl - 1)];
-        tri_id[r] = J.packed ? tlo + (w & 0xffffff) : w;
+        tri_id[r] = tlo;
+        if (n > 0) {
+            const int32_t w = J.sorted[pos + min(sl + S * r, n - 1)];
+            tri_id[r] = J.packed ? tlo + (w & 0xffffff) : w;
+        }
     }
 #pragma unroll
     for (int q = 0; q < M * HS / 64; q++) hk[q * 64 + lane] = HASH_EMPTY;
