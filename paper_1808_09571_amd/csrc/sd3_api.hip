@@ -103,7 +103,7 @@ void *ensure(DevBuf &b, size_t bytes);
 struct Workspace {
     SideState side[2];
     DevBuf rows, queue, qlb, rescue, exact, scalars, out_d;
-    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, cub, oc, small, grpA, grpB, wi_lb, wlist, sorttab;
+    DevBuf keys0, keys1, vals0, vals1, hist, part, vcode, kc, cub, oc, bn, small, grpA, grpB, wi_lb, wlist, sorttab;
     DevBuf seg_in, seg_mesh, seg_out;  // segment calls: staged inputs, prepared mesh, outputs
     DevBuf vol_items, vol_part;        // volume calls: work items, partial sums
     DevBuf solid;                      // solid semantics: queries, directions, results
@@ -134,7 +134,7 @@ struct Workspace {
             for (DevBuf *b : bs) release(*b);
         }
         DevBuf *bs[] = {&rows, &queue, &qlb, &rescue, &exact, &scalars, &out_d, &keys0, &keys1,
-                        &vals0, &vals1, &hist, &part, &vcode, &kc, &cub, &oc, &small, &grpA, &grpB, &wi_lb,
+                        &vals0, &vals1, &hist, &part, &vcode, &kc, &cub, &oc, &bn, &small, &grpA, &grpB, &wi_lb,
                         &wlist, &sorttab, &seg_in, &seg_mesh, &seg_out, &vol_items, &vol_part, &solid};
         for (DevBuf *b : bs) release(*b);
     }
@@ -559,7 +559,7 @@ void plan_call(sd3_ctx *ctx, Workspace &ws, const sd3_geoms *a, const sd3_geoms 
         C.PB.seg = SortSeg{ds + 9 * G1, ds + 10 * G1, C.A.t_off, C.B.t_off, G, C.A.nt, P.sbA[G], nb, P.rsi,
                            G >= SORT_TABLE_MIN_ROWS ? (SBlock *)ws.buf(ws.sorttab, sizeof(SBlock) * (nb + 1))
                                                     : nullptr,
-                           C.PB.kc};
+                           C.PB.kc, cull ? (int32_t *)ws.buf(ws.bn, sizeof(int32_t) * (nb + 1)) : nullptr};
     }
     QueueGeo &Q = C.Q;
     Q.wi_off = ds + 6 * G1;

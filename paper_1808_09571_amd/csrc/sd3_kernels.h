@@ -76,6 +76,8 @@ struct SortSeg {
     const int32_t *kc;             // [2G] kept items per row of a culling call, else nullptr:
                                    // after the first pass they lead each row's range and
                                    // later passes read and place only them
+    int32_t *bn;                   // [nb] kept items per sort block of a culling call (the key
+                                   // kernel writes them first in the block), else nullptr
 };
 // Calls of at least this many rows build the sort-block table first.
 constexpr int64_t SORT_TABLE_MIN_ROWS = 64;

@@ -682,9 +682,11 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         }
     }
     if ((int64_t)blockIdx.x >= S.nb) return;  // the one block of a call with no items
-    const SBlock k = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
+    const int64_t bl = xcd_block(blockIdx.x, gridDim.x);
+    const SBlock k = sort_block(S, bl);
     const MortonSide &M = k.side ? B : A;
     __shared__ uint32_t nkeep;  // the block's kept triangles (culling)
+    __shared__ uint32_t wk[PER][16];  // kept items per round and wave (culling)
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     if (threadIdx.x == 0) nkeep = 0;
     const int64_t vb = M.v_off[k.g];
@@ -750,37 +752,64 @@ __global__ __launch_bounds__(1024) void k_morton(MortonSide A, MortonSide B, Sor
         for (int c = 0; c < 6; c++) b[c] = __shfl(mb, c);
         sc = row_cells(b, lo);
     }
+    // a culling call writes the block's kept items first, in item order, at
+    // the kept items before them (a ballot per round and wave, one barrier);
+    // the first sort pass reads only those, the culled ones being counted in
+    // digit 255
+    int32_t at[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) at[r] = r * 1024 + (int)threadIdx.x;
+    if (VC && M.kc) {
+        const int w = (int)(threadIdx.x >> 6);
+        unsigned long long bal[PER];
+#pragma unroll
+        for (int r = 0; r < PER; r++) {
+            bal[r] = __ballot(ok[r] && !cut[r]);
+            if (lane == 0) wk[r][w] = (uint32_t)__popcll(bal[r]);
+        }
+        __syncthreads();
+        uint32_t run = 0;
+#pragma unroll
+        for (int r = 0; r < PER; r++) {
+            uint32_t before = 0, tot = 0;
+            for (int q = 0; q < 16; q++) {
+                const uint32_t c = wk[r][q];
+                before += q < w ? c : 0u;
+                tot += c;
+            }
+            at[r] = (int32_t)(run + before + (uint32_t)__popcll(bal[r] & lanes_below()));
+            run += tot;
+        }
+        if (threadIdx.x == 0) {
+            nkeep = run;
+            S.bn[bl] = (int32_t)run;
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; r++) {
-        if (!ok[r]) continue;
+        if (!ok[r] || cut[r]) continue;  // (culled items are counted below, not written)
         const int j = r * 1024 + (int)threadIdx.x;
         if (!VC) code[r] = morton_code(cen[VC ? 0 : r], lo, sc);
         uint32_t key = code[r] >> (30 - mbits);
         if (VC && M.kc) {
             // kept keys hold no 255 digit (each byte capped at 254), so that
-            // every pass places the culled items, all 255 digits, at the end
-            // of the row
-            const uint32_t kmax = (1u << mbits) - 1u;
+            // every pass places the culled items (all digits 255, counted,
+            // never written) at the end of the row
             uint32_t kk = 0;
             for (int sh = 0; sh < mbits; sh += 8) kk |= min((key >> sh) & 255u, 254u) << sh;
-            key = cut[r] ? kmax : kk;
+            key = kk;
         }
-        keys[k.i0 + j] = key;
-        vals[k.i0 + j] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
-        // culled items all fall in the last digit: counted per wave below
-        // (one LDS atomic instead of one per item on a single address)
-        if (!cut[r]) atomicAdd(&h[key & 255u], 1u);
+        keys[k.i0 + at[r]] = key;
+        vals[k.i0 + at[r]] = (int32_t)(LOC ? k.loc + j : k.t0 + j);
+        atomicAdd(&h[key & 255u], 1u);
     }
     if (VC && M.kc) {
-        uint32_t kept = 0, ncut = 0;
+        // culled items all fall in digit 255: one LDS atomic per wave
+        uint32_t ncut = 0;
 #pragma unroll
-        for (int r = 0; r < PER; r++) {
-            kept += (uint32_t)__popcll(__ballot(ok[r] && !cut[r]));
-            ncut += (uint32_t)__popcll(__ballot(ok[r] && cut[r]));
-        }
-        if (lane == 0 && kept) atomicAdd(&nkeep, kept);
-        if (lane == 0 && ncut) atomicAdd(&h[((1u << mbits) - 1u) & 255u], ncut);
+        for (int r = 0; r < PER; r++) ncut += (uint32_t)__popcll(__ballot(ok[r] && cut[r]));
+        if (lane == 0 && ncut) atomicAdd(&h[255], ncut);
     }
     __syncthreads();
     if (threadIdx.x < 256) hist[k.hbase + (int64_t)threadIdx.x * k.hstride] = h[threadIdx.x];
@@ -918,12 +947,14 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *kin, const int3
     __shared__ int32_t sval[MODE == 0 ? RS_ITEMS : 1];
     __shared__ uint8_t sdig[MODE == 1 ? RS_ITEMS : 1];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-    const SBlock sbk = sort_block(S, xcd_block(blockIdx.x, gridDim.x));
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const SBlock sbk = sort_block(S, blk);
     const int64_t b0 = sbk.i0;
-    // items of this block: [b0, n); after the first pass of a culling call
-    // the kept ones only (the culled ones keep their reserved places, digit
-    // 255 at the row's end, unwritten)
-    const int nvalid = later ? kept_in_block(S, sbk) : sbk.n;
+    // items of this block: [b0, n); in a culling call the kept ones only
+    // (first in the block for the first pass, first in the row after it; the
+    // culled ones keep their reserved places, digit 255 at the row's end,
+    // unwritten)
+    const int nvalid = later ? kept_in_block(S, sbk) : (S.bn ? S.bn[blk] : sbk.n);
     const int64_t n = b0 + nvalid;
     if (ncraw > 0) {
         // exclusive scan of the raw chunk totals (one per thread) into loff
